@@ -1,0 +1,365 @@
+/*
+ * FP64 CPU oracle for the colour-temperature decolorization and its global
+ * tone-mapping application.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing on the product path may call, link or load
+ * this file: only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark use it, to decide whether the GPU results are right and to time
+ * a plain CPU implementation beside them. It shares no code, header, table or
+ * constant with the HIP kernels.
+ *
+ * What it computes (Ambalathankandy et al., "A color temperature-based
+ * high-speed decolorization", arXiv 2108.13656):
+ *   - Sec. II-B, Eqs. (1)-(6): the per-pixel luminance L from (R, G, B) with the
+ *     two weights beta_R (warm bias of red over green, Eq. 3) and beta_k (warm
+ *     over cool, Eq. 6); defaults beta_R = 0.55, beta_k = 0.8 (end of Sec. II-B).
+ *   - Sec. III-B.1: a global tone curve applied to L. The paper only says the
+ *     curve is a centred sigmoid for contrast enhancement; the statistics and the
+ *     curve below are this project's reading of that sentence:
+ *         x = ln(Lhat + eps) for every pixel of the image,
+ *         mu = mean(x), sigma = population standard deviation of x,
+ *         T = 1 / (1 + exp(-c (x - mu) / max(sigma, sigma_floor))).
+ *
+ * Readings where the paper is silent:
+ *   - u8 inputs are code values 0..255, no gamma linearisation; f16 and f32
+ *     inputs are the stored values.  "Normalised units" Lhat = L / 255 for u8
+ *     input and Lhat = L for float input (L is degree-1 homogeneous, so the
+ *     scale only fixes the unit of the output).
+ *   - A black pixel (R + G + B == 0) has L = 0, the limit of Eqs. (4)-(6).
+ *   - NaN and negative channel values are read as 0.
+ *   - beta_R and beta_k may be anywhere in the closed interval [0, 1].
+ *   - u8 encode rounds half up and clamps: min(255, floor(255 Lhat + 0.5)).
+ *   - f16 encode is IEEE binary16 round-to-nearest-even.
+ *
+ * Arithmetic is plain IEEE double with the C library's sqrt, log and exp; build
+ * with -O2 -fno-fast-math -ffp-contract=off so that nothing is fused or
+ * reordered.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { REF_U8 = 0, REF_F16 = 1, REF_F32 = 2 };
+
+/* ---------------------------------------------------------------- binary16 */
+
+/* IEEE 754 binary16 to double, from the format's definition: 1 sign bit,
+ * 5 exponent bits (bias 15), 10 fraction bits; exponent 0 encodes zero and
+ * subnormals (fraction * 2^-24), exponent 31 encodes infinities and NaNs. */
+double ref_half_to_double(uint16_t h)
+{
+    int sign = (h >> 15) & 1;
+    int e = (h >> 10) & 31;
+    int f = h & 1023;
+    double v;
+    if (e == 0)
+        v = ldexp((double)f, -24);
+    else if (e == 31)
+        v = f ? NAN : INFINITY;
+    else
+        v = ldexp(1024.0 + f, e - 25);
+    return sign ? -v : v;
+}
+
+/* double to binary16 with round-to-nearest, ties to even. Magnitudes at or
+ * above 65520 (the midpoint between the largest finite half and 2^16) become
+ * infinity. */
+uint16_t ref_double_to_half(double x)
+{
+    uint16_t sign = 0;
+    if (isnan(x))
+        return 0x7e00;
+    if (signbit(x)) {
+        sign = 0x8000;
+        x = -x;
+    }
+    if (x >= 65520.0)
+        return sign | 0x7c00;
+    if (x == 0.0)
+        return sign;
+    int e2;
+    frexp(x, &e2);            /* x = m * 2^e2, m in [0.5, 1) */
+    int exp_unb = e2 - 1;     /* x = m' * 2^exp_unb, m' in [1, 2) */
+    /* Spacing of representable halves near x: 2^(exp_unb - 10) for normals,
+     * 2^-24 for subnormals. Round x / spacing to the nearest integer, ties to
+     * even (x / spacing is exact: spacing is a power of two). */
+    int q_exp = exp_unb < -14 ? -24 : exp_unb - 10;
+    double scaled = ldexp(x, -q_exp);
+    double fl = floor(scaled);
+    double rem = scaled - fl;
+    double k = fl;
+    if (rem > 0.5 || (rem == 0.5 && fmod(fl, 2.0) != 0.0))
+        k = fl + 1.0;
+    double r = ldexp(k, q_exp); /* the rounded value, exactly */
+    if (r >= 65520.0)
+        return sign | 0x7c00;
+    /* Re-encode r, which is exactly representable. */
+    if (r < ldexp(1.0, -14)) {
+        return sign | (uint16_t)(r * ldexp(1.0, 24));
+    }
+    int er;
+    double mr = frexp(r, &er); /* r = mr * 2^er, mr in [0.5,1) */
+    int biased = er - 1 + 15;
+    uint16_t frac = (uint16_t)((mr * 2.0 - 1.0) * 1024.0);
+    return sign | (uint16_t)(biased << 10) | frac;
+}
+
+/* ------------------------------------------------------------- Eqs. (1)-(6) */
+
+static double sanitise(double v)
+{
+    /* NaN and negative values read as 0 (NaN fails the comparison). */
+    return (v > 0.0) ? v : 0.0;
+}
+
+/* Luminance L of one pixel, Sec. II-B, Eqs. (1)-(6), evaluated in the paper's
+ * order and notation. Output in the units of the input. */
+double ref_decolor_px(double R, double G, double B, double beta_r, double beta_k)
+{
+    R = sanitise(R);
+    G = sanitise(G);
+    B = sanitise(B);
+    double S = R + G + B;
+    if (S == 0.0)
+        return 0.0; /* black: limit of Eqs. (4)-(6) */
+
+    double L_white = sqrt((R * R + G * G + B * B) / 3.0);            /* Eq. (1) */
+    double L_b = B;                                                   /* Eq. (2) */
+    double L_gr = sqrt(beta_r * R * R + (1.0 - beta_r) * G * G);      /* Eq. (3) */
+    double wr = R / S;
+    double wb = B / S;
+    double L_warm = wr * L_gr + (1.0 - wr) * L_white;                 /* Eq. (4) */
+    double L_cool = (1.0 - wb) * L_b + wb * L_white;                  /* Eq. (5) */
+    return sqrt(beta_k * L_warm * L_warm + (1.0 - beta_k) * L_cool * L_cool); /* Eq. (6) */
+}
+
+/* All four intermediate luminances of one pixel (for tests that inspect the
+ * individual equations): out = {L_white, L_gr, L_warm, L_cool, L}. */
+void ref_decolor_px_terms(double R, double G, double B, double beta_r, double beta_k,
+                          double *out)
+{
+    R = sanitise(R);
+    G = sanitise(G);
+    B = sanitise(B);
+    double S = R + G + B;
+    double L_white = sqrt((R * R + G * G + B * B) / 3.0);
+    double L_gr = sqrt(beta_r * R * R + (1.0 - beta_r) * G * G);
+    double L_warm = 0.0, L_cool = 0.0;
+    if (S != 0.0) {
+        double wr = R / S, wb = B / S;
+        L_warm = wr * L_gr + (1.0 - wr) * L_white;
+        L_cool = (1.0 - wb) * B + wb * L_white;
+    }
+    out[0] = L_white;
+    out[1] = L_gr;
+    out[2] = L_warm;
+    out[3] = L_cool;
+    out[4] = ref_decolor_px(R, G, B, beta_r, beta_k);
+}
+
+/* --------------------------------------------------------------- encoders */
+
+/* Normalised Lhat -> 8-bit code: round half up, clamp to [0, 255]. */
+uint8_t ref_encode_u8(double lhat)
+{
+    double v = floor(255.0 * sanitise(lhat) + 0.5);
+    return (uint8_t)(v > 255.0 ? 255.0 : v);
+}
+
+void ref_encode_u8_array(const double *lhat, int64_t n, uint8_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = ref_encode_u8(lhat[i]);
+}
+
+void ref_encode_f16_array(const double *v, int64_t n, uint16_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = ref_double_to_half(v[i]);
+}
+
+void ref_decode_f16_array(const uint16_t *h, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = ref_half_to_double(h[i]);
+}
+
+/* ------------------------------------------------------------ image driver */
+
+static double load_channel(const unsigned char *p, int dtype, int c)
+{
+    switch (dtype) {
+    case REF_U8:
+        return (double)p[c];
+    case REF_F16: {
+        uint16_t h;
+        memcpy(&h, p + 2 * c, 2);
+        return ref_half_to_double(h);
+    }
+    default: {
+        float f;
+        memcpy(&f, p + 4 * c, 4);
+        return (double)f;
+    }
+    }
+}
+
+static int dtype_size(int dtype)
+{
+    return dtype == REF_U8 ? 1 : dtype == REF_F16 ? 2 : 4;
+}
+
+typedef struct {
+    const unsigned char *src;
+    int dtype, W;
+    int64_t pitch;
+    double beta_r, beta_k;
+    double *out;
+    int row0, row1;
+} rows_job;
+
+static void decolor_rows(const rows_job *j)
+{
+    int es = dtype_size(j->dtype);
+    double unit = j->dtype == REF_U8 ? 255.0 : 1.0;
+    for (int y = j->row0; y < j->row1; ++y) {
+        const unsigned char *row = j->src + (int64_t)y * j->pitch;
+        for (int x = 0; x < j->W; ++x) {
+            const unsigned char *p = row + (int64_t)3 * es * x;
+            double R = load_channel(p, j->dtype, 0);
+            double G = load_channel(p, j->dtype, 1);
+            double B = load_channel(p, j->dtype, 2);
+            j->out[(int64_t)y * j->W + x] = ref_decolor_px(R, G, B, j->beta_r, j->beta_k) / unit;
+        }
+    }
+}
+
+static void *decolor_rows_thread(void *arg)
+{
+    decolor_rows((const rows_job *)arg);
+    return NULL;
+}
+
+/* Normalised luminance Lhat of every pixel of an interleaved HWC RGB image.
+ * src: host pointer, row y starts at src + y * pitch_bytes; out: W*H doubles,
+ * row-major and packed. nthreads <= 1 runs on the calling thread; otherwise the
+ * rows are split into nthreads contiguous bands. Returns 0, or -1 on a bad
+ * argument. */
+int ref_decolorize_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes,
+                         double beta_r, double beta_k, double *out, int nthreads)
+{
+    if (!src || !out || W < 0 || H < 0 || dtype < 0 || dtype > 2)
+        return -1;
+    if (pitch_bytes < (int64_t)3 * dtype_size(dtype) * W)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > H)
+        nthreads = H > 0 ? H : 1;
+    rows_job *jobs = (rows_job *)calloc((size_t)nthreads, sizeof(rows_job));
+    pthread_t *tids = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !tids) {
+        free(jobs);
+        free(tids);
+        return -1;
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        rows_job j = {(const unsigned char *)src, dtype, W, pitch_bytes, beta_r, beta_k, out,
+                      (int)((int64_t)H * t / nthreads), (int)((int64_t)H * (t + 1) / nthreads)};
+        jobs[t] = j;
+    }
+    for (int t = 1; t < nthreads; ++t)
+        pthread_create(&tids[t], NULL, decolor_rows_thread, &jobs[t]);
+    decolor_rows(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t)
+        pthread_join(tids[t], NULL);
+    free(jobs);
+    free(tids);
+    return 0;
+}
+
+/* L in code units for every 24-bit colour: out[(R << 16) | (G << 8) | B]. */
+void ref_all_colours(double beta_r, double beta_k, double *out)
+{
+    for (int r = 0; r < 256; ++r)
+        for (int g = 0; g < 256; ++g)
+            for (int b = 0; b < 256; ++b)
+                out[(r << 16) | (g << 8) | b] = ref_decolor_px(r, g, b, beta_r, beta_k);
+}
+
+/* ---------------------------------------------------- global tone mapping */
+
+/* Statistics of x = ln(Lhat + eps) over all n pixels of one image, two passes
+ * in double: stats = {mu, sigma, min Lhat, max Lhat}. n == 0 gives zeros. */
+void ref_tonemap_stats(const double *lhat, int64_t n, double eps, double *stats)
+{
+    if (n <= 0) {
+        stats[0] = stats[1] = stats[2] = stats[3] = 0.0;
+        return;
+    }
+    double sum = 0.0, mn = lhat[0], mx = lhat[0];
+    for (int64_t i = 0; i < n; ++i) {
+        sum += log(lhat[i] + eps);
+        if (lhat[i] < mn)
+            mn = lhat[i];
+        if (lhat[i] > mx)
+            mx = lhat[i];
+    }
+    double mu = sum / (double)n;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = log(lhat[i] + eps) - mu;
+        ss += d * d;
+    }
+    stats[0] = mu;
+    stats[1] = sqrt(ss / (double)n);
+    stats[2] = mn;
+    stats[3] = mx;
+}
+
+/* The centred sigmoid on one pixel, given the image's mu and sigma. */
+double ref_tonemap_curve(double lhat, double eps, double contrast, double mu, double sigma,
+                         double sigma_floor)
+{
+    double s = sigma > sigma_floor ? sigma : sigma_floor;
+    double x = log(lhat + eps);
+    return 1.0 / (1.0 + exp(-contrast * (x - mu) / s));
+}
+
+void ref_tonemap_curve_array(const double *lhat, int64_t n, double eps, double contrast,
+                             double mu, double sigma, double sigma_floor, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = ref_tonemap_curve(lhat[i], eps, contrast, mu, sigma, sigma_floor);
+}
+
+/* Whole global tone map of one image: decolorize (threaded over rows), the
+ * statistics (single thread), then the curve. lhat_out (W*H, may be NULL)
+ * receives the normalised luminance, t_out (W*H) the curve value, stats the
+ * four figures of ref_tonemap_stats. Returns 0, or -1 on a bad argument or
+ * allocation failure. */
+int ref_tonemap_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes,
+                      double beta_r, double beta_k, double eps, double contrast,
+                      double sigma_floor, double *lhat_out, double *t_out, double *stats,
+                      int nthreads)
+{
+    int64_t n = (int64_t)W * H;
+    double *lhat = lhat_out;
+    if (!t_out || !stats)
+        return -1;
+    if (!lhat) {
+        lhat = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        if (!lhat)
+            return -1;
+    }
+    int rc = ref_decolorize_image(src, dtype, W, H, pitch_bytes, beta_r, beta_k, lhat, nthreads);
+    if (rc == 0) {
+        ref_tonemap_stats(lhat, n, eps, stats);
+        ref_tonemap_curve_array(lhat, n, eps, contrast, stats[0], stats[1], sigma_floor, t_out);
+    }
+    if (!lhat_out)
+        free(lhat);
+    return rc;
+}

@@ -1,0 +1,103 @@
+"""Pure-Python FP64 twin of the C oracle (scalar, slow, for tiny inputs).
+
+TEST INFRASTRUCTURE ONLY: used by the test-suite to cross-check the C oracle
+(two independent transcriptions of the same definitions). Nothing on the
+product path imports it.
+
+Follows Sec. II-B, Eqs. (1)-(6) of arXiv 2108.13656 for the luminance, and this
+project's reading of the centred-sigmoid global tone curve of Sec. III-B.1 (log
+domain, centred on the mean of ln(Lhat + eps), slope normalised by the
+population standard deviation).
+"""
+import math
+
+BETA_R = 0.55  # Sec. II-B, parameter choice after Eq. (6)
+BETA_K = 0.80
+
+
+def _clean(v):
+    """NaN and negative channel values read as 0."""
+    v = float(v)
+    return v if v > 0.0 else 0.0
+
+
+def luminance_terms(r, g, b, beta_r=BETA_R, beta_k=BETA_K):
+    """(L_white, L_b, L_gr, L_warm, L_cool, L) of one pixel, Eqs. (1)-(6).
+
+    A black pixel returns all zeros (limit of Eqs. (4)-(6) as R+G+B -> 0).
+    """
+    r, g, b = _clean(r), _clean(g), _clean(b)
+    total = r + g + b
+    # Eq. (1): RMS of the three channels ("Euclidean distance" of RGB, /3).
+    l_white = math.sqrt((r * r + g * g + b * b) / 3.0)
+    # Eq. (2): the blue channel as it is.
+    l_b = b
+    # Eq. (3): red and green weighted by beta_R and 1 - beta_R.
+    l_gr = math.sqrt(beta_r * r * r + (1.0 - beta_r) * g * g)
+    if total == 0.0:
+        return (l_white, l_b, l_gr, 0.0, 0.0, 0.0)
+    red_share = r / total
+    blue_share = b / total
+    # Eq. (4): warm blend driven by the red share.
+    l_warm = red_share * l_gr + (1.0 - red_share) * l_white
+    # Eq. (5): cool blend driven by the inverse blue share.
+    l_cool = (1.0 - blue_share) * l_b + blue_share * l_white
+    # Eq. (6): weighted RMS of the warm and cool luminances.
+    lum = math.sqrt(beta_k * l_warm ** 2 + (1.0 - beta_k) * l_cool ** 2)
+    return (l_white, l_b, l_gr, l_warm, l_cool, lum)
+
+
+def luminance(r, g, b, beta_r=BETA_R, beta_k=BETA_K):
+    """L of one pixel in the units of its input, Eqs. (1)-(6)."""
+    return luminance_terms(r, g, b, beta_r, beta_k)[5]
+
+
+def half_bits_to_float(bits):
+    """IEEE 754 binary16 bit pattern -> Python float (definition of the format)."""
+    sign = -1.0 if (bits >> 15) & 1 else 1.0
+    exponent = (bits >> 10) & 0x1F
+    fraction = bits & 0x3FF
+    if exponent == 0:
+        return sign * fraction * 2.0 ** -24
+    if exponent == 31:
+        return sign * math.inf if fraction == 0 else math.nan
+    return sign * (1.0 + fraction / 1024.0) * 2.0 ** (exponent - 15)
+
+
+def decolorize_image(pixels, dtype, beta_r=BETA_R, beta_k=BETA_K):
+    """Normalised luminance of a nested-list image [[(r, g, b), ...], ...].
+
+    dtype is "u8" (code values, output divided by 255), "f16" (values given as
+    binary16 bit patterns) or "f32" (values as floats).
+    """
+    out = []
+    for row in pixels:
+        out_row = []
+        for px in row:
+            if dtype == "f16":
+                px = [half_bits_to_float(int(v)) for v in px]
+            lum = luminance(px[0], px[1], px[2], beta_r, beta_k)
+            out_row.append(lum / 255.0 if dtype == "u8" else lum)
+        out.append(out_row)
+    return out
+
+
+def encode_u8(lhat):
+    """Round half up and clamp: min(255, floor(255 * Lhat + 0.5))."""
+    return min(255, int(math.floor(255.0 * _clean(lhat) + 0.5)))
+
+
+def tonemap_stats(lhat_values, eps):
+    """(mu, sigma, min, max) of x = ln(Lhat + eps) over all pixels (fsum)."""
+    xs = [math.log(v + eps) for v in lhat_values]
+    n = len(xs)
+    mu = math.fsum(xs) / n
+    sigma = math.sqrt(math.fsum((x - mu) ** 2 for x in xs) / n)
+    return mu, sigma, min(lhat_values), max(lhat_values)
+
+
+def tonemap_curve(lhat, eps, contrast, mu, sigma, sigma_floor):
+    """Centred sigmoid of ln(Lhat + eps) around mu with slope contrast / sigma."""
+    scale = max(sigma, sigma_floor)
+    x = math.log(lhat + eps)
+    return 1.0 / (1.0 + math.exp(-contrast * (x - mu) / scale))
