@@ -1,0 +1,208 @@
+"""Throughput benchmark of the decolorization + global tone-map hot path on one
+MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+``dc_tonemap_global`` on 16 binary16 linear-RGB images of 4096 x 4096 (the
+statistics pass fused with the decolorization of Eqs. (1)-(6), the fixed-order
+combine, and the curve pass that writes FP32 T). Inputs are resident in HBM
+before timing starts. The same run also times the plain decolorization of the
+64-frame video batch (32 x 1920x1080 + 32 x 3840x2160, 8-bit in, 8-bit + FP32
+out) in one batched launch, reported in the same JSON line.
+
+Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused: this
+build measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+METRIC = "Gpixels/s + % of HBM peak (decolorize+tonemap); p50/p99 latency served"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--images", type=int, default=16, help="HDR images per step")
+    ap.add_argument("--size", type=int, default=4096, help="HDR image side")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-images", type=int, default=2)
+    ap.add_argument("--skip-video", action="store_true")
+    ap.add_argument("--only", choices=["tonemap", "video"], default=None,
+                    help="time one workload only (for profiler runs)")
+    return ap.parse_args()
+
+
+def gen_hdr(n, size):
+    import synth
+    return [synth.hdr_image(i, shape=(size, size)) for i in range(n)]
+
+
+def time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per step
+
+
+def kernel_times(fn, reps, P, dev):
+    """Per-kernel durations (ms) from the library's own HIP events."""
+    import torch
+    P.set_profiling(True, dev)
+    acc = None
+    for _ in range(reps):
+        fn()
+        t = P.last_timings(dev)
+        acc = t if acc is None else [a + b for a, b in zip(acc, t)]
+    P.set_profiling(False, dev)
+    torch.cuda.synchronize()
+    return [a / reps for a in acc]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported by this build" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2108_13656_amd as P
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)
+    result = {}
+
+    # ---------------------------------------------------- HDR tone map (headline)
+    n_img, size = args.images, args.size
+    hdr_px = n_img * size * size
+    if args.only in (None, "tonemap"):
+        log("generating %d HDR images %dx%d" % (n_img, size, size))
+        t0 = time.time()
+        imgs = gen_hdr(n_img, size)
+        log("generated in %.1f s" % (time.time() - t0))
+        xs = [torch.from_numpy(a).to(dev) for a in imgs]
+        outs = [torch.empty((size, size), dtype=torch.float32, device=dev) for _ in xs]
+        stats = torch.empty((n_img, P.STATS_BYTES), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+
+        def step():
+            P.tonemap_global(xs, outs=outs, stats=stats, stream=stream)
+
+        with torch.cuda.stream(stream):
+            ms = time_steps(step, args.steps, args.warmup, stream)
+            ktimes = kernel_times(step, max(5, args.steps // 2), P, dev)
+        log("tonemap step %.3f ms; kernels (pass1, combine, pass2) %s ms" %
+            (ms, ", ".join("%.3f" % t for t in ktimes)))
+        gpx = hdr_px / (ms * 1e-3) / 1e9
+        step_bytes = hdr_px * (6 + 4)  # read RGB f16 once, write T f32 once
+        # Dominant kernel: the curve pass (re-reads the input, writes T).
+        k_pass1, k_comb, k_pass2 = ktimes
+        dom = ("tonemap_pass2", k_pass2, hdr_px * 10) if k_pass2 >= k_pass1 else \
+              ("tonemap_pass1", k_pass1, hdr_px * 6)
+        ach = dom[2] / (dom[1] * 1e-3) / 1e9
+        result.update({
+            "metric": METRIC, "value": round(gpx, 3), "unit": "Gpixels/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "hdr_tonemap", "images": n_img, "height": size,
+                       "width": size, "src": "f16 linear RGB", "dst": "f32 T",
+                       "hot_path": "decolorize + stats + combine + curve"},
+            "hbm_frac_step": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_ms": {"tonemap_pass1": round(k_pass1, 4), "tonemap_combine": round(k_comb, 4),
+                          "tonemap_pass2": round(k_pass2, 4)},
+            "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": None},
+        })
+
+        # CPU baseline: the FP64 oracle, single thread, on a sample of images.
+        if not args.no_cpu_baseline:
+            import oracle
+            k = min(args.cpu_sample_images, n_img)
+            log("cpu baseline: oracle on %d image(s), 1 thread" % k)
+            t0 = time.time()
+            worst = 0.0
+            for i in range(k):
+                t_ref, _, _ = oracle.tonemap(imgs[i], nthreads=1)
+                worst = max(worst, float(np.max(np.abs(outs[i].cpu().numpy() - t_ref))))
+            dt = time.time() - t0
+            cpu_gpx = k * size * size / dt / 1e9
+            result["cpu_baseline"] = {"value": round(cpu_gpx, 6), "unit": "Gpixels/s", "cores": 1,
+                                      "kind": "oracle",
+                                      "sample": "%d of the %d images (%dx%d f16), full tone map in "
+                                                "FP64, one thread" % (k, n_img, size, size)}
+            result["parity_sample"] = {"images": k, "max_abs_err_T": worst}
+            log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
+        del xs, outs
+        torch.cuda.empty_cache()
+
+    # ---------------------------------------------------- video batch decolorize
+    if args.only in (None, "video") and not args.skip_video:
+        import synth
+        log("generating 64 video frames")
+        t0 = time.time()
+        frames = [torch.from_numpy(synth.video_frame(i)).to(dev) for i in range(64)]
+        log("generated in %.1f s" % (time.time() - t0))
+        vpx = sum(f.shape[0] * f.shape[1] for f in frames)
+        o8 = [torch.empty(f.shape[:2], dtype=torch.uint8, device=dev) for f in frames]
+        o32 = [torch.empty(f.shape[:2], dtype=torch.float32, device=dev) for f in frames]
+        torch.cuda.synchronize()
+
+        def vstep():
+            P.decolorize_batch(frames, outs=o8, outs2=o32, stream=stream)
+
+        def vstep_single():
+            for f, a, b in zip(frames, o8, o32):
+                P.decolorize(f, out=a, out2=b, stream=stream)
+
+        with torch.cuda.stream(stream):
+            vms = time_steps(vstep, args.steps, args.warmup, stream)
+            vk = kernel_times(vstep, max(5, args.steps // 2), P, dev)[0]
+            vms_single = time_steps(vstep_single, max(3, args.steps // 4), 1, stream)
+        vbytes = vpx * 8
+        vach = vbytes / (vk * 1e-3) / 1e9
+        video = {"workload": "video_decolorize", "frames": "32x1920x1080 + 32x3840x2160",
+                 "src": "u8 sRGB", "dst": "u8 + f32", "ms_per_step": round(vms, 4),
+                 "value": round(vpx / (vms * 1e-3) / 1e9, 3), "unit": "Gpixels/s",
+                 "per_image_launches_gpx": round(vpx / (vms_single * 1e-3) / 1e9, 3),
+                 "roofline": {"bound": "hbm", "kernel": "decolor_table", "achieved": round(vach, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(vach / HBM_PEAK_GBS, 4), "traffic": None}}
+        log("video step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %.3f "
+            "Gpx/s" % (vms, video["value"], vk, vach, video["per_image_launches_gpx"]))
+        if not result:
+            result.update({"metric": METRIC, "value": video["value"], "unit": "Gpixels/s",
+                           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                           "ms_per_step": video["ms_per_step"], "higher_is_better": True,
+                           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                           "data": "synthetic", "config": {"workload": "video_decolorize"},
+                           "roofline": video["roofline"]})
+        else:
+            result["video_decolorize"] = video
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * decolor.h - C ABI of the MI355X (gfx950) colour-temperature decolorization
+ * library.
+ *
+ * The method: Ambalathankandy et al., "A color temperature-based high-speed
+ * decolorization: an empirical approach for tone mapping applications"
+ * (arXiv 2108.13656).
+ *   - Decolorization, Sec. II-B, Eqs. (1)-(6): per pixel,
+ *       L_white = sqrt((R^2 + G^2 + B^2) / 3)                       (1)
+ *       L_b     = B                                                  (2)
+ *       L_gr    = sqrt(beta_R R^2 + (1 - beta_R) G^2)                (3)
+ *       L_warm  = R/S L_gr + (1 - R/S) L_white,  S = R + G + B        (4)
+ *       L_cool  = (1 - B/S) L_b + B/S L_white                         (5)
+ *       L       = sqrt(beta_k L_warm^2 + (1 - beta_k) L_cool^2)      (6)
+ *     with beta_R = 0.55, beta_k = 0.8 (the values chosen after Eq. (6)).
+ *   - Global tone mapping on L, Sec. III-B.1: the paper names a centred
+ *     sigmoid tone curve; this library reads it as
+ *       x = ln(Lhat + eps) over all pixels of one image,
+ *       mu = mean(x), sigma = population standard deviation of x,
+ *       T  = 1 / (1 + exp(-contrast (x - mu) / max(sigma, sigma_floor))).
+ *
+ * Units. 8-bit inputs are code values 0..255 (no gamma linearisation); binary16
+ * and binary32 inputs are linear values as stored. Lhat, the "normalised"
+ * luminance, is L / 255 for 8-bit input and L itself for float input. A black
+ * pixel (R + G + B == 0) has L = 0; NaN and negative channels read as 0. Float
+ * inputs are meant to lie in [0, 1e18]; values below 1e-30 may be flushed.
+ *
+ * Output encodings (dst, dst2): DC_F32 = the value as float; DC_F16 = binary16,
+ * round to nearest even; DC_U8 = min(255, floor(255 v + 0.5)) with v clamped
+ * to >= 0, where v is Lhat for decolorization and T for tone mapping.
+ *
+ * Memory. Every image pointer (src, dst, dst2) is a DEVICE pointer on the
+ * context's device, owned by the caller, and must stay valid until the work
+ * enqueued on `stream` has completed. Images are interleaved HWC RGB (3
+ * channels, R first) with a row pitch in bytes; outputs are one channel with
+ * their own row pitch. Host arrays passed to a call (dc_image lists, params)
+ * are read before the call returns and may be freed at once. The context owns
+ * its workspace (descriptor tables, statistics partials) and frees it in
+ * dc_destroy. 16-byte aligned bases and pitches take the vectorised path;
+ * anything else is still correct but slower.
+ *
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * All compute calls are asynchronous with respect to the host.
+ *
+ * Errors. Calls return DC_OK (0) or a negative DC_ERR_* code. Arguments are
+ * validated before anything is enqueued; a batch is all-or-nothing. Nothing
+ * aborts and no C++ exception crosses this interface. dc_last_error_message()
+ * gives a thread-local description of the last failure.
+ *
+ * Threads. A context is not thread-safe; use one per host thread.
+ */
+#ifndef DECOLOR_H
+#define DECOLOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DC_ABI_VERSION 1
+
+/* Status codes. */
+#define DC_OK 0
+#define DC_ERR_INVALID_ARG (-1) /* null pointer, bad size, pitch, dtype or parameter */
+#define DC_ERR_UNSUPPORTED (-2) /* a combination this build does not implement */
+#define DC_ERR_ALIAS (-3)       /* an output overlaps an input or another output */
+#define DC_ERR_NO_MEMORY (-4)   /* workspace allocation failed */
+#define DC_ERR_HIP (-5)         /* a HIP runtime call failed */
+#define DC_ERR_NO_DEVICE (-6)   /* no usable GPU, or the device index is out of range */
+
+/* Element types. DC_NONE marks an absent optional output. */
+#define DC_NONE (-1)
+#define DC_U8 0
+#define DC_F16 1
+#define DC_F32 2
+
+/* Eq. (3) and Eq. (6) weights. Each must be finite and in [0, 1] (the paper
+ * uses the open interval (0.5, 1); the blends stay convex on all of [0, 1]). */
+typedef struct dc_params {
+    float beta_r; /* default 0.55 */
+    float beta_k; /* default 0.80 */
+} dc_params;
+
+/* Global tone-curve parameters (Sec. III-B.1 reading above). eps > 0 keeps the
+ * logarithm finite on black pixels; contrast > 0 is the slope in units of the
+ * image's standard deviation; sigma_floor > 0 bounds the slope on flat images. */
+typedef struct dc_tm_params {
+    float eps;         /* default 1e-4 */
+    float contrast;    /* default 2.0  */
+    float sigma_floor; /* default 1e-3 */
+} dc_tm_params;
+
+/* One image. width, height >= 1. src_pitch >= 3 * width * sizeof(src element);
+ * dst_pitch >= width * sizeof(dst element); dst2 (optional, NULL with
+ * dst2_dtype = DC_NONE) likewise. Outputs must not overlap the input or each
+ * other. flags must be 0. */
+typedef struct dc_image {
+    const void *src; /* device, interleaved RGB, row y at src + y * src_pitch */
+    void *dst;       /* device, 1 channel */
+    void *dst2;      /* device, 1 channel, or NULL */
+    int64_t src_pitch;
+    int64_t dst_pitch;
+    int64_t dst2_pitch;
+    int32_t width;
+    int32_t height;
+    int32_t src_dtype;  /* DC_U8, DC_F16 or DC_F32 */
+    int32_t dst_dtype;  /* DC_U8, DC_F16 or DC_F32 */
+    int32_t dst2_dtype; /* DC_NONE, DC_U8, DC_F16 or DC_F32 */
+    int32_t flags;      /* reserved, 0 */
+} dc_image;
+
+/* Per-image statistics of the global tone map (FP32 accumulation). */
+typedef struct dc_stats {
+    float log_mean; /* mu: mean of ln(Lhat + eps) */
+    float log_std;  /* sigma: population standard deviation of ln(Lhat + eps) */
+    float l_min;    /* smallest Lhat */
+    float l_max;    /* largest Lhat */
+    int64_t count;  /* pixels, width * height */
+} dc_stats;
+
+typedef struct dc_ctx dc_ctx;
+
+/* Creates a context bound to HIP device `device` (it becomes current on the
+ * calling thread). *ctx receives the handle. Errors: DC_ERR_INVALID_ARG (ctx
+ * NULL), DC_ERR_NO_DEVICE, DC_ERR_NO_MEMORY, DC_ERR_HIP. */
+int dc_create(dc_ctx **ctx, int device);
+
+/* Synchronises the device and frees the context's workspace. NULL is a no-op. */
+int dc_destroy(dc_ctx *ctx);
+
+/* Host-only argument check, the same one every compute call runs first; it
+ * touches no GPU and needs no context. tm may be NULL when no tone map is
+ * meant. Returns DC_OK or the error the compute call would return. */
+int dc_validate(const dc_image *imgs, int32_t n, const dc_params *params,
+                const dc_tm_params *tm);
+
+/* Decolorization of one image, Sec. II-B, Eqs. (1)-(6): writes Lhat of every
+ * pixel to img->dst (and img->dst2 if set), each in its own encoding. params
+ * NULL means the defaults. One pass over the input, one over each output. */
+int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, void *stream);
+
+/* Decolorization of n images of any sizes and element types in one persistent
+ * launch over a device tile table (Sec. II-B, Eqs. (1)-(6) per pixel). imgs is
+ * a HOST array of n descriptors; n == 0 is a no-op. The result of every image
+ * is bit-identical to dc_decolorize on that image alone. */
+int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                        void *stream);
+
+/* Global tone map (Sec. III-B.1 reading above) of n images: per image, one
+ * statistics pass fused with the decolorization (Eqs. (1)-(6)), a fixed-order
+ * combine of per-chunk partials, and a curve pass that recomputes L and writes
+ * T to dst (and Lhat to dst2 if set). imgs is a HOST array; tm NULL means the
+ * defaults; stats, if not NULL, is a DEVICE array of n dc_stats that receives
+ * each image's statistics. Results of an image do not depend on which other
+ * images share the call. */
+int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                      const dc_tm_params *tm, dc_stats *stats, void *stream);
+
+/* Measurement hooks (instrumentation, not part of the method). With on != 0,
+ * every later compute call on ctx records timing events on its stream before
+ * and after each kernel it launches: decolorize and decolorize_batch record one
+ * interval (the decolorization kernel); tonemap_global records three (the
+ * statistics pass, the combine, the curve pass). dc_last_timings waits for the
+ * last such call to finish and writes up to cap interval lengths in
+ * milliseconds to ms (host array); it returns how many it wrote, or a negative
+ * status. Only the most recent call's intervals are kept. */
+int dc_set_profiling(dc_ctx *ctx, int on);
+int dc_last_timings(dc_ctx *ctx, float *ms, int32_t cap);
+
+/* Static description of a status code. */
+const char *dc_status_string(int status);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *dc_last_error_message(void);
+
+/* DC_ABI_VERSION of the built library. */
+int dc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DECOLOR_H */

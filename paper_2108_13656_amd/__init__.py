@@ -1,0 +1,320 @@
+"""Python binding of the MI355X decolorization library (``libdecolor.so``).
+
+Argument marshalling only: every step of the path runs in the HIP kernels
+behind the C ABI declared in ``include/decolor.h`` (Ambalathankandy et al.,
+arXiv 2108.13656, Sec. II-B Eqs. (1)-(6) and the global tone map of
+Sec. III-B.1). PyTorch supplies device memory and streams.
+
+There is no CPU fallback: if the library has not been built, or no GPU is
+present, every compute call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdecolor.so")
+
+DC_OK = 0
+DC_ERR_INVALID_ARG = -1
+DC_ERR_UNSUPPORTED = -2
+DC_ERR_ALIAS = -3
+DC_ERR_NO_MEMORY = -4
+DC_ERR_HIP = -5
+DC_ERR_NO_DEVICE = -6
+
+DC_NONE, DC_U8, DC_F16, DC_F32 = -1, 0, 1, 2
+_TORCH_TO_DC = {torch.uint8: DC_U8, torch.float16: DC_F16, torch.float32: DC_F32}
+
+BETA_R = 0.55  # Eq. (3) weight chosen after Eq. (6)
+BETA_K = 0.80  # Eq. (6) weight
+TM_EPS, TM_CONTRAST, TM_SIGMA_FLOOR = 1e-4, 2.0, 1e-3
+
+
+class DcImage(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("dst2", ctypes.c_void_p),
+                ("src_pitch", ctypes.c_int64), ("dst_pitch", ctypes.c_int64),
+                ("dst2_pitch", ctypes.c_int64), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("src_dtype", ctypes.c_int32),
+                ("dst_dtype", ctypes.c_int32), ("dst2_dtype", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class DcParams(ctypes.Structure):
+    _fields_ = [("beta_r", ctypes.c_float), ("beta_k", ctypes.c_float)]
+
+
+class DcTmParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_float), ("contrast", ctypes.c_float),
+                ("sigma_floor", ctypes.c_float)]
+
+
+class DcStats(ctypes.Structure):
+    _fields_ = [("log_mean", ctypes.c_float), ("log_std", ctypes.c_float),
+                ("l_min", ctypes.c_float), ("l_max", ctypes.c_float), ("count", ctypes.c_int64)]
+
+
+STATS_BYTES = ctypes.sizeof(DcStats)
+
+
+class DecolorError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d): %s" % (_status_string(status), status, message))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libdecolor.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdecolor.so is not built: run `python -m paper_2108_13656_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    img_p = ctypes.POINTER(DcImage)
+    par_p = ctypes.POINTER(DcParams)
+    tm_p = ctypes.POINTER(DcTmParams)
+    L.dc_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    L.dc_destroy.argtypes = [vp]
+    L.dc_validate.argtypes = [img_p, i32, par_p, tm_p]
+    L.dc_decolorize.argtypes = [vp, img_p, par_p, vp]
+    L.dc_decolorize_batch.argtypes = [vp, img_p, i32, par_p, vp]
+    L.dc_tonemap_global.argtypes = [vp, img_p, i32, par_p, tm_p, vp, vp]
+    L.dc_status_string.argtypes = [ctypes.c_int]
+    L.dc_status_string.restype = ctypes.c_char_p
+    L.dc_last_error_message.argtypes = []
+    L.dc_last_error_message.restype = ctypes.c_char_p
+    L.dc_version.argtypes = []
+    L.dc_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.dc_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    for name in ("dc_create", "dc_destroy", "dc_validate", "dc_decolorize", "dc_decolorize_batch",
+                 "dc_tonemap_global", "dc_version", "dc_set_profiling", "dc_last_timings"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _status_string(status):
+    try:
+        return lib().dc_status_string(status).decode()
+    except Exception:  # library missing while formatting an error
+        return "status"
+
+
+def _check(status):
+    if status != DC_OK:
+        raise DecolorError(status, lib().dc_last_error_message().decode())
+
+
+class Context:
+    """Owns one ``dc_ctx`` (workspace ring) on one device."""
+
+    def __init__(self, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib().dc_create(ctypes.byref(self._h), dev.index))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().dc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts = {}
+
+
+def context(device=None):
+    """The shared context of a device (created on first use)."""
+    idx = torch.cuda.current_device() if device is None else torch.device(device).index
+    if idx not in _contexts:
+        _contexts[idx] = Context(idx)
+    return _contexts[idx]
+
+
+# ------------------------------------------------------------- marshalling
+
+def _dc_dtype(t):
+    try:
+        return _TORCH_TO_DC[t]
+    except KeyError:
+        raise TypeError("unsupported dtype %s (uint8, float16, float32)" % t) from None
+
+
+def _check_rgb(x):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if x.dim() != 3 or x.shape[2] != 3:
+        raise ValueError("expected an HxWx3 interleaved RGB tensor, got %s" % (tuple(x.shape),))
+    if x.stride(2) != 1 or x.stride(1) != 3 or x.stride(0) < 3 * x.shape[1]:
+        raise ValueError("the W and channel axes must be packed (strides (pitch, 3, 1))")
+
+
+def _check_gray(y, h, w, device):
+    if y.dim() != 2 or tuple(y.shape) != (h, w) or y.device != device:
+        raise ValueError("output must be an HxW tensor on the input's device")
+    if y.stride(1) != 1 or y.stride(0) < w:
+        raise ValueError("output rows must be packed (strides (pitch, 1))")
+
+
+def _image(x, out, out2):
+    h, w = x.shape[0], x.shape[1]
+    d = DcImage()
+    d.src = x.data_ptr()
+    d.src_pitch = x.stride(0) * x.element_size()
+    d.width, d.height = w, h
+    d.src_dtype = _dc_dtype(x.dtype)
+    _check_gray(out, h, w, x.device)
+    d.dst = out.data_ptr()
+    d.dst_pitch = out.stride(0) * out.element_size()
+    d.dst_dtype = _dc_dtype(out.dtype)
+    if out2 is None:
+        d.dst2, d.dst2_pitch, d.dst2_dtype = None, 0, DC_NONE
+    else:
+        _check_gray(out2, h, w, x.device)
+        d.dst2 = out2.data_ptr()
+        d.dst2_pitch = out2.stride(0) * out2.element_size()
+        d.dst2_dtype = _dc_dtype(out2.dtype)
+    d.flags = 0
+    return d
+
+
+def _params(beta_r, beta_k):
+    return DcParams(beta_r, beta_k)
+
+
+def _stream_ptr(stream, device):
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _alloc(x, dtype, h, w):
+    return torch.empty((h, w), dtype=dtype, device=x.device)
+
+
+# ------------------------------------------------------------- public API
+
+def decolorize(x, out_dtype=torch.float32, out2_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
+               out=None, out2=None, stream=None):
+    """Luminance of Eqs. (1)-(6) for one HxWx3 image.
+
+    Returns the HxW output (Lhat as float, or its 8-bit / binary16 encoding),
+    or (out, out2) when a second output is requested.
+    """
+    _check_rgb(x)
+    h, w = x.shape[0], x.shape[1]
+    out = _alloc(x, out_dtype, h, w) if out is None else out
+    if out2 is None and out2_dtype is not None:
+        out2 = _alloc(x, out2_dtype, h, w)
+    d = _image(x, out, out2)
+    p = _params(beta_r, beta_k)
+    ctx = context(x.device)
+    _check(lib().dc_decolorize(ctx.handle, ctypes.byref(d), ctypes.byref(p),
+                               _stream_ptr(stream, x.device)))
+    return out if out2 is None else (out, out2)
+
+
+def _image_array(xs, outs, outs2):
+    arr = (DcImage * len(xs))()
+    for i, x in enumerate(xs):
+        _check_rgb(x)
+        arr[i] = _image(x, outs[i], None if outs2 is None else outs2[i])
+    return arr
+
+
+def decolorize_batch(xs, out_dtype=torch.float32, out2_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
+                     outs=None, outs2=None, stream=None):
+    """Decolorization of a list of images (any sizes, mixed input types) in one
+    persistent launch. Returns a list of outputs (or of (out, out2) pairs)."""
+    xs = list(xs)
+    if not xs:
+        return []
+    dev = xs[0].device
+    if outs is None:
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+    if outs2 is None and out2_dtype is not None:
+        outs2 = [_alloc(x, out2_dtype, x.shape[0], x.shape[1]) for x in xs]
+    arr = _image_array(xs, outs, outs2)
+    p = _params(beta_r, beta_k)
+    _check(lib().dc_decolorize_batch(context(dev).handle, arr, len(xs), ctypes.byref(p),
+                                     _stream_ptr(stream, dev)))
+    return outs if outs2 is None else list(zip(outs, outs2))
+
+
+def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
+                   eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, outs=None,
+                   lhats=None, stats=None, want_stats=True, stream=None):
+    """Global tone map (Sec. III-B.1, centred sigmoid on ln(Lhat + eps)) of a
+    list of images. Returns (T outputs, Lhat outputs or None, stats) where
+    stats is a uint8 device tensor of n x 24 bytes (see ``stats_to_host``)."""
+    xs = list(xs)
+    if not xs:
+        return [], None, None
+    dev = xs[0].device
+    if outs is None:
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+    if lhats is None and lhat_dtype is not None:
+        lhats = [_alloc(x, lhat_dtype, x.shape[0], x.shape[1]) for x in xs]
+    if stats is None and want_stats:
+        stats = torch.empty((len(xs), STATS_BYTES), dtype=torch.uint8, device=dev)
+    arr = _image_array(xs, outs, lhats)
+    p = _params(beta_r, beta_k)
+    tm = DcTmParams(eps, contrast, sigma_floor)
+    _check(lib().dc_tonemap_global(context(dev).handle, arr, len(xs), ctypes.byref(p),
+                                   ctypes.byref(tm),
+                                   ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                                   _stream_ptr(stream, dev)))
+    return outs, lhats, stats
+
+
+def stats_to_host(stats):
+    """List of dicts (log_mean, log_std, l_min, l_max, count) from the device
+    statistics tensor returned by ``tonemap_global``."""
+    raw = stats.cpu().contiguous()
+    f = raw[:, :16].contiguous().view(torch.float32)
+    c = raw[:, 16:24].contiguous().view(torch.int64)
+    return [{"mu": float(f[i, 0]), "sigma": float(f[i, 1]), "l_min": float(f[i, 2]),
+             "l_max": float(f[i, 3]), "count": int(c[i, 0])} for i in range(raw.shape[0])]
+
+
+def validate(images, beta_r=BETA_R, beta_k=BETA_K, tm=None):
+    """Host-only check of DcImage descriptors (no GPU needed). Returns the status."""
+    arr = (DcImage * len(images))(*images) if images else None
+    p = _params(beta_r, beta_k)
+    tmp = DcTmParams(*tm) if tm is not None else None
+    return lib().dc_validate(arr, len(images), ctypes.byref(p),
+                             ctypes.byref(tmp) if tmp is not None else None)
+
+
+def set_profiling(on, device=None):
+    """Records per-kernel timing events on later calls of this device's context."""
+    _check(lib().dc_set_profiling(context(device).handle, 1 if on else 0))
+
+
+def last_timings(device=None, cap=8):
+    """Per-kernel durations (ms) of the most recent profiled call."""
+    buf = (ctypes.c_float * cap)()
+    n = lib().dc_last_timings(context(device).handle, buf, cap)
+    if n < 0:
+        _check(n)
+    return [float(buf[i]) for i in range(n)]
+
+
+def last_error():
+    return lib().dc_last_error_message().decode()

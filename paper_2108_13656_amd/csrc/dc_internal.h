@@ -1,0 +1,104 @@
+// Internal types shared by the HIP kernels (kernels.hip) and the host runtime
+// (runtime.cpp). Not part of the public ABI (include/decolor.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dc {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kGroupBytes = 48;      // input bytes per vector group: 3 x 16 B
+constexpr int kStatsPxPerThread = 16; // pixels per thread in a statistics chunk
+constexpr int64_t kStatsChunkPx = (int64_t)kBlock * kStatsPxPerThread; // 4096
+
+// Pixels per vector group for each input element type (48 B of RGB).
+__host__ __device__ constexpr int group_px(int src_dtype)
+{
+    return src_dtype == 0 ? 16 : (src_dtype == 1 ? 8 : 4);
+}
+
+__host__ __device__ constexpr int elem_size(int dtype)
+{
+    return dtype == 0 ? 1 : (dtype == 1 ? 2 : 4);
+}
+
+// How an image is walked.
+enum Walk : int32_t {
+    kWalkPacked = 0, // one segment of W*H pixels, vector groups
+    kWalkRows = 1,   // H segments of W pixels (16-B aligned pitches), vector groups
+    kWalkScalar = 2, // H segments of W pixels, one pixel at a time
+};
+
+// Per-pixel coefficients of Eqs. (3) and (6), in the scaling the input's
+// per-pixel form expects (see lum_code / lum_linear).
+struct Coef {
+    float cr; // beta_R        (x3 for 8-bit input)
+    float cg; // 1 - beta_R    (x3 for 8-bit input)
+    float ck; // beta_k        (/3 for 8-bit input)
+    float cc; // 1 - beta_k    (/3 for 8-bit input)
+};
+
+// Device-side descriptor of one image, built by the host runtime.
+struct DevImage {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint8_t *dst2;
+    int64_t src_seg_stride; // bytes between segment starts (row pitch, or 0 when packed)
+    int64_t dst_seg_stride;
+    int64_t dst2_seg_stride;
+    int64_t seg_len;        // pixels per segment
+    int64_t tiles_per_seg;  // tiles of the launch's tile size per segment
+    int64_t tile_begin;     // first global tile of this image (batched launches)
+    int64_t chunk_begin;    // first statistics partial of this image (tone map)
+    int64_t ntiles;         // tiles of this image
+    int64_t npx;            // pixels, width * height
+    int32_t src_dtype;
+    int32_t dst_dtype;
+    int32_t dst2_dtype;     // -1 = none
+    int32_t walk;
+    int32_t image;          // index within the call
+    float unit;             // Lhat = L * unit (1/255 for 8-bit input)
+    Coef k;                 // per-pixel constants for this image's input type
+};
+
+// Statistics partial of one chunk, in log2 units: count, mean and sum of
+// squared deviations of x2 = log2(Lhat + eps) (Chan et al. merge), and the
+// extremes of Lhat.
+struct Part {
+    float n, mean, m2, lo, hi;
+};
+
+// Per-image curve of the tone map: T = 1 / (1 + exp2(a * (x2 - mu2))).
+struct Curve {
+    float a, mu2;
+};
+
+struct TmArgs {
+    float eps;
+    float contrast;
+    float sigma_floor;
+};
+
+// Output statistics, laid out as dc_stats.
+struct StatsOut {
+    float log_mean, log_std, l_min, l_max;
+    int64_t count;
+};
+
+// Kernel launchers (kernels.hip). All return the hipError_t of the launch.
+hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid,
+                                 hipStream_t s);
+hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
+                                int64_t total_tiles, int mixed_src, int src_dtype,
+                                int groups, int64_t grid, hipStream_t s);
+hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
+                           int64_t total_tiles, TmArgs tm, Part *parts, hipStream_t s);
+hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *tile_end,
+                              TmArgs tm, const Part *parts, Curve *curves, StatsOut *stats,
+                              hipStream_t s);
+hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
+                           int64_t total_tiles, TmArgs tm, const Curve *curves,
+                           hipStream_t s);
+
+} // namespace dc

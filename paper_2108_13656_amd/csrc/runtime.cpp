@@ -1,0 +1,592 @@
+// Host runtime behind include/decolor.h: argument validation, the context and
+// its workspace ring, the per-image walk classification and tile tables, and
+// the launch sequences of the three compute entry points.
+#include "../../include/decolor.h"
+#include "dc_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+bool dtype_ok(int32_t d) { return d == DC_U8 || d == DC_F16 || d == DC_F32; }
+
+struct Range {
+    uintptr_t lo, hi; // [lo, hi)
+    int image;
+    int kind; // 0 src, 1 dst, 2 dst2
+};
+
+const char *kind_name(int k) { return k == 0 ? "src" : (k == 1 ? "dst" : "dst2"); }
+
+// Byte extent of a 2-D buffer: (height - 1) rows of pitch plus one row. Returns
+// false on int64 overflow.
+bool extent(const void *base, int64_t pitch, int64_t row_bytes, int32_t height, Range &r)
+{
+    const __int128 span = (__int128)pitch * (height - 1) + row_bytes;
+    if (span > (__int128)INT64_MAX)
+        return false;
+    const __int128 hi = (__int128)(uintptr_t)base + span;
+    if (hi > (__int128)UINTPTR_MAX)
+        return false;
+    r.lo = (uintptr_t)base;
+    r.hi = (uintptr_t)hi;
+    return true;
+}
+
+int validate_params(const dc_params *p)
+{
+    if (!p)
+        return DC_OK;
+    const float b[2] = {p->beta_r, p->beta_k};
+    for (float v : b)
+        if (!std::isfinite(v) || v < 0.0f || v > 1.0f)
+            return fail(DC_ERR_INVALID_ARG, "beta_r and beta_k must be finite and in [0, 1]");
+    return DC_OK;
+}
+
+int validate_tm(const dc_tm_params *tm)
+{
+    if (!tm)
+        return DC_OK;
+    const float v[3] = {tm->eps, tm->contrast, tm->sigma_floor};
+    for (float x : v)
+        if (!std::isfinite(x) || !(x > 0.0f))
+            return fail(DC_ERR_INVALID_ARG, "eps, contrast and sigma_floor must be finite and > 0");
+    return DC_OK;
+}
+
+int validate_images(const dc_image *imgs, int32_t n)
+{
+    if (n < 0)
+        return fail(DC_ERR_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && !imgs)
+        return fail(DC_ERR_INVALID_ARG, "image list is NULL");
+    std::vector<Range> outs, ins;
+    outs.reserve((size_t)n * 2);
+    ins.reserve((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const dc_image &m = imgs[i];
+        const std::string at = " (image " + std::to_string(i) + ")";
+        if (!m.src || !m.dst)
+            return fail(DC_ERR_INVALID_ARG, "src and dst must not be NULL" + at);
+        if (m.width < 1 || m.height < 1)
+            return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + at);
+        if (m.flags != 0)
+            return fail(DC_ERR_INVALID_ARG, "flags must be 0" + at);
+        if (!dtype_ok(m.src_dtype) || !dtype_ok(m.dst_dtype))
+            return fail(DC_ERR_INVALID_ARG, "src_dtype and dst_dtype must be DC_U8, DC_F16 or DC_F32" + at);
+        if (m.dst2_dtype == DC_NONE) {
+            if (m.dst2)
+                return fail(DC_ERR_INVALID_ARG, "dst2 must be NULL when dst2_dtype is DC_NONE" + at);
+        } else {
+            if (!dtype_ok(m.dst2_dtype))
+                return fail(DC_ERR_INVALID_ARG, "dst2_dtype must be DC_NONE, DC_U8, DC_F16 or DC_F32" + at);
+            if (!m.dst2)
+                return fail(DC_ERR_INVALID_ARG, "dst2 is NULL but dst2_dtype is set" + at);
+        }
+        const int64_t es = dc::elem_size(m.src_dtype);
+        const int64_t row_in = 3 * es * (int64_t)m.width;
+        if (m.src_pitch < row_in)
+            return fail(DC_ERR_INVALID_ARG, "src_pitch is smaller than 3 * width * element size" + at);
+        if ((uintptr_t)m.src % es || m.src_pitch % es)
+            return fail(DC_ERR_INVALID_ARG, "src and src_pitch must be multiples of the element size" + at);
+        Range r;
+        if (!extent(m.src, m.src_pitch, row_in, m.height, r))
+            return fail(DC_ERR_INVALID_ARG, "src extent overflows" + at);
+        r.image = i;
+        r.kind = 0;
+        ins.push_back(r);
+        const void *op[2] = {m.dst, m.dst2};
+        const int64_t pitch[2] = {m.dst_pitch, m.dst2_pitch};
+        const int32_t dt[2] = {m.dst_dtype, m.dst2_dtype};
+        for (int o = 0; o < 2; ++o) {
+            if (!op[o])
+                continue;
+            const int64_t eo = dc::elem_size(dt[o]);
+            const int64_t row = eo * (int64_t)m.width;
+            if (pitch[o] < row)
+                return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) +
+                                                    "_pitch is smaller than width * element size" + at);
+            if ((uintptr_t)op[o] % eo || pitch[o] % eo)
+                return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) +
+                                                    " and its pitch must be multiples of the element size" + at);
+            if (!extent(op[o], pitch[o], row, m.height, r))
+                return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) + " extent overflows" + at);
+            r.image = i;
+            r.kind = o + 1;
+            outs.push_back(r);
+        }
+    }
+    // No output may overlap another output or any input (inputs may be shared).
+    auto by_lo = [](const Range &a, const Range &b) { return a.lo < b.lo; };
+    std::sort(outs.begin(), outs.end(), by_lo);
+    for (size_t j = 1; j < outs.size(); ++j)
+        if (outs[j].lo < outs[j - 1].hi)
+            return fail(DC_ERR_ALIAS, std::string(kind_name(outs[j].kind)) + " of image " +
+                                          std::to_string(outs[j].image) + " overlaps " +
+                                          kind_name(outs[j - 1].kind) + " of image " +
+                                          std::to_string(outs[j - 1].image));
+    for (const Range &in : ins) {
+        // The output with the largest lo below in.hi is the only candidate
+        // that can overlap, since outputs are disjoint and sorted.
+        auto it = std::lower_bound(outs.begin(), outs.end(), Range{in.hi, 0, 0, 0}, by_lo);
+        if (it != outs.begin()) {
+            const Range &o = *(it - 1);
+            if (o.hi > in.lo)
+                return fail(DC_ERR_ALIAS, std::string(kind_name(o.kind)) + " of image " +
+                                              std::to_string(o.image) + " overlaps src of image " +
+                                              std::to_string(in.image));
+        }
+    }
+    return DC_OK;
+}
+
+// Constants of the two per-pixel forms. The 8-bit form carries sqrt(3) S
+// scaling (cr, cg scaled by 3; ck, cc by 1/3); the linear form uses the plain
+// weights. Computed in double, rounded once.
+dc::Coef coef_of(const dc_params *p, int src_dtype)
+{
+    const double br = p ? p->beta_r : 0.55, bk = p ? p->beta_k : 0.80;
+    if (src_dtype == DC_U8)
+        return dc::Coef{(float)(3.0 * br), (float)(3.0 * (1.0 - br)), (float)(bk / 3.0),
+                        (float)((1.0 - bk) / 3.0)};
+    return dc::Coef{(float)br, (float)(1.0 - br), (float)bk, (float)(1.0 - bk)};
+}
+
+dc::TmArgs tm_of(const dc_tm_params *tm)
+{
+    return tm ? dc::TmArgs{tm->eps, tm->contrast, tm->sigma_floor} : dc::TmArgs{1e-4f, 2.0f, 1e-3f};
+}
+
+// Walk classification and tile count of one image for tiles of tile_px pixels.
+dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_params *params)
+{
+    dc::DevImage d;
+    std::memset(&d, 0, sizeof(d));
+    d.src = (const uint8_t *)m.src;
+    d.dst = (uint8_t *)m.dst;
+    d.dst2 = (uint8_t *)m.dst2;
+    d.src_dtype = m.src_dtype;
+    d.dst_dtype = m.dst_dtype;
+    d.dst2_dtype = m.dst2 ? m.dst2_dtype : DC_NONE;
+    d.image = index;
+    d.unit = m.src_dtype == DC_U8 ? (float)(1.0 / 255.0) : 1.0f;
+    d.npx = (int64_t)m.width * m.height;
+    d.k = coef_of(params, m.src_dtype);
+
+    const int64_t W = m.width, H = m.height;
+    const int64_t es = dc::elem_size(m.src_dtype);
+    const int64_t e1 = dc::elem_size(m.dst_dtype);
+    const int64_t e2 = m.dst2 ? dc::elem_size(m.dst2_dtype) : 0;
+    const bool aligned = ((uintptr_t)m.src % 16 == 0) && ((uintptr_t)m.dst % 16 == 0) &&
+                         (!m.dst2 || (uintptr_t)m.dst2 % 16 == 0);
+    const bool packed = H == 1 || (m.src_pitch == 3 * es * W && m.dst_pitch == e1 * W &&
+                                   (!m.dst2 || m.dst2_pitch == e2 * W));
+    const bool rows16 = m.src_pitch % 16 == 0 && m.dst_pitch % 16 == 0 &&
+                        (!m.dst2 || m.dst2_pitch % 16 == 0);
+    int64_t nseg;
+    if (aligned && packed) {
+        d.walk = dc::kWalkPacked;
+        d.seg_len = W * H;
+        nseg = 1;
+    } else {
+        d.walk = (aligned && rows16) ? dc::kWalkRows : dc::kWalkScalar;
+        d.seg_len = W;
+        d.src_seg_stride = m.src_pitch;
+        d.dst_seg_stride = m.dst_pitch;
+        d.dst2_seg_stride = m.dst2 ? m.dst2_pitch : 0;
+        nseg = H;
+    }
+    d.tiles_per_seg = (d.seg_len + tile_px - 1) / tile_px;
+    d.ntiles = d.tiles_per_seg * nseg;
+    return d;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+} // namespace
+
+// ------------------------------------------------------------------ context
+
+struct dc_ctx {
+    static constexpr int kSlots = 8;
+    struct Slot {
+        void *host = nullptr;  // pinned staging of the descriptor table
+        size_t host_cap = 0;
+        void *dev = nullptr;   // device table, tile ends, partials, curves
+        size_t dev_cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    };
+    int device = 0;
+    int num_cu = 256;
+    int groups = 2;  // vector groups per thread per decolorization tile
+    int64_t grid = 0; // 0 = one workgroup per tile
+    Slot slots[kSlots];
+    int next = 0;
+    // Measurement hooks: timing events recorded around each kernel.
+    static constexpr int kMaxEvents = 8;
+    bool profiling = false;
+    hipEvent_t prof[kMaxEvents] = {};
+    int prof_used = 0;
+};
+
+namespace {
+
+// Takes the next workspace slot, waiting for the work that last used it, and
+// makes sure it can hold host_bytes of staging and dev_bytes on the device.
+int acquire_slot(dc_ctx *ctx, size_t host_bytes, size_t dev_bytes, dc_ctx::Slot **out)
+{
+    dc_ctx::Slot &s = ctx->slots[ctx->next];
+    ctx->next = (ctx->next + 1) % dc_ctx::kSlots;
+    if (s.pending) {
+        if (hipEventSynchronize(s.done) != hipSuccess)
+            return fail(DC_ERR_HIP, "hipEventSynchronize failed on a workspace slot");
+        s.pending = false;
+    }
+    if (s.host_cap < host_bytes) {
+        if (s.host)
+            (void)hipHostFree(s.host);
+        s.host = nullptr;
+        s.host_cap = 0;
+        const size_t cap = std::max(host_bytes + host_bytes / 2, (size_t)4096);
+        if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(DC_ERR_NO_MEMORY, "pinned staging allocation failed");
+        s.host_cap = cap;
+    }
+    if (s.dev_cap < dev_bytes) {
+        if (s.dev)
+            (void)hipFree(s.dev);
+        s.dev = nullptr;
+        s.dev_cap = 0;
+        const size_t cap = std::max(dev_bytes + dev_bytes / 2, (size_t)65536);
+        if (hipMalloc(&s.dev, cap) != hipSuccess)
+            return fail(DC_ERR_NO_MEMORY, "device workspace allocation failed");
+        s.dev_cap = cap;
+    }
+    *out = &s;
+    return DC_OK;
+}
+
+int release_slot(dc_ctx::Slot *s, hipStream_t stream)
+{
+    if (hipEventRecord(s->done, stream) != hipSuccess)
+        return fail(DC_ERR_HIP, "hipEventRecord failed");
+    s->pending = true;
+    return DC_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Records timing event i on the stream when profiling is on.
+void mark(dc_ctx *ctx, int i, hipStream_t s)
+{
+    if (!ctx->profiling || i >= dc_ctx::kMaxEvents)
+        return;
+    if (hipEventRecord(ctx->prof[i], s) == hipSuccess)
+        ctx->prof_used = i + 1;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Builds the descriptor table and inclusive tile-end prefix for n images in
+// the slot's staging buffer, copies it to the device, and returns the device
+// addresses of both.
+struct Table {
+    dc::DevImage *table;
+    int64_t *tile_end;
+    dc::Part *parts;
+    dc::Curve *curves;
+    int64_t total_tiles;
+    bool mixed;
+};
+
+int stage_table(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                bool tonemap, int groups, hipStream_t stream, dc_ctx::Slot **slot_out, Table *t)
+{
+    std::vector<dc::DevImage> d((size_t)n);
+    int64_t total = 0;
+    bool mixed = false;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t tile_px = tonemap ? dc::kStatsChunkPx
+                                        : (int64_t)dc::kBlock * groups * dc::group_px(imgs[i].src_dtype);
+        d[i] = describe(imgs[i], i, tile_px, params);
+        d[i].tile_begin = total;
+        d[i].chunk_begin = total; // one statistics partial per tile on the tone-map path
+        total += d[i].ntiles;
+        mixed |= imgs[i].src_dtype != imgs[0].src_dtype;
+    }
+    const size_t tbl = align_up(sizeof(dc::DevImage) * n, 256);
+    const size_t ends = align_up(sizeof(int64_t) * n, 256);
+    const size_t parts = tonemap ? align_up(sizeof(dc::Part) * (size_t)total, 256) : 0;
+    const size_t curves = tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0;
+    dc_ctx::Slot *s = nullptr;
+    int rc = acquire_slot(ctx, tbl + ends, tbl + ends + parts + curves, &s);
+    if (rc != DC_OK)
+        return rc;
+    char *h = (char *)s->host;
+    std::memcpy(h, d.data(), sizeof(dc::DevImage) * n);
+    int64_t *he = (int64_t *)(h + tbl);
+    for (int32_t i = 0; i < n; ++i)
+        he[i] = d[i].tile_begin + d[i].ntiles;
+    hipError_t e = hipMemcpyAsync(s->dev, s->host, tbl + ends, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "descriptor upload");
+    char *dv = (char *)s->dev;
+    t->table = (dc::DevImage *)dv;
+    t->tile_end = (int64_t *)(dv + tbl);
+    t->parts = tonemap ? (dc::Part *)(dv + tbl + ends) : nullptr;
+    t->curves = tonemap ? (dc::Curve *)(dv + tbl + ends + parts) : nullptr;
+    t->total_tiles = total;
+    t->mixed = mixed;
+    *slot_out = s;
+    return DC_OK;
+}
+
+int check_ctx(dc_ctx *ctx)
+{
+    if (!ctx)
+        return fail(DC_ERR_INVALID_ARG, "context is NULL");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    return DC_OK;
+}
+
+} // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int dc_version(void) { return DC_ABI_VERSION; }
+
+const char *dc_status_string(int status)
+{
+    switch (status) {
+    case DC_OK: return "ok";
+    case DC_ERR_INVALID_ARG: return "invalid argument";
+    case DC_ERR_UNSUPPORTED: return "unsupported";
+    case DC_ERR_ALIAS: return "output overlaps an input or another output";
+    case DC_ERR_NO_MEMORY: return "out of memory";
+    case DC_ERR_HIP: return "HIP runtime error";
+    case DC_ERR_NO_DEVICE: return "no usable device";
+    default: return "unknown status";
+    }
+}
+
+const char *dc_last_error_message(void) { return g_last_error.c_str(); }
+
+int dc_validate(const dc_image *imgs, int32_t n, const dc_params *params, const dc_tm_params *tm)
+{
+    g_last_error.clear();
+    int rc = validate_params(params);
+    if (rc == DC_OK)
+        rc = validate_tm(tm);
+    if (rc == DC_OK)
+        rc = validate_images(imgs, n);
+    return rc;
+}
+
+int dc_create(dc_ctx **out, int device)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(DC_ERR_INVALID_ARG, "ctx out-pointer is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(DC_ERR_NO_DEVICE, "no HIP device is visible");
+    if (device < 0 || device >= count)
+        return fail(DC_ERR_NO_DEVICE, "device index out of range");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipSetDevice");
+    dc_ctx *ctx = new (std::nothrow) dc_ctx();
+    if (!ctx)
+        return fail(DC_ERR_NO_MEMORY, "context allocation failed");
+    ctx->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+        ctx->num_cu = cus;
+    ctx->groups = env_int("DC_GROUPS", 2);
+    if (ctx->groups != 1 && ctx->groups != 2 && ctx->groups != 4)
+        ctx->groups = 2;
+    ctx->grid = env_int("DC_GRID", 0);
+    for (auto &s : ctx->slots) {
+        e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            dc_destroy(ctx);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    *out = ctx;
+    return DC_OK;
+}
+
+int dc_set_profiling(dc_ctx *ctx, int on)
+{
+    g_last_error.clear();
+    if (!ctx)
+        return fail(DC_ERR_INVALID_ARG, "context is NULL");
+    if (on && !ctx->prof[0]) {
+        (void)hipSetDevice(ctx->device);
+        for (auto &e : ctx->prof) {
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess)
+                return hip_fail(err, "hipEventCreate");
+        }
+    }
+    ctx->profiling = on != 0;
+    ctx->prof_used = 0;
+    return DC_OK;
+}
+
+int dc_last_timings(dc_ctx *ctx, float *ms, int32_t cap)
+{
+    g_last_error.clear();
+    if (!ctx || (!ms && cap > 0) || cap < 0)
+        return fail(DC_ERR_INVALID_ARG, "bad context or output array");
+    if (ctx->prof_used < 2)
+        return 0;
+    hipError_t e = hipEventSynchronize(ctx->prof[ctx->prof_used - 1]);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipEventSynchronize");
+    int n = 0;
+    for (int i = 0; i + 1 < ctx->prof_used && n < cap; ++i, ++n) {
+        e = hipEventElapsedTime(&ms[n], ctx->prof[i], ctx->prof[i + 1]);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventElapsedTime");
+    }
+    return n;
+}
+
+int dc_destroy(dc_ctx *ctx)
+{
+    if (!ctx)
+        return DC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &s : ctx->slots) {
+        if (s.host)
+            (void)hipHostFree(s.host);
+        if (s.dev)
+            (void)hipFree(s.dev);
+        if (s.done)
+            (void)hipEventDestroy(s.done);
+    }
+    for (auto &e : ctx->prof)
+        if (e)
+            (void)hipEventDestroy(e);
+    delete ctx;
+    return DC_OK;
+}
+
+int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, void *stream)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    if (!img)
+        return fail(DC_ERR_INVALID_ARG, "image is NULL");
+    rc = dc_validate(img, 1, params, nullptr);
+    if (rc != DC_OK)
+        return rc;
+    const int g = ctx->groups;
+    const dc::DevImage d =
+        describe(*img, 0, (int64_t)dc::kBlock * g * dc::group_px(img->src_dtype), params);
+    ctx->prof_used = 0;
+    mark(ctx, 0, (hipStream_t)stream);
+    hipError_t e = dc::launch_decolor_single(d, g, ctx->grid, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "decolorize launch");
+    mark(ctx, 1, (hipStream_t)stream);
+    return DC_OK;
+}
+
+int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                        void *stream)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    rc = dc_validate(imgs, n, params, nullptr);
+    if (rc != DC_OK || n == 0)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    dc_ctx::Slot *slot = nullptr;
+    Table t;
+    rc = stage_table(ctx, imgs, n, params, false, ctx->groups, st, &slot, &t);
+    if (rc != DC_OK)
+        return rc;
+    ctx->prof_used = 0;
+    mark(ctx, 0, st);
+    hipError_t e = dc::launch_decolor_table(t.table, t.tile_end, n, t.total_tiles, t.mixed,
+                                            imgs[0].src_dtype, ctx->groups,
+                                            ctx->grid, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "decolorize_batch launch");
+    mark(ctx, 1, st);
+    return release_slot(slot, st);
+}
+
+int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                      const dc_tm_params *tm, dc_stats *stats, void *stream)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    rc = dc_validate(imgs, n, params, tm);
+    if (rc != DC_OK || n == 0)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    dc_ctx::Slot *slot = nullptr;
+    Table t;
+    rc = stage_table(ctx, imgs, n, params, true, 0, st, &slot, &t);
+    if (rc != DC_OK)
+        return rc;
+    const dc::TmArgs a = tm_of(tm);
+    ctx->prof_used = 0;
+    mark(ctx, 0, st);
+    hipError_t e = dc::launch_tm_pass1(t.table, t.tile_end, n, t.total_tiles, a, t.parts, st);
+    mark(ctx, 1, st);
+    if (e == hipSuccess)
+        e = dc::launch_tm_finalize(t.table, n, t.tile_end, a, t.parts, t.curves,
+                                   (dc::StatsOut *)stats, st);
+    mark(ctx, 2, st);
+    if (e == hipSuccess)
+        e = dc::launch_tm_pass2(t.table, t.tile_end, n, t.total_tiles, a, t.curves, st);
+    mark(ctx, 3, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "tonemap_global launch");
+    return release_slot(slot, st);
+}
+
+} // extern "C"
+
+static_assert(sizeof(dc_stats) == sizeof(dc::StatsOut), "dc_stats layout");
+static_assert(sizeof(dc_image) == 72, "dc_image layout");

@@ -1,0 +1,65 @@
+"""Shared helpers of the GPU parity tests: tolerances, comparisons, reporting."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+F32_ABS_TOL = 1e-5  # FP32 output vs the FP64 oracle on the [0, 1] scale
+F32_REL_TOL = 1e-5  # linear (HDR) inputs: relative to the oracle value
+U8_MAX_LSB = 1      # 8-bit outputs: at most one code apart
+U8_MAX_MISMATCH_FRACTION = 1e-4
+
+
+def report(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    import paper_2108_13656_amd as P
+    P.lib()  # raises if the HIP library is not built
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def check_f32(got, want_lhat, what, rel=False):
+    """|got - want| <= 1e-5 (absolute on [0, 1]; relative to max(1, |want|) when rel)."""
+    got = np.asarray(got, np.float64)
+    err = np.abs(got - want_lhat)
+    scale = np.maximum(1.0, np.abs(want_lhat)) if rel else 1.0
+    worst = float(np.max(err / scale)) if err.size else 0.0
+    report("%s: max %s error %.3e over %d px" % (what, "scaled" if rel else "abs", worst, err.size))
+    assert worst <= (F32_REL_TOL if rel else F32_ABS_TOL), what
+    return worst
+
+
+def check_u8(got, want_codes, what, max_fraction=U8_MAX_MISMATCH_FRACTION):
+    got = np.asarray(got).astype(np.int32)
+    want = np.asarray(want_codes).astype(np.int32)
+    diff = np.abs(got - want)
+    n_off = int(np.count_nonzero(diff))
+    frac = n_off / max(1, diff.size)
+    report("%s: u8 max |diff| %d, %d of %d codes off by one (fraction %.3e)" %
+           (what, int(diff.max()) if diff.size else 0, n_off, diff.size, frac))
+    assert int(diff.max() if diff.size else 0) <= U8_MAX_LSB, what
+    assert frac <= max_fraction, what
+    return frac
+
+
+def check_f16(got_half, want_half, what):
+    """GPU binary16 output vs the oracle's round-to-nearest-even encoding of the
+    FP64 value: equal, or one binary16 step apart where FP32 rounding moved the
+    value across a rounding midpoint."""
+    g = np.asarray(got_half, np.float16).astype(np.float64)
+    w = np.asarray(want_half, np.float16).astype(np.float64)
+    step = np.spacing(np.abs(w).astype(np.float16)).astype(np.float64)
+    bad = np.abs(g - w) > step
+    n_off = int(np.count_nonzero(g != w))
+    report("%s: f16 %d of %d values one step off" % (what, n_off, g.size))
+    assert not np.any(bad), what

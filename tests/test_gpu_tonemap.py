@@ -1,0 +1,121 @@
+"""GPU parity of the global tone map (Sec. III-B.1, centred sigmoid on
+ln(Lhat + eps), slope normalised by the image's standard deviation) against the
+FP64 oracle, through ``dc_tonemap_global``.
+
+Tolerances. The statistics are FP32 Chan merges of FP32 log2 values: |d mu| and
+|d sigma| / sigma stay below 2e-5. T = 1 / (1 + exp(-c z)) moves by at most
+c / 4 * |dz| with z = (x - mu) / s, so for images with sigma >= 0.1 the 1e-5
+bound on T holds with room to spare; flat images are checked by their closed
+form (T = 1/2) instead.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2108_13656_amd as P
+import synth
+from gpuhelp import check_f32, check_u8, need_gpu, report, to_dev
+
+pytestmark = pytest.mark.gpu
+TM = dict(eps=1e-4, contrast=2.0, sigma_floor=1e-3)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def _check_stats(st, ref, what):
+    report("%s: mu %.7f/%.7f sigma %.7f/%.7f" % (what, st["mu"], ref["mu"], st["sigma"],
+                                                  ref["sigma"]))
+    assert abs(st["mu"] - ref["mu"]) <= 2e-5 * (1 + abs(ref["mu"])), what
+    assert abs(st["sigma"] - ref["sigma"]) <= 2e-5 * max(ref["sigma"], 1e-3), what
+    assert st["l_min"] == pytest.approx(ref["l_min"], rel=1e-5, abs=1e-6)
+    assert st["l_max"] == pytest.approx(ref["l_max"], rel=1e-5, abs=1e-6)
+    assert st["count"] == ref["count"]
+
+
+@pytest.mark.parametrize("kind,shape", [("u8", (64, 64)), ("u8", (1, 1)), ("u8", (37, 91)),
+                                        ("f16", (256, 256)), ("f16", (5, 4099)),
+                                        ("f32", (70, 33)), ("u8", (512, 512))])
+def test_tonemap_vs_oracle(dev, kind, shape):
+    h, w = shape
+    if kind == "u8":
+        img = synth.gradient_rects() if shape == (512, 512) else synth.random_image(7, h, w, np.uint8)
+    elif kind == "f16":
+        img = synth.hdr_pixels(np.random.default_rng(h * w), h, w)
+    else:
+        img = synth.random_image(8, h, w, np.float32, scale=5.0)
+    t_ref, lhat_ref, st_ref = oracle.tonemap(img, **TM)
+    outs, lhats, stats = P.tonemap_global([to_dev(img, dev)], torch.float32, torch.float32, **TM)
+    st = P.stats_to_host(stats)[0]
+    name = "%s %dx%d" % (kind, h, w)
+    if h * w > 1:
+        _check_stats(st, st_ref, name)
+        check_f32(outs[0].cpu().numpy(), t_ref, name + " T")
+    else:
+        assert st["sigma"] == 0.0 and outs[0].item() == 0.5
+    check_f32(lhats[0].cpu().numpy(), lhat_ref, name + " Lhat", rel=kind != "u8")
+
+
+def test_two_pixel_closed_form(dev):
+    img = np.array([[[200, 10, 10], [10, 20, 200]]], np.uint8)
+    outs, _, _ = P.tonemap_global([to_dev(img, dev)], **TM)
+    got = sorted(outs[0].cpu().numpy().ravel())
+    want = [1 / (1 + math.exp(2.0)), 1 / (1 + math.exp(-2.0))]
+    report("two-pixel T %s vs %s" % (got, want))
+    assert got == pytest.approx(want, abs=1e-5)
+
+
+def test_constant_image_is_one_half(dev):
+    for img in (np.full((33, 65, 3), 77, np.uint8), np.full((7, 9, 3), 3.5, np.float16)):
+        outs, _, stats = P.tonemap_global([to_dev(img, dev)], **TM)
+        assert torch.all(outs[0] == 0.5)
+        assert P.stats_to_host(stats)[0]["sigma"] == 0.0
+
+
+def test_u8_output_codes(dev):
+    img = synth.gradient_rects()
+    t_ref, _, _ = oracle.tonemap(img, **TM)
+    outs, _, _ = P.tonemap_global([to_dev(img, dev)], torch.uint8, **TM)
+    check_u8(outs[0].cpu().numpy(), oracle.encode_u8(t_ref), "tonemap u8", max_fraction=1e-3)
+
+
+def test_lhat_matches_decolorize(dev):
+    img = synth.hdr_pixels(np.random.default_rng(3), 77, 190)
+    x = to_dev(img, dev)
+    _, lhats, _ = P.tonemap_global([x], torch.float32, torch.float32, **TM)
+    assert torch.equal(lhats[0], P.decolorize(x))
+
+
+def test_result_independent_of_batch(dev):
+    """Each image's T and statistics are bit-identical alone and in a mix."""
+    rng = np.random.default_rng(9)
+    imgs = []
+    for i in range(9):
+        h, w = (int(v) for v in rng.integers(1, 400, 2))
+        imgs.append(synth.hdr_pixels(rng, h, w) if i % 2 else synth.sdr_pixels(rng, h, w))
+    xs = [to_dev(a, dev) for a in imgs]
+    mix_t, _, mix_st = P.tonemap_global(xs, torch.float32, **TM)
+    mix_st = P.stats_to_host(mix_st)
+    for i, x in enumerate(xs):
+        t, _, st = P.tonemap_global([x], torch.float32, **TM)
+        assert torch.equal(t[0], mix_t[i]), i
+        assert P.stats_to_host(st)[0] == mix_st[i], i
+    for i in (0, 1):
+        t_ref, _, st_ref = oracle.tonemap(imgs[i], **TM)
+        _check_stats(mix_st[i], st_ref, "mix image %d" % i)
+        check_f32(mix_t[i].cpu().numpy(), t_ref, "mix image %d T" % i)
+
+
+def test_pitched_and_unaligned_views(dev):
+    big = synth.random_image(11, 50, 96, np.uint8)
+    for x0, name in ((16, "rows"), (1, "scalar")):
+        view = big[:, x0:x0 + 70]
+        t_ref, _, st_ref = oracle.tonemap(view, **TM)
+        outs, _, stats = P.tonemap_global([to_dev(big, dev)[:, x0:x0 + 70]], **TM)
+        _check_stats(P.stats_to_host(stats)[0], st_ref, name)
+        check_f32(outs[0].cpu().numpy(), t_ref, name + " T")
