@@ -36,10 +36,15 @@ def parse():
     ap.add_argument("--images", type=int, default=16, help="HDR images per step")
     ap.add_argument("--size", type=int, default=4096, help="HDR image side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-images", type=int, default=2)
+    ap.add_argument("--cpu-sample-images", type=int, default=8)
     ap.add_argument("--skip-video", action="store_true")
     ap.add_argument("--only", choices=["tonemap", "video"], default=None,
                     help="time one workload only (for profiler runs)")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON launch shapes to use instead of autotuning (written by --save-tuning)")
+    ap.add_argument("--save-tuning", default=None, help="write the autotuned shapes here")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -92,6 +97,28 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(dev)
     result = {}
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n, "copies": 3}), flush=True)
+        return
+    fixed = None
+    if args.tuning:
+        with open(args.tuning) as f:
+            fixed = json.load(f)
+    saved = {}
+
+    def tune(kind, *bufs):
+        if fixed is not None:
+            P.set_tuning(fixed, dev)
+            return P.get_tuning(dev)
+        t = P.autotune(kind, *bufs, stream=stream)
+        saved.update(t)
+        return t
 
     # ---------------------------------------------------- HDR tone map (headline)
     n_img, size = args.images, args.size
@@ -106,12 +133,19 @@ def main():
         stats = torch.empty((n_img, P.STATS_BYTES), dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
 
-        def step():
-            P.tonemap_global(xs, outs=outs, stats=stats, stream=stream)
-
         with torch.cuda.stream(stream):
+            tuning = tune(P.PLAN_TONEMAP, xs, outs)
+            log("autotuned tone-map shape: %s" % tuning)
+            plan = P.Plan(P.PLAN_TONEMAP, xs, outs, stats=stats, graph=True)
+            plan_ev = P.Plan(P.PLAN_TONEMAP, xs, outs, stats=stats, graph=False)
+
+            def step():
+                plan.run(stream)
+
             ms = time_steps(step, args.steps, args.warmup, stream)
-            ktimes = kernel_times(step, max(5, args.steps // 2), P, dev)
+            ktimes = kernel_times(lambda: plan_ev.run(stream), max(5, args.steps // 2), P, dev)
+            dyn_ms = time_steps(lambda: P.tonemap_global(xs, outs=outs, stats=stats, stream=stream),
+                                max(3, args.steps // 2), 1, stream)
         log("tonemap step %.3f ms; kernels (pass1, combine, pass2) %s ms" %
             (ms, ", ".join("%.3f" % t for t in ktimes)))
         gpx = hdr_px / (ms * 1e-3) / 1e9
@@ -132,6 +166,9 @@ def main():
             "hbm_frac_step": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "kernel_ms": {"tonemap_pass1": round(k_pass1, 4), "tonemap_combine": round(k_comb, 4),
                           "tonemap_pass2": round(k_pass2, 4)},
+            "launch": {"plan": "hip graph replay of the 3 kernels",
+                       "tuning": {k: v for k, v in tuning.items() if "pass" in k},
+                       "per_call_api_ms_per_step": round(dyn_ms, 4)},
             "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                          "traffic": None},
@@ -142,12 +179,13 @@ def main():
             import oracle
             k = min(args.cpu_sample_images, n_img)
             log("cpu baseline: oracle on %d image(s), 1 thread" % k)
-            t0 = time.time()
+            dt = 0.0
             worst = 0.0
             for i in range(k):
+                t0 = time.time()
                 t_ref, _, _ = oracle.tonemap(imgs[i], nthreads=1)
+                dt += time.time() - t0
                 worst = max(worst, float(np.max(np.abs(outs[i].cpu().numpy() - t_ref))))
-            dt = time.time() - t0
             cpu_gpx = k * size * size / dt / 1e9
             result["cpu_baseline"] = {"value": round(cpu_gpx, 6), "unit": "Gpixels/s", "cores": 1,
                                       "kind": "oracle",
@@ -155,6 +193,8 @@ def main():
                                                 "FP64, one thread" % (k, n_img, size, size)}
             result["parity_sample"] = {"images": k, "max_abs_err_T": worst}
             log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
+        plan.close()
+        plan_ev.close()
         del xs, outs
         torch.cuda.empty_cache()
 
@@ -170,23 +210,33 @@ def main():
         o32 = [torch.empty(f.shape[:2], dtype=torch.float32, device=dev) for f in frames]
         torch.cuda.synchronize()
 
-        def vstep():
-            P.decolorize_batch(frames, outs=o8, outs2=o32, stream=stream)
-
-        def vstep_single():
-            for f, a, b in zip(frames, o8, o32):
-                P.decolorize(f, out=a, out2=b, stream=stream)
-
         with torch.cuda.stream(stream):
-            vms = time_steps(vstep, args.steps, args.warmup, stream)
-            vk = kernel_times(vstep, max(5, args.steps // 2), P, dev)[0]
-            vms_single = time_steps(vstep_single, max(3, args.steps // 4), 1, stream)
+            vtune = tune(P.PLAN_DECOLORIZE, frames, o8, o32)
+            log("autotuned decolorize shape: %s" % vtune)
+            vplan = P.Plan(P.PLAN_DECOLORIZE, frames, o8, o32, graph=True)
+            vplan_ev = P.Plan(P.PLAN_DECOLORIZE, frames, o8, o32, graph=False)
+            # plain per-image launches: one kernel per frame, no host marshalling
+            singles = [P.Plan(P.PLAN_DECOLORIZE, [f], [a], [b]) for f, a, b in zip(frames, o8, o32)]
+
+            def vstep_single():
+                for sp in singles:
+                    sp.run(stream)
+
+            vms = time_steps(lambda: vplan.run(stream), args.steps, args.warmup, stream)
+            vk = kernel_times(lambda: vplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
+            vms_single = time_steps(vstep_single, max(3, args.steps // 2), 1, stream)
+            vplan.close()
+            vplan_ev.close()
+            for sp in singles:
+                sp.close()
         vbytes = vpx * 8
         vach = vbytes / (vk * 1e-3) / 1e9
         video = {"workload": "video_decolorize", "frames": "32x1920x1080 + 32x3840x2160",
                  "src": "u8 sRGB", "dst": "u8 + f32", "ms_per_step": round(vms, 4),
                  "value": round(vpx / (vms * 1e-3) / 1e9, 3), "unit": "Gpixels/s",
                  "per_image_launches_gpx": round(vpx / (vms_single * 1e-3) / 1e9, 3),
+                 "tuning": {"groups_u8": vtune["groups"][0],
+                            "grid_per_cu": vtune["decolor_grid_per_cu"]},
                  "roofline": {"bound": "hbm", "kernel": "decolor_table", "achieved": round(vach, 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(vach / HBM_PEAK_GBS, 4), "traffic": None}}
@@ -201,6 +251,9 @@ def main():
                            "roofline": video["roofline"]})
         else:
             result["video_decolorize"] = video
+    if args.save_tuning and saved:
+        with open(args.save_tuning, "w") as f:
+            json.dump(P.get_tuning(dev), f)
     print(json.dumps(result), flush=True)
 
 

@@ -157,6 +157,61 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
 int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                       const dc_tm_params *tm, dc_stats *stats, void *stream);
 
+/* ---------------------------------------------------------------- plans
+ * A plan freezes one call's images, parameters and launch shape: the
+ * descriptor table is built, validated and copied to the device once, and
+ * every dc_plan_run enqueues only the kernels. This is the batched launch of
+ * dc_decolorize_batch (kind DC_PLAN_DECOLORIZE) or the three-kernel tone map
+ * of dc_tonemap_global (kind DC_PLAN_TONEMAP) for callers that process the
+ * same buffers repeatedly (video pipelines, serving slots). The buffers named
+ * by the plan must outlive it. With DC_PLAN_GRAPH the first run captures the
+ * kernels into a HIP graph on `stream` (which must not be NULL) and every run
+ * replays that graph. Results equal those of the corresponding direct call.
+ * A plan may run on any stream of its context's device, but runs of one plan
+ * must not overlap (they share its statistics workspace). */
+typedef struct dc_plan dc_plan;
+#define DC_PLAN_DECOLORIZE 0
+#define DC_PLAN_TONEMAP 1
+#define DC_PLAN_GRAPH 1 /* flag */
+
+/* imgs: HOST array of n >= 1 descriptors; tm and stats (DEVICE, n entries)
+ * only for DC_PLAN_TONEMAP; flags 0 or DC_PLAN_GRAPH. Allocates the plan's
+ * device workspace and waits for its upload. Errors as dc_tonemap_global. */
+int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
+                   const dc_params *params, const dc_tm_params *tm, dc_stats *stats,
+                   int32_t flags, dc_plan **plan);
+int dc_plan_run(dc_plan *plan, void *stream);
+/* Synchronises the device and frees the plan. NULL is a no-op. */
+int dc_plan_destroy(dc_plan *plan);
+
+/* --------------------------------------------------------------- tuning
+ * Launch shapes used by later calls and plans of a context. groups: vector
+ * groups (48 input bytes each) per thread in a decolorization tile, 1, 2 or 4,
+ * per input type (index DC_U8, DC_F16, DC_F32) and for batches mixing input
+ * types; *_grid_per_cu: persistent workgroups per compute unit, 0..64, where
+ * 0 launches one workgroup per tile. The tone map's statistics chunks are
+ * fixed (1024 pixels per partial), so no setting changes any result bit. */
+typedef struct dc_tuning {
+    int32_t groups[3];
+    int32_t mixed_groups;
+    int32_t decolor_grid_per_cu;
+    int32_t pass1_grid_per_cu;
+    int32_t pass2_grid_per_cu;
+} dc_tuning;
+
+int dc_get_tuning(dc_ctx *ctx, dc_tuning *out);
+int dc_set_tuning(dc_ctx *ctx, const dc_tuning *tuning);
+
+/* Autotuner: times every candidate launch shape (groups 1/2/4 x grids per CU
+ * 0/1/2/4/8/16 for kind DC_PLAN_DECOLORIZE; grids per CU for each tone-map
+ * pass for DC_PLAN_TONEMAP) on the given images with HIP events on `stream`
+ * (median of 5 runs after a warm-up), keeps the fastest in the context and
+ * writes it to *chosen (if not NULL). The candidate runs write the images'
+ * outputs. Synchronises `stream`. */
+int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
+                const dc_params *params, const dc_tm_params *tm, void *stream,
+                dc_tuning *chosen);
+
 /* Measurement hooks (instrumentation, not part of the method). With on != 0,
  * every later compute call on ctx records timing events on its stream before
  * and after each kernel it launches: decolorize and decolorize_batch record one

@@ -58,6 +58,32 @@ class DcStats(ctypes.Structure):
 STATS_BYTES = ctypes.sizeof(DcStats)
 
 
+class DcTuning(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32 * 3), ("mixed_groups", ctypes.c_int32),
+                ("decolor_grid_per_cu", ctypes.c_int32), ("pass1_grid_per_cu", ctypes.c_int32),
+                ("pass2_grid_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"groups": list(self.groups), "mixed_groups": self.mixed_groups,
+                "decolor_grid_per_cu": self.decolor_grid_per_cu,
+                "pass1_grid_per_cu": self.pass1_grid_per_cu,
+                "pass2_grid_per_cu": self.pass2_grid_per_cu}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for i, g in enumerate(d["groups"]):
+            t.groups[i] = g
+        t.mixed_groups = d["mixed_groups"]
+        t.decolor_grid_per_cu = d["decolor_grid_per_cu"]
+        t.pass1_grid_per_cu = d["pass1_grid_per_cu"]
+        t.pass2_grid_per_cu = d["pass2_grid_per_cu"]
+        return t
+
+
+PLAN_DECOLORIZE, PLAN_TONEMAP, PLAN_GRAPH = 0, 1, 1
+
+
 class DecolorError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s (status %d): %s" % (_status_string(status), status, message))
@@ -90,10 +116,19 @@ def lib():
     L.dc_last_error_message.argtypes = []
     L.dc_last_error_message.restype = ctypes.c_char_p
     L.dc_version.argtypes = []
+    tun_p = ctypes.POINTER(DcTuning)
+    L.dc_plan_create.argtypes = [vp, i32, img_p, i32, par_p, tm_p, vp, i32, ctypes.POINTER(vp)]
+    L.dc_plan_run.argtypes = [vp, vp]
+    L.dc_plan_destroy.argtypes = [vp]
+    L.dc_get_tuning.argtypes = [vp, tun_p]
+    L.dc_set_tuning.argtypes = [vp, tun_p]
+    L.dc_autotune.argtypes = [vp, i32, img_p, i32, par_p, tm_p, vp, tun_p]
     L.dc_set_profiling.argtypes = [vp, ctypes.c_int]
     L.dc_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     for name in ("dc_create", "dc_destroy", "dc_validate", "dc_decolorize", "dc_decolorize_batch",
-                 "dc_tonemap_global", "dc_version", "dc_set_profiling", "dc_last_timings"):
+                 "dc_tonemap_global", "dc_version", "dc_set_profiling", "dc_last_timings",
+                 "dc_plan_create", "dc_plan_run", "dc_plan_destroy", "dc_get_tuning",
+                 "dc_set_tuning", "dc_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -300,6 +335,66 @@ def validate(images, beta_r=BETA_R, beta_k=BETA_K, tm=None):
     tmp = DcTmParams(*tm) if tm is not None else None
     return lib().dc_validate(arr, len(images), ctypes.byref(p),
                              ctypes.byref(tmp) if tmp is not None else None)
+
+
+class Plan:
+    """A frozen batched decolorization or tone map over fixed buffers
+    (``dc_plan_*``): the descriptor table is uploaded once, and ``run()``
+    enqueues only the kernels (or replays a captured HIP graph)."""
+
+    def __init__(self, kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
+                 contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stats=None, graph=False):
+        xs = list(xs)
+        self.device = xs[0].device
+        self._keep = (xs, list(outs), None if outs2 is None else list(outs2), stats)
+        arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
+        p = _params(beta_r, beta_k)
+        tm = DcTmParams(eps, contrast, sigma_floor) if kind == PLAN_TONEMAP else None
+        self._h = ctypes.c_void_p()
+        _check(lib().dc_plan_create(context(self.device).handle, kind, arr, len(xs),
+                                    ctypes.byref(p), ctypes.byref(tm) if tm is not None else None,
+                                    ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                                    PLAN_GRAPH if graph else 0, ctypes.byref(self._h)))
+
+    def run(self, stream=None):
+        _check(lib().dc_plan_run(self._h, _stream_ptr(stream, self.device)))
+
+    def close(self):
+        if self._h:
+            lib().dc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def get_tuning(device=None):
+    t = DcTuning()
+    _check(lib().dc_get_tuning(context(device).handle, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(d, device=None):
+    t = DcTuning.from_dict(d)
+    _check(lib().dc_set_tuning(context(device).handle, ctypes.byref(t)))
+
+
+def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
+             contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stream=None):
+    """Runs the library's launch-shape search on these buffers and returns the
+    tuning it kept (a dict, see ``get_tuning``)."""
+    xs = list(xs)
+    dev = xs[0].device
+    arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
+    p = _params(beta_r, beta_k)
+    tm = DcTmParams(eps, contrast, sigma_floor)
+    t = DcTuning()
+    _check(lib().dc_autotune(context(dev).handle, kind, arr, len(xs), ctypes.byref(p),
+                             ctypes.byref(tm), _stream_ptr(stream, dev), ctypes.byref(t)))
+    return t.as_dict()
 
 
 def set_profiling(on, device=None):

@@ -10,7 +10,8 @@ namespace dc {
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kGroupBytes = 48;      // input bytes per vector group: 3 x 16 B
 constexpr int kStatsPxPerThread = 16; // pixels per thread in a statistics chunk
-constexpr int64_t kStatsChunkPx = (int64_t)kBlock * kStatsPxPerThread; // 4096
+constexpr int64_t kStatsChunkPx = (int64_t)kBlock * kStatsPxPerThread; // 4096 px per tile
+constexpr int kWavesPerBlock = kBlock / 64; // statistics partials per tone-map tile
 
 // Pixels per vector group for each input element type (48 B of RGB).
 __host__ __device__ constexpr int group_px(int src_dtype)
@@ -87,18 +88,18 @@ struct StatsOut {
 };
 
 // Kernel launchers (kernels.hip). All return the hipError_t of the launch.
-hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid,
-                                 hipStream_t s);
+hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, hipStream_t s);
 hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
-                                int64_t total_tiles, int mixed_src, int src_dtype,
-                                int groups, int64_t grid, hipStream_t s);
+                                int64_t total_tiles, int mixed_src, int src_dtype, int groups,
+                                int64_t grid, hipStream_t s);
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, Part *parts, hipStream_t s);
+                           int64_t total_tiles, TmArgs tm, Part *parts, int64_t grid,
+                           hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *tile_end,
                               TmArgs tm, const Part *parts, Curve *curves, StatsOut *stats,
                               hipStream_t s);
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, const Curve *curves,
+                           int64_t total_tiles, TmArgs tm, const Curve *curves, int64_t grid,
                            hipStream_t s);
 
 } // namespace dc

@@ -158,21 +158,28 @@ __device__ __forceinline__ void load_px(const uint8_t *p, float &R, float &G, fl
 
 // ------------------------------------------------------------ encode
 
-// Output encodings: f32 / f16 store v * fscale; u8 stores floor(v * u8scale +
-// 0.5) clamped to [0, 255] (the conversion instruction saturates; the explicit
-// min covers HDR values above 1).
-__device__ __forceinline__ unsigned u8_code(float v, float u8scale)
-{
-    return (unsigned)fminf(floorf(fmaf(v, u8scale, 0.5f)), 255.0f);
-}
+// Output encodings. F32 stores v (times fscale when SF); F16 stores the
+// round-to-nearest-even binary16 of the same; U8 stores v (times u8scale when
+// SU) converted by v_cvt_pk_u8_f32, which rounds to nearest with ties to even
+// and saturates to [0, 255] (NaN gives 0).
+struct Enc {
+    float fscale;
+    float u8scale;
+};
 
+template <bool SU>
 __device__ __forceinline__ unsigned pack_u8x4(float a, float b, float c, float d, float s)
 {
-    unsigned w = __builtin_amdgcn_cvt_pk_u8_f32(fminf(floorf(fmaf(a, s, 0.5f)), 255.0f), 0, 0u);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(fminf(floorf(fmaf(b, s, 0.5f)), 255.0f), 1, w);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(fminf(floorf(fmaf(c, s, 0.5f)), 255.0f), 2, w);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(fminf(floorf(fmaf(d, s, 0.5f)), 255.0f), 3, w);
-    return w;
+    if constexpr (SU) {
+        a *= s;
+        b *= s;
+        c *= s;
+        d *= s;
+    }
+    unsigned w = __builtin_amdgcn_cvt_pk_u8_f32(a, 0, 0u);
+    w = __builtin_amdgcn_cvt_pk_u8_f32(b, 1, w);
+    w = __builtin_amdgcn_cvt_pk_u8_f32(c, 2, w);
+    return __builtin_amdgcn_cvt_pk_u8_f32(d, 3, w);
 }
 
 __device__ __forceinline__ unsigned pack_f16x2(float a, float b)
@@ -183,15 +190,15 @@ __device__ __forceinline__ unsigned pack_f16x2(float a, float b)
 }
 
 // Stores GPX consecutive values at pixel index px of a 1-channel row.
-template <int GPX>
+template <int GPX, bool SF, bool SU>
 __device__ __forceinline__ void store_group(uint8_t *base, int dtype, int64_t px,
-                                            const float (&v)[GPX], float fscale, float u8scale)
+                                            const float (&v)[GPX], Enc e)
 {
     if (dtype == 0) {
         unsigned w[GPX / 4];
 #pragma unroll
         for (int i = 0; i < GPX / 4; ++i)
-            w[i] = pack_u8x4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3], u8scale);
+            w[i] = pack_u8x4<SU>(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3], e.u8scale);
         uint8_t *p = base + px;
         if constexpr (GPX == 16)
             *gpw<u32x4>(p) = u32x4{w[0], w[1], w[2], w[3]};
@@ -203,38 +210,52 @@ __device__ __forceinline__ void store_group(uint8_t *base, int dtype, int64_t px
         unsigned w[GPX / 2];
 #pragma unroll
         for (int i = 0; i < GPX / 2; ++i)
-            w[i] = pack_f16x2(v[2 * i] * fscale, v[2 * i + 1] * fscale);
+            w[i] = SF ? pack_f16x2(v[2 * i] * e.fscale, v[2 * i + 1] * e.fscale)
+                      : pack_f16x2(v[2 * i], v[2 * i + 1]);
         uint8_t *p = base + 2 * px;
         if constexpr (GPX == 4) {
             *gpw<u32x2>(p) = u32x2{w[0], w[1]};
         } else {
 #pragma unroll
             for (int i = 0; i < GPX / 8; ++i)
-                gpw<u32x4>(p)[i] =
-                    u32x4{w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]};
+                gpw<u32x4>(p)[i] = u32x4{w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]};
         }
     } else {
         uint8_t *p = base + 4 * px;
 #pragma unroll
-        for (int i = 0; i < GPX / 4; ++i)
-            gpw<u32x4>(p)[i] =
-                u32x4{__builtin_bit_cast(unsigned, v[4 * i] * fscale),
-                      __builtin_bit_cast(unsigned, v[4 * i + 1] * fscale),
-                      __builtin_bit_cast(unsigned, v[4 * i + 2] * fscale),
-                      __builtin_bit_cast(unsigned, v[4 * i + 3] * fscale)};
+        for (int i = 0; i < GPX / 4; ++i) {
+            float a = v[4 * i], b = v[4 * i + 1], c = v[4 * i + 2], d = v[4 * i + 3];
+            if constexpr (SF) {
+                a *= e.fscale;
+                b *= e.fscale;
+                c *= e.fscale;
+                d *= e.fscale;
+            }
+            gpw<u32x4>(p)[i] = u32x4{__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                     __builtin_bit_cast(unsigned, c), __builtin_bit_cast(unsigned, d)};
+        }
     }
 }
 
-__device__ __forceinline__ void store_px(uint8_t *base, int dtype, int64_t px, float v,
-                                         float fscale, float u8scale)
+template <bool SF, bool SU>
+__device__ __forceinline__ void store_px(uint8_t *base, int dtype, int64_t px, float v, Enc e)
 {
     if (dtype == 0)
-        gpw<uint8_t>(base)[px] = (uint8_t)u8_code(v, u8scale);
+        gpw<uint8_t>(base)[px] = (uint8_t)__builtin_amdgcn_cvt_pk_u8_f32(SU ? v * e.u8scale : v, 0, 0u);
     else if (dtype == 1)
-        gpw<_Float16>(base)[px] = (_Float16)(v * fscale);
+        gpw<_Float16>(base)[px] = (_Float16)(SF ? v * e.fscale : v);
     else
-        gpw<float>(base)[px] = v * fscale;
+        gpw<float>(base)[px] = SF ? v * e.fscale : v;
 }
+
+// Encoding of Lhat from L (input units): 8-bit input carries L in code units,
+// so FP outputs scale by 1/255 and the 8-bit output takes L as is; float input
+// carries Lhat, so only the 8-bit output scales (by 255).
+template <int SRC>
+struct LumEnc {
+    static constexpr bool SF = SRC == 0;
+    static constexpr bool SU = SRC != 0;
+};
 
 // ------------------------------------------------------------ tile walk
 
@@ -261,9 +282,10 @@ __device__ __forceinline__ TileRef tile_ref(const DevImage &im, int64_t tile, in
 }
 
 // Luminance of all pixels a thread owns in one tile (G vector groups of GPX
-// pixels, or the same count of single pixels on the scalar walk). lv holds L
-// in input units; valid marks pixels inside the segment. Returns the pixel
-// index of slot 0 of each group through gpx0.
+// pixels, or the same count of single pixels on the per-pixel walk). lv holds L
+// in input units; valid marks pixels inside the segment. In both walks the
+// valid slots of a thread form a prefix, and slot 0 of lane 0 of a wave holds
+// the wave's first pixel.
 template <int SRC, int G>
 __device__ __forceinline__ void tile_lum(const DevImage &im, const TileRef &t, Coef k,
                                          float (&lv)[G * group_px(SRC)],
@@ -321,12 +343,10 @@ __device__ __forceinline__ void tile_lum(const DevImage &im, const TileRef &t, C
     }
 }
 
-// Writes per-pixel values v (G*GPX of them, laid out as tile_lum produced
-// them) to one output.
-template <int SRC, int G>
+// Writes per-pixel values v (laid out as tile_lum produced them) to one output.
+template <int SRC, int G, bool SF, bool SU>
 __device__ __forceinline__ void tile_store(const DevImage &im, const TileRef &t, uint8_t *out,
-                                           int dtype, const float (&v)[G * group_px(SRC)],
-                                           float fscale, float u8scale)
+                                           int dtype, const float (&v)[G * group_px(SRC)], Enc e)
 {
     constexpr int GPX = group_px(SRC);
     const int tid = threadIdx.x;
@@ -339,12 +359,12 @@ __device__ __forceinline__ void tile_store(const DevImage &im, const TileRef &t,
 #pragma unroll
                 for (int i = 0; i < GPX; ++i)
                     vv[i] = v[g * GPX + i];
-                store_group<GPX>(out, dtype, gp, vv, fscale, u8scale);
+                store_group<GPX, SF, SU>(out, dtype, gp, vv, e);
             } else {
 #pragma unroll
                 for (int i = 0; i < GPX; ++i)
                     if (gp + i < t.n)
-                        store_px(out, dtype, gp + i, v[g * GPX + i], fscale, u8scale);
+                        store_px<SF, SU>(out, dtype, gp + i, v[g * GPX + i], e);
             }
         }
     } else {
@@ -352,8 +372,35 @@ __device__ __forceinline__ void tile_store(const DevImage &im, const TileRef &t,
         for (int j = 0; j < G * GPX; ++j) {
             const int64_t p = t.px0 + (int64_t)j * kBlock + tid;
             if (p < t.n)
-                store_px(out, dtype, p, v[j], fscale, u8scale);
+                store_px<SF, SU>(out, dtype, p, v[j], e);
         }
+    }
+}
+
+// Visits the global tiles of a persistent block (blockIdx.x, blockIdx.x +
+// gridDim.x, ...) with the index of the image that owns each. tile_end is the
+// inclusive prefix sum of the images' tile counts; tiles only grow, so the
+// owner is found once by binary search and then advanced in place.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(const int64_t *__restrict__ tile_end, int nimg,
+                                              int64_t total_tiles, F &&f)
+{
+    int64_t tile = blockIdx.x;
+    if (tile >= total_tiles)
+        return;
+    int lo = 0, hi = nimg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_end[mid] > tile)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    int i = lo;
+    for (; tile < total_tiles; tile += gridDim.x) {
+        while (tile_end[i] <= tile)
+            ++i;
+        f(i, tile);
     }
 }
 
@@ -373,12 +420,14 @@ __device__ __forceinline__ void group_lum(const unsigned (&w)[12], Coef k,
 // first, then each group is evaluated and stored while later loads are still
 // in flight.
 template <int SRC, int G>
-__device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile, Coef k)
+__device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile)
 {
     constexpr int GPX = group_px(SRC);
     constexpr int ES = elem_size(SRC);
+    constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
     const TileRef t = tile_ref(im, tile, (int64_t)kBlock * G * GPX);
-    const float u8s = 255.0f * im.unit;
+    const Enc e{im.unit, 255.0f};
+    const Coef k = im.k;
     const int tid = threadIdx.x;
     if (im.walk != kWalkScalar) {
         unsigned w[G][12];
@@ -396,17 +445,17 @@ __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile, C
             if (full[g]) {
                 float v[GPX];
                 group_lum<SRC>(w[g], k, v);
-                store_group<GPX>(t.dst, im.dst_dtype, gp, v, im.unit, u8s);
+                store_group<GPX, SF, SU>(t.dst, im.dst_dtype, gp, v, e);
                 if (t.dst2)
-                    store_group<GPX>(t.dst2, im.dst2_dtype, gp, v, im.unit, u8s);
+                    store_group<GPX, SF, SU>(t.dst2, im.dst2_dtype, gp, v, e);
             } else {
                 for (int64_t p = gp; p < t.n && p < gp + GPX; ++p) {
                     float R, G_, B;
                     load_px<SRC>(t.src + p * 3 * ES, R, G_, B);
                     const float v = lum<SRC>(R, G_, B, k);
-                    store_px(t.dst, im.dst_dtype, p, v, im.unit, u8s);
+                    store_px<SF, SU>(t.dst, im.dst_dtype, p, v, e);
                     if (t.dst2)
-                        store_px(t.dst2, im.dst2_dtype, p, v, im.unit, u8s);
+                        store_px<SF, SU>(t.dst2, im.dst2_dtype, p, v, e);
                 }
             }
         }
@@ -417,9 +466,9 @@ __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile, C
                 float R, G_, B;
                 load_px<SRC>(t.src + p * 3 * ES, R, G_, B);
                 const float v = lum<SRC>(R, G_, B, k);
-                store_px(t.dst, im.dst_dtype, p, v, im.unit, u8s);
+                store_px<SF, SU>(t.dst, im.dst_dtype, p, v, e);
                 if (t.dst2)
-                    store_px(t.dst2, im.dst2_dtype, p, v, im.unit, u8s);
+                    store_px<SF, SU>(t.dst2, im.dst2_dtype, p, v, e);
             }
         }
     }
@@ -429,22 +478,7 @@ template <int SRC, int G>
 __global__ __launch_bounds__(kBlock) void k_decolor_single(DevImage im, int64_t ntiles)
 {
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        decolor_tile<SRC, G>(im, tile, im.k);
-}
-
-// Index of the image owning global tile `tile`: the first i with
-// tile_end[i] > tile (tile_end is the inclusive prefix sum of tile counts).
-__device__ __forceinline__ int find_image(const int64_t *tile_end, int nimg, int64_t tile)
-{
-    int lo = 0, hi = nimg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (tile_end[mid] > tile)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
+        decolor_tile<SRC, G>(im, tile);
 }
 
 // One launch over the tiles of many images. MIXED = the input element type
@@ -454,22 +488,21 @@ __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__rest
                                                           const int64_t *__restrict__ tile_end,
                                                           int nimg, int64_t total_tiles)
 {
-    for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-        const int i = find_image(tile_end, nimg, tile);
+    for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
             // Tile sizes are per image: G groups of its own group width.
             if (im.src_dtype == 0)
-                decolor_tile<0, G>(im, lt, im.k);
+                decolor_tile<0, G>(im, lt);
             else if (im.src_dtype == 1)
-                decolor_tile<1, G>(im, lt, im.k);
+                decolor_tile<1, G>(im, lt);
             else
-                decolor_tile<2, G>(im, lt, im.k);
+                decolor_tile<2, G>(im, lt);
         } else {
-            decolor_tile<SRC, G>(im, lt, im.k);
+            decolor_tile<SRC, G>(im, lt);
         }
-    }
+    });
 }
 
 // ------------------------------------------------------------ tone map
@@ -498,68 +531,103 @@ __device__ __forceinline__ Part merge(const Part &a, const Part &b)
     return r;
 }
 
-// Statistics pass: one tile = one fixed chunk of kStatsChunkPx pixels (16 per
-// thread), so the partials, and the statistics merged from them in a fixed
-// order, depend only on the image, never on the other images of the call.
+// x2 = log2(Lhat + eps) from L in input units. Both passes use this one
+// expression, so a pixel gets the same x2 in the statistics and in the curve.
+__device__ __forceinline__ float xlog2(float l, float unit, float eps)
+{
+    return hw_log2(fmaf(l, unit, eps));
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Statistics pass over one tile of kStatsChunkPx pixels (16 per thread). Each
+// wave reduces its 1024 pixels to one partial with no workgroup barrier: sums
+// of d = x2 - K and d^2, shifted by K = x2 of the wave's first pixel (so a
+// flat image gives exactly mean = K, M2 = 0), count and the extremes of L.
+// Chunks are fixed slices of each image, so the partials, and the statistics
+// merged from them in a fixed order, never depend on the other images of the
+// call or on the launch shape.
 template <int SRC>
-__device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, Coef k,
-                                              TmArgs tm, Part *parts, Part *sh)
+__device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
+                                              Part *__restrict__ parts)
 {
     constexpr int G = kStatsPxPerThread / group_px(SRC);
     constexpr int NV = kStatsPxPerThread;
     const TileRef t = tile_ref(im, tile, kStatsChunkPx);
     float lv[NV];
     bool valid[NV];
-    tile_lum<SRC, G>(im, t, k, lv, valid);
+    tile_lum<SRC, G>(im, t, im.k, lv, valid);
     if (t.dst2)
-        tile_store<SRC, G>(im, t, t.dst2, im.dst2_dtype, lv, im.unit, 255.0f * im.unit);
-
-    // Per-thread exact two-pass statistics over its own pixels (in registers).
+        tile_store<SRC, G, LumEnc<SRC>::SF, LumEnc<SRC>::SU>(im, t, t.dst2, im.dst2_dtype, lv,
+                                                            Enc{im.unit, 255.0f});
     float x[NV];
-    float cnt = 0.0f, sum = 0.0f, lo = __builtin_inff(), hi = -__builtin_inff();
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const float lh = lv[i] * im.unit;
-        x[i] = hw_log2(lh + tm.eps);
-        if (valid[i]) {
-            cnt += 1.0f;
-            sum += x[i];
-            lo = fminf(lo, lh);
-            hi = fmaxf(hi, lh);
-        }
-    }
-    Part p = part_empty();
-    if (cnt > 0.0f) {
-        const float mean = sum / cnt;
-        float m2 = 0.0f;
+    for (int i = 0; i < NV; ++i)
+        x[i] = xlog2(lv[i], im.unit, tm.eps);
+    const float K = __builtin_bit_cast(
+        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x[0])));
+    float s = 0.0f, q = 0.0f, lo = lv[0], hi = lv[0];
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+        cnt += valid[i] ? 1 : 0;
+    if (cnt == NV) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const float d = x[i] - mean;
-            m2 = valid[i] ? fmaf(d, d, m2) : m2;
+            const float d = x[i] - K;
+            s += d;
+            q = fmaf(d, d, q);
+            lo = fminf(lo, lv[i]);
+            hi = fmaxf(hi, lv[i]);
         }
-        p = Part{cnt, mean, m2, lo, hi};
-    }
-    const int tid = threadIdx.x;
-    sh[tid] = p;
-    __syncthreads();
-    if (tid < 64) {
-        // Wave 0: each lane folds four consecutive thread partials, then a
-        // fixed butterfly over the 64 lanes.
-        Part a = merge(merge(sh[4 * tid], sh[4 * tid + 1]), merge(sh[4 * tid + 2], sh[4 * tid + 3]));
+    } else if (cnt > 0) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            Part b;
-            b.n = __shfl_down(a.n, off, 64);
-            b.mean = __shfl_down(a.mean, off, 64);
-            b.m2 = __shfl_down(a.m2, off, 64);
-            b.lo = __shfl_down(a.lo, off, 64);
-            b.hi = __shfl_down(a.hi, off, 64);
-            a = merge(a, b);
+        for (int i = 0; i < NV; ++i) {
+            const float d = valid[i] ? x[i] - K : 0.0f;
+            const float l = valid[i] ? lv[i] : lv[0];
+            s += d;
+            q = fmaf(d, d, q);
+            lo = fminf(lo, l);
+            hi = fmaxf(hi, l);
         }
-        if (tid == 0)
-            parts[im.chunk_begin + tile] = a;
+    } else {
+        lo = __builtin_inff();
+        hi = -__builtin_inff();
     }
-    __syncthreads();
+    s = wave_sum(s);
+    q = wave_sum(q);
+    const float n = wave_sum((float)cnt);
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+        Part p = part_empty();
+        if (n > 0.0f) {
+            const float m = s / n;
+            p = Part{n, K + m, fmaxf(fmaf(-s, m, q), 0.0f), lo * im.unit, hi * im.unit};
+        }
+        parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] = p;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict__ table,
@@ -567,18 +635,16 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict_
                                                      int nimg, int64_t total_tiles, TmArgs tm,
                                                      Part *__restrict__ parts)
 {
-    __shared__ Part sh[kBlock];
-    for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-        const int i = find_image(tile_end, nimg, tile);
+    for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
         if (im.src_dtype == 0)
-            tm_pass1_tile<0>(im, lt, im.k, tm, parts, sh);
+            tm_pass1_tile<0>(im, lt, tm, parts);
         else if (im.src_dtype == 1)
-            tm_pass1_tile<1>(im, lt, im.k, tm, parts, sh);
+            tm_pass1_tile<1>(im, lt, tm, parts);
         else
-            tm_pass1_tile<2>(im, lt, im.k, tm, parts, sh);
-    }
+            tm_pass1_tile<2>(im, lt, tm, parts);
+    });
 }
 
 // One workgroup per image: fixed-order merge of the image's chunk partials,
@@ -592,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restri
     __shared__ Part sh[kBlock];
     const int img = blockIdx.x;
     const DevImage im = table[img];
-    const int64_t nch = tile_end[img] - im.tile_begin;
+    const int64_t nch = (tile_end[img] - im.tile_begin) * kWavesPerBlock;
     const int tid = threadIdx.x;
     Part a = part_empty();
     for (int64_t c = tid; c < nch; c += kBlock)
@@ -625,21 +691,18 @@ __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restri
 }
 
 template <int SRC>
-__device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, Coef k,
-                                              TmArgs tm, Curve cv)
+__device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, TmArgs tm, Curve cv)
 {
     constexpr int G = kStatsPxPerThread / group_px(SRC);
     constexpr int NV = kStatsPxPerThread;
     const TileRef t = tile_ref(im, tile, kStatsChunkPx);
     float lv[NV];
     bool valid[NV];
-    tile_lum<SRC, G>(im, t, k, lv, valid);
+    tile_lum<SRC, G>(im, t, im.k, lv, valid);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const float x2 = hw_log2(fmaf(lv[i], im.unit, tm.eps));
-        lv[i] = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
-    }
-    tile_store<SRC, G>(im, t, t.dst, im.dst_dtype, lv, 1.0f, 255.0f);
+    for (int i = 0; i < NV; ++i)
+        lv[i] = hw_rcp(1.0f + hw_exp2(cv.a * (xlog2(lv[i], im.unit, tm.eps) - cv.mu2)));
+    tile_store<SRC, G, false, true>(im, t, t.dst, im.dst_dtype, lv, Enc{1.0f, 255.0f});
 }
 
 __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict__ table,
@@ -647,18 +710,17 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
                                                      int nimg, int64_t total_tiles, TmArgs tm,
                                                      const Curve *__restrict__ curves)
 {
-    for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-        const int i = find_image(tile_end, nimg, tile);
+    for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const Curve cv = curves[i];
         const int64_t lt = tile - im.tile_begin;
         if (im.src_dtype == 0)
-            tm_pass2_tile<0>(im, lt, im.k, tm, cv);
+            tm_pass2_tile<0>(im, lt, tm, cv);
         else if (im.src_dtype == 1)
-            tm_pass2_tile<1>(im, lt, im.k, tm, cv);
+            tm_pass2_tile<1>(im, lt, tm, cv);
         else
-            tm_pass2_tile<2>(im, lt, im.k, tm, cv);
-    }
+            tm_pass2_tile<2>(im, lt, tm, cv);
+    });
 }
 
 // ------------------------------------------------------------ launchers
@@ -671,8 +733,7 @@ static unsigned grid_of(int64_t ntiles, int64_t grid)
     return (unsigned)(g > 0 ? g : 1);
 }
 
-hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid,
-                                 hipStream_t s)
+hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, hipStream_t s)
 {
     const int64_t ntiles = im.ntiles;
     const unsigned g = grid_of(ntiles, grid);
@@ -695,8 +756,8 @@ hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid,
 }
 
 hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
-                                int64_t total_tiles, int mixed_src, int src_dtype,
-                                int groups, int64_t grid, hipStream_t s)
+                                int64_t total_tiles, int mixed_src, int src_dtype, int groups,
+                                int64_t grid, hipStream_t s)
 {
     const unsigned g = grid_of(total_tiles, grid);
 #define DC_LAUNCH_TABLE(S, GG, M)                                                                 \
@@ -728,9 +789,9 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
 }
 
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, Part *parts, hipStream_t s)
+                           int64_t total_tiles, TmArgs tm, Part *parts, int64_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tm_pass1, dim3(grid_of(total_tiles, 0)), dim3(kBlock), 0, s, table,
+    hipLaunchKernelGGL(k_tm_pass1, dim3(grid_of(total_tiles, grid)), dim3(kBlock), 0, s, table,
                        tile_end, nimg, total_tiles, tm, parts);
     return hipGetLastError();
 }
@@ -745,10 +806,10 @@ hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *ti
 }
 
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, const Curve *curves,
+                           int64_t total_tiles, TmArgs tm, const Curve *curves, int64_t grid,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tm_pass2, dim3(grid_of(total_tiles, 0)), dim3(kBlock), 0, s, table,
+    hipLaunchKernelGGL(k_tm_pass2, dim3(grid_of(total_tiles, grid)), dim3(kBlock), 0, s, table,
                        tile_end, nimg, total_tiles, tm, curves);
     return hipGetLastError();
 }

@@ -215,15 +215,20 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
     return d;
 }
 
-int env_int(const char *name, int dflt)
-{
-    const char *v = std::getenv(name);
-    return v && *v ? std::atoi(v) : dflt;
-}
-
 } // namespace
 
 // ------------------------------------------------------------------ context
+
+// Launch shapes. groups = vector groups per thread in a decolorization tile
+// (per input type, and one value for batches that mix input types); *_gpc =
+// persistent workgroups per compute unit (0 = one workgroup per tile).
+struct Tune {
+    int groups[3] = {2, 2, 2};
+    int mixed_groups = 2;
+    int decolor_gpc = 0;
+    int pass1_gpc = 0;
+    int pass2_gpc = 0;
+};
 
 struct dc_ctx {
     static constexpr int kSlots = 8;
@@ -237,8 +242,7 @@ struct dc_ctx {
     };
     int device = 0;
     int num_cu = 256;
-    int groups = 2;  // vector groups per thread per decolorization tile
-    int64_t grid = 0; // 0 = one workgroup per tile
+    Tune tune;
     Slot slots[kSlots];
     int next = 0;
     // Measurement hooks: timing events recorded around each kernel.
@@ -249,6 +253,148 @@ struct dc_ctx {
 };
 
 namespace {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Records timing event i on the stream when profiling is on.
+void mark(dc_ctx *ctx, bool on, int i, hipStream_t s)
+{
+    if (!on || !ctx->profiling || i >= dc_ctx::kMaxEvents)
+        return;
+    if (i == 0)
+        ctx->prof_used = 0;
+    if (hipEventRecord(ctx->prof[i], s) == hipSuccess)
+        ctx->prof_used = i + 1;
+}
+
+int ensure_prof_events(dc_ctx *ctx)
+{
+    if (ctx->prof[0])
+        return DC_OK;
+    for (auto &e : ctx->prof) {
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess)
+            return fail(DC_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
+    }
+    return DC_OK;
+}
+
+int64_t grid_blocks(const dc_ctx *ctx, int gpc) { return gpc > 0 ? (int64_t)gpc * ctx->num_cu : 0; }
+
+// Host image of a launch: descriptors, tile prefix and the launch shape that
+// the tile sizes were built for.
+struct HostTable {
+    std::vector<dc::DevImage> d;
+    std::vector<int64_t> tile_end;
+    int64_t total_tiles = 0;
+    bool mixed = false;
+    int src0 = 0;
+    int groups = 2;  // decolorization only
+    bool tonemap = false;
+};
+
+void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool tonemap,
+                 const Tune &tune, HostTable &h)
+{
+    h.d.resize((size_t)n);
+    h.tile_end.resize((size_t)n);
+    h.tonemap = tonemap;
+    h.src0 = n > 0 ? imgs[0].src_dtype : 0;
+    h.mixed = false;
+    for (int32_t i = 0; i < n; ++i)
+        h.mixed |= imgs[i].src_dtype != h.src0;
+    h.groups = h.mixed ? tune.mixed_groups : tune.groups[h.src0];
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t tile_px =
+            tonemap ? dc::kStatsChunkPx : (int64_t)dc::kBlock * h.groups * dc::group_px(imgs[i].src_dtype);
+        h.d[i] = describe(imgs[i], i, tile_px, params);
+        h.d[i].tile_begin = total;
+        h.d[i].chunk_begin = total * dc::kWavesPerBlock; // tone map: one partial per wave
+        total += h.d[i].ntiles;
+        h.tile_end[i] = total;
+    }
+    h.total_tiles = total;
+}
+
+// Byte layout of the device copy: table | tile ends | partials | curves.
+struct Layout {
+    size_t table, ends, parts, curves, upload, total;
+};
+
+Layout layout_of(const HostTable &h)
+{
+    const size_t n = h.d.size();
+    Layout l;
+    l.table = 0;
+    l.ends = align_up(sizeof(dc::DevImage) * n, 256);
+    l.parts = l.ends + align_up(sizeof(int64_t) * n, 256);
+    l.upload = l.parts;
+    l.curves = l.parts + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_tiles *
+                                                   dc::kWavesPerBlock, 256) : 0);
+    l.total = l.curves + (h.tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0);
+    return l;
+}
+
+void write_upload(const HostTable &h, const Layout &l, char *dst)
+{
+    std::memcpy(dst + l.table, h.d.data(), sizeof(dc::DevImage) * h.d.size());
+    std::memcpy(dst + l.ends, h.tile_end.data(), sizeof(int64_t) * h.tile_end.size());
+}
+
+struct DevBufs {
+    const dc::DevImage *table;
+    const int64_t *tile_end;
+    dc::Part *parts;
+    dc::Curve *curves;
+};
+
+DevBufs bufs_of(void *dev, const Layout &l)
+{
+    char *p = (char *)dev;
+    return DevBufs{(const dc::DevImage *)(p + l.table), (const int64_t *)(p + l.ends),
+                   (dc::Part *)(p + l.parts), (dc::Curve *)(p + l.curves)};
+}
+
+// Kernel sequence of a decolorization launch over a staged table.
+int enqueue_decolor(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tune &t,
+                    hipStream_t st, bool marks)
+{
+    mark(ctx, marks, 0, st);
+    hipError_t e = dc::launch_decolor_table(b.table, b.tile_end, (int)h.d.size(), h.total_tiles,
+                                            h.mixed, h.src0, h.groups,
+                                            grid_blocks(ctx, t.decolor_gpc), st);
+    if (e != hipSuccess)
+        return hip_fail(e, "decolorize launch");
+    mark(ctx, marks, 1, st);
+    return DC_OK;
+}
+
+// Kernel sequence of a tone map over a staged table.
+int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tune &t,
+                    dc::TmArgs a, dc::StatsOut *stats, hipStream_t st, bool marks)
+{
+    const int n = (int)h.d.size();
+    mark(ctx, marks, 0, st);
+    hipError_t e = dc::launch_tm_pass1(b.table, b.tile_end, n, h.total_tiles, a, b.parts,
+                                       grid_blocks(ctx, t.pass1_gpc), st);
+    mark(ctx, marks, 1, st);
+    if (e == hipSuccess)
+        e = dc::launch_tm_finalize(b.table, n, b.tile_end, a, b.parts, b.curves, stats, st);
+    mark(ctx, marks, 2, st);
+    if (e == hipSuccess)
+        e = dc::launch_tm_pass2(b.table, b.tile_end, n, h.total_tiles, a, b.curves,
+                                grid_blocks(ctx, t.pass2_gpc), st);
+    mark(ctx, marks, 3, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "tonemap launch");
+    return DC_OK;
+}
 
 // Takes the next workspace slot, waiting for the work that last used it, and
 // makes sure it can hold host_bytes of staging and dev_bytes on the device.
@@ -293,73 +439,18 @@ int release_slot(dc_ctx::Slot *s, hipStream_t stream)
     return DC_OK;
 }
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-// Records timing event i on the stream when profiling is on.
-void mark(dc_ctx *ctx, int i, hipStream_t s)
+// Stages a table in the next ring slot and copies it to the device on `st`.
+int stage(dc_ctx *ctx, const HostTable &h, hipStream_t st, dc_ctx::Slot **slot, DevBufs *b)
 {
-    if (!ctx->profiling || i >= dc_ctx::kMaxEvents)
-        return;
-    if (hipEventRecord(ctx->prof[i], s) == hipSuccess)
-        ctx->prof_used = i + 1;
-}
-
-int hip_fail(hipError_t e, const char *what)
-{
-    return fail(DC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-// Builds the descriptor table and inclusive tile-end prefix for n images in
-// the slot's staging buffer, copies it to the device, and returns the device
-// addresses of both.
-struct Table {
-    dc::DevImage *table;
-    int64_t *tile_end;
-    dc::Part *parts;
-    dc::Curve *curves;
-    int64_t total_tiles;
-    bool mixed;
-};
-
-int stage_table(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
-                bool tonemap, int groups, hipStream_t stream, dc_ctx::Slot **slot_out, Table *t)
-{
-    std::vector<dc::DevImage> d((size_t)n);
-    int64_t total = 0;
-    bool mixed = false;
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t tile_px = tonemap ? dc::kStatsChunkPx
-                                        : (int64_t)dc::kBlock * groups * dc::group_px(imgs[i].src_dtype);
-        d[i] = describe(imgs[i], i, tile_px, params);
-        d[i].tile_begin = total;
-        d[i].chunk_begin = total; // one statistics partial per tile on the tone-map path
-        total += d[i].ntiles;
-        mixed |= imgs[i].src_dtype != imgs[0].src_dtype;
-    }
-    const size_t tbl = align_up(sizeof(dc::DevImage) * n, 256);
-    const size_t ends = align_up(sizeof(int64_t) * n, 256);
-    const size_t parts = tonemap ? align_up(sizeof(dc::Part) * (size_t)total, 256) : 0;
-    const size_t curves = tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0;
-    dc_ctx::Slot *s = nullptr;
-    int rc = acquire_slot(ctx, tbl + ends, tbl + ends + parts + curves, &s);
+    const Layout l = layout_of(h);
+    int rc = acquire_slot(ctx, l.upload, l.total, slot);
     if (rc != DC_OK)
         return rc;
-    char *h = (char *)s->host;
-    std::memcpy(h, d.data(), sizeof(dc::DevImage) * n);
-    int64_t *he = (int64_t *)(h + tbl);
-    for (int32_t i = 0; i < n; ++i)
-        he[i] = d[i].tile_begin + d[i].ntiles;
-    hipError_t e = hipMemcpyAsync(s->dev, s->host, tbl + ends, hipMemcpyHostToDevice, stream);
+    write_upload(h, l, (char *)(*slot)->host);
+    hipError_t e = hipMemcpyAsync((*slot)->dev, (*slot)->host, l.upload, hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return hip_fail(e, "descriptor upload");
-    char *dv = (char *)s->dev;
-    t->table = (dc::DevImage *)dv;
-    t->tile_end = (int64_t *)(dv + tbl);
-    t->parts = tonemap ? (dc::Part *)(dv + tbl + ends) : nullptr;
-    t->curves = tonemap ? (dc::Curve *)(dv + tbl + ends + parts) : nullptr;
-    t->total_tiles = total;
-    t->mixed = mixed;
-    *slot_out = s;
+    *b = bufs_of((*slot)->dev, l);
     return DC_OK;
 }
 
@@ -370,6 +461,146 @@ int check_ctx(dc_ctx *ctx)
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
+    return DC_OK;
+}
+
+bool tune_ok(const dc_tuning &t)
+{
+    auto g_ok = [](int g) { return g == 1 || g == 2 || g == 4; };
+    auto c_ok = [](int c) { return c >= 0 && c <= 64; };
+    return g_ok(t.groups[0]) && g_ok(t.groups[1]) && g_ok(t.groups[2]) && g_ok(t.mixed_groups) &&
+           c_ok(t.decolor_grid_per_cu) && c_ok(t.pass1_grid_per_cu) && c_ok(t.pass2_grid_per_cu);
+}
+
+dc_tuning to_public(const Tune &t)
+{
+    dc_tuning o;
+    for (int i = 0; i < 3; ++i)
+        o.groups[i] = t.groups[i];
+    o.mixed_groups = t.mixed_groups;
+    o.decolor_grid_per_cu = t.decolor_gpc;
+    o.pass1_grid_per_cu = t.pass1_gpc;
+    o.pass2_grid_per_cu = t.pass2_gpc;
+    return o;
+}
+
+Tune from_public(const dc_tuning &o)
+{
+    Tune t;
+    for (int i = 0; i < 3; ++i)
+        t.groups[i] = o.groups[i];
+    t.mixed_groups = o.mixed_groups;
+    t.decolor_gpc = o.decolor_grid_per_cu;
+    t.pass1_gpc = o.pass1_grid_per_cu;
+    t.pass2_gpc = o.pass2_grid_per_cu;
+    return t;
+}
+
+} // namespace
+
+// ------------------------------------------------------------------ plans
+
+struct dc_plan {
+    dc_ctx *ctx = nullptr;
+    int32_t kind = DC_PLAN_DECOLORIZE;
+    HostTable h;
+    Tune tune;
+    void *dev = nullptr;
+    DevBufs b{};
+    dc::TmArgs tm{};
+    dc::StatsOut *stats = nullptr;
+    bool graph = false;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int plan_enqueue(dc_plan *p, hipStream_t st, bool marks)
+{
+    if (p->kind == DC_PLAN_TONEMAP)
+        return enqueue_tonemap(p->ctx, p->h, p->b, p->tune, p->tm, p->stats, st, marks);
+    return enqueue_decolor(p->ctx, p->h, p->b, p->tune, st, marks);
+}
+
+void plan_free(dc_plan *p)
+{
+    if (!p)
+        return;
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->dev)
+        (void)hipFree(p->dev);
+    delete p;
+}
+
+// Builds a plan with a given launch shape (used by dc_plan_create and the tuner).
+int plan_build(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n, const dc_params *params,
+               const dc_tm_params *tm, dc_stats *stats, int32_t flags, const Tune &tune,
+               dc_plan **out)
+{
+    dc_plan *p = new (std::nothrow) dc_plan();
+    if (!p)
+        return fail(DC_ERR_NO_MEMORY, "plan allocation failed");
+    p->ctx = ctx;
+    p->kind = kind;
+    p->tune = tune;
+    p->tm = tm_of(tm);
+    p->stats = (dc::StatsOut *)stats;
+    p->graph = (flags & DC_PLAN_GRAPH) != 0;
+    build_table(imgs, n, params, kind == DC_PLAN_TONEMAP, tune, p->h);
+    const Layout l = layout_of(p->h);
+    std::vector<char> up(l.upload);
+    write_upload(p->h, l, up.data());
+    hipError_t e = hipMalloc(&p->dev, l.total);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return fail(DC_ERR_NO_MEMORY, "plan workspace allocation failed");
+    }
+    e = hipMemcpy(p->dev, up.data(), l.upload, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "plan upload");
+    }
+    p->b = bufs_of(p->dev, l);
+    *out = p;
+    return DC_OK;
+}
+
+// Median over reps of the summed duration of event intervals [first, last).
+int time_plan(dc_plan *p, hipStream_t st, int reps, std::vector<float> *per_interval)
+{
+    dc_ctx *ctx = p->ctx;
+    const int ev = ensure_prof_events(ctx);
+    if (ev != DC_OK)
+        return ev;
+    const bool was = ctx->profiling;
+    ctx->profiling = true;
+    const int nint = p->kind == DC_PLAN_TONEMAP ? 3 : 1;
+    std::vector<std::vector<float>> samples(nint);
+    for (int r = 0; r < reps + 1; ++r) {
+        int rc = plan_enqueue(p, st, true);
+        if (rc != DC_OK) {
+            ctx->profiling = was;
+            return rc;
+        }
+        if (hipEventSynchronize(ctx->prof[nint]) != hipSuccess) {
+            ctx->profiling = was;
+            return fail(DC_ERR_HIP, "tuner timing failed");
+        }
+        if (r == 0)
+            continue; // warm-up
+        for (int i = 0; i < nint; ++i) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ctx->prof[i], ctx->prof[i + 1]);
+            samples[i].push_back(ms);
+        }
+    }
+    ctx->profiling = was;
+    per_interval->assign(nint, 0.0f);
+    for (int i = 0; i < nint; ++i) {
+        std::sort(samples[i].begin(), samples[i].end());
+        (*per_interval)[i] = samples[i][samples[i].size() / 2];
+    }
     return DC_OK;
 }
 
@@ -430,10 +661,6 @@ int dc_create(dc_ctx **out, int device)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         cus > 0)
         ctx->num_cu = cus;
-    ctx->groups = env_int("DC_GROUPS", 2);
-    if (ctx->groups != 1 && ctx->groups != 2 && ctx->groups != 4)
-        ctx->groups = 2;
-    ctx->grid = env_int("DC_GRID", 0);
     for (auto &s : ctx->slots) {
         e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -445,18 +672,57 @@ int dc_create(dc_ctx **out, int device)
     return DC_OK;
 }
 
+int dc_destroy(dc_ctx *ctx)
+{
+    if (!ctx)
+        return DC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &s : ctx->slots) {
+        if (s.host)
+            (void)hipHostFree(s.host);
+        if (s.dev)
+            (void)hipFree(s.dev);
+        if (s.done)
+            (void)hipEventDestroy(s.done);
+    }
+    for (auto &e : ctx->prof)
+        if (e)
+            (void)hipEventDestroy(e);
+    delete ctx;
+    return DC_OK;
+}
+
+int dc_get_tuning(dc_ctx *ctx, dc_tuning *out)
+{
+    g_last_error.clear();
+    if (!ctx || !out)
+        return fail(DC_ERR_INVALID_ARG, "context or output is NULL");
+    *out = to_public(ctx->tune);
+    return DC_OK;
+}
+
+int dc_set_tuning(dc_ctx *ctx, const dc_tuning *t)
+{
+    g_last_error.clear();
+    if (!ctx || !t)
+        return fail(DC_ERR_INVALID_ARG, "context or tuning is NULL");
+    if (!tune_ok(*t))
+        return fail(DC_ERR_INVALID_ARG, "groups must be 1, 2 or 4 and grids per CU in [0, 64]");
+    ctx->tune = from_public(*t);
+    return DC_OK;
+}
+
 int dc_set_profiling(dc_ctx *ctx, int on)
 {
     g_last_error.clear();
     if (!ctx)
         return fail(DC_ERR_INVALID_ARG, "context is NULL");
-    if (on && !ctx->prof[0]) {
+    if (on) {
         (void)hipSetDevice(ctx->device);
-        for (auto &e : ctx->prof) {
-            hipError_t err = hipEventCreate(&e);
-            if (err != hipSuccess)
-                return hip_fail(err, "hipEventCreate");
-        }
+        const int rc = ensure_prof_events(ctx);
+        if (rc != DC_OK)
+            return rc;
     }
     ctx->profiling = on != 0;
     ctx->prof_used = 0;
@@ -482,27 +748,6 @@ int dc_last_timings(dc_ctx *ctx, float *ms, int32_t cap)
     return n;
 }
 
-int dc_destroy(dc_ctx *ctx)
-{
-    if (!ctx)
-        return DC_OK;
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    for (auto &s : ctx->slots) {
-        if (s.host)
-            (void)hipHostFree(s.host);
-        if (s.dev)
-            (void)hipFree(s.dev);
-        if (s.done)
-            (void)hipEventDestroy(s.done);
-    }
-    for (auto &e : ctx->prof)
-        if (e)
-            (void)hipEventDestroy(e);
-    delete ctx;
-    return DC_OK;
-}
-
 int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, void *stream)
 {
     g_last_error.clear();
@@ -514,15 +759,15 @@ int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, voi
     rc = dc_validate(img, 1, params, nullptr);
     if (rc != DC_OK)
         return rc;
-    const int g = ctx->groups;
+    const int g = ctx->tune.groups[img->src_dtype];
     const dc::DevImage d =
         describe(*img, 0, (int64_t)dc::kBlock * g * dc::group_px(img->src_dtype), params);
-    ctx->prof_used = 0;
-    mark(ctx, 0, (hipStream_t)stream);
-    hipError_t e = dc::launch_decolor_single(d, g, ctx->grid, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    mark(ctx, true, 0, st);
+    hipError_t e = dc::launch_decolor_single(d, g, grid_blocks(ctx, ctx->tune.decolor_gpc), st);
     if (e != hipSuccess)
         return hip_fail(e, "decolorize launch");
-    mark(ctx, 1, (hipStream_t)stream);
+    mark(ctx, true, 1, st);
     return DC_OK;
 }
 
@@ -537,19 +782,16 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
     if (rc != DC_OK || n == 0)
         return rc;
     const hipStream_t st = (hipStream_t)stream;
+    HostTable h;
+    build_table(imgs, n, params, false, ctx->tune, h);
     dc_ctx::Slot *slot = nullptr;
-    Table t;
-    rc = stage_table(ctx, imgs, n, params, false, ctx->groups, st, &slot, &t);
+    DevBufs b;
+    rc = stage(ctx, h, st, &slot, &b);
     if (rc != DC_OK)
         return rc;
-    ctx->prof_used = 0;
-    mark(ctx, 0, st);
-    hipError_t e = dc::launch_decolor_table(t.table, t.tile_end, n, t.total_tiles, t.mixed,
-                                            imgs[0].src_dtype, ctx->groups,
-                                            ctx->grid, st);
-    if (e != hipSuccess)
-        return hip_fail(e, "decolorize_batch launch");
-    mark(ctx, 1, st);
+    rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
+    if (rc != DC_OK)
+        return rc;
     return release_slot(slot, st);
 }
 
@@ -564,26 +806,169 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
     if (rc != DC_OK || n == 0)
         return rc;
     const hipStream_t st = (hipStream_t)stream;
+    HostTable h;
+    build_table(imgs, n, params, true, ctx->tune, h);
     dc_ctx::Slot *slot = nullptr;
-    Table t;
-    rc = stage_table(ctx, imgs, n, params, true, 0, st, &slot, &t);
+    DevBufs b;
+    rc = stage(ctx, h, st, &slot, &b);
     if (rc != DC_OK)
         return rc;
-    const dc::TmArgs a = tm_of(tm);
-    ctx->prof_used = 0;
-    mark(ctx, 0, st);
-    hipError_t e = dc::launch_tm_pass1(t.table, t.tile_end, n, t.total_tiles, a, t.parts, st);
-    mark(ctx, 1, st);
-    if (e == hipSuccess)
-        e = dc::launch_tm_finalize(t.table, n, t.tile_end, a, t.parts, t.curves,
-                                   (dc::StatsOut *)stats, st);
-    mark(ctx, 2, st);
-    if (e == hipSuccess)
-        e = dc::launch_tm_pass2(t.table, t.tile_end, n, t.total_tiles, a, t.curves, st);
-    mark(ctx, 3, st);
-    if (e != hipSuccess)
-        return hip_fail(e, "tonemap_global launch");
+    rc = enqueue_tonemap(ctx, h, b, ctx->tune, tm_of(tm), (dc::StatsOut *)stats, st, true);
+    if (rc != DC_OK)
+        return rc;
     return release_slot(slot, st);
+}
+
+int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
+                   const dc_params *params, const dc_tm_params *tm, dc_stats *stats, int32_t flags,
+                   dc_plan **plan)
+{
+    g_last_error.clear();
+    if (!plan)
+        return fail(DC_ERR_INVALID_ARG, "plan out-pointer is NULL");
+    *plan = nullptr;
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP)
+        return fail(DC_ERR_INVALID_ARG, "kind must be DC_PLAN_DECOLORIZE or DC_PLAN_TONEMAP");
+    if (flags & ~DC_PLAN_GRAPH)
+        return fail(DC_ERR_INVALID_ARG, "unknown plan flags");
+    if (n < 1)
+        return fail(DC_ERR_INVALID_ARG, "a plan needs at least one image");
+    if (kind == DC_PLAN_DECOLORIZE && (tm || stats))
+        return fail(DC_ERR_INVALID_ARG, "tm and stats apply to tone-map plans only");
+    rc = dc_validate(imgs, n, params, tm);
+    if (rc != DC_OK)
+        return rc;
+    return plan_build(ctx, kind, imgs, n, params, tm, stats, flags, ctx->tune, plan);
+}
+
+int dc_plan_run(dc_plan *p, void *stream)
+{
+    g_last_error.clear();
+    if (!p)
+        return fail(DC_ERR_INVALID_ARG, "plan is NULL");
+    int rc = check_ctx(p->ctx);
+    if (rc != DC_OK)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    if (!p->graph)
+        return plan_enqueue(p, st, true);
+    if (!st)
+        return fail(DC_ERR_INVALID_ARG, "graph plans need a non-null stream");
+    if (!p->exec) {
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        rc = plan_enqueue(p, st, false);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st, &g);
+        if (rc != DC_OK) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            p->exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    hipError_t e = hipGraphLaunch(p->exec, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGraphLaunch");
+    return DC_OK;
+}
+
+int dc_plan_destroy(dc_plan *p)
+{
+    if (!p)
+        return DC_OK;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+    return DC_OK;
+}
+
+int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
+                const dc_params *params, const dc_tm_params *tm, void *stream, dc_tuning *chosen)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP)
+        return fail(DC_ERR_INVALID_ARG, "kind must be DC_PLAN_DECOLORIZE or DC_PLAN_TONEMAP");
+    if (n < 1)
+        return fail(DC_ERR_INVALID_ARG, "tuning needs at least one image");
+    rc = dc_validate(imgs, n, params, kind == DC_PLAN_TONEMAP ? tm : nullptr);
+    if (rc != DC_OK)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const int gpcs[] = {0, 1, 2, 4, 8, 16};
+    const int reps = 5;
+    Tune best = ctx->tune;
+    std::vector<float> ms;
+    auto run = [&](const Tune &t, std::vector<float> *out) -> int {
+        dc_plan *p = nullptr;
+        int r = plan_build(ctx, kind, imgs, n, params, tm, nullptr, 0, t, &p);
+        if (r == DC_OK)
+            r = time_plan(p, st, reps, out);
+        if (p) {
+            (void)hipStreamSynchronize(st);
+            plan_free(p);
+        }
+        return r;
+    };
+    if (kind == DC_PLAN_DECOLORIZE) {
+        bool mixed = false;
+        for (int32_t i = 1; i < n; ++i)
+            mixed |= imgs[i].src_dtype != imgs[0].src_dtype;
+        float best_ms = 1e30f;
+        for (int g : {1, 2, 4}) {
+            for (int c : gpcs) {
+                Tune t = ctx->tune;
+                if (mixed)
+                    t.mixed_groups = g;
+                else
+                    t.groups[imgs[0].src_dtype] = g;
+                t.decolor_gpc = c;
+                rc = run(t, &ms);
+                if (rc != DC_OK)
+                    return rc;
+                if (ms[0] < best_ms) {
+                    best_ms = ms[0];
+                    best = t;
+                }
+            }
+        }
+    } else {
+        float b1 = 1e30f, b2 = 1e30f;
+        for (int c : gpcs) {
+            Tune t = ctx->tune;
+            t.pass1_gpc = c;
+            t.pass2_gpc = c;
+            rc = run(t, &ms);
+            if (rc != DC_OK)
+                return rc;
+            if (ms[0] < b1) {
+                b1 = ms[0];
+                best.pass1_gpc = c;
+            }
+            if (ms[2] < b2) {
+                b2 = ms[2];
+                best.pass2_gpc = c;
+            }
+        }
+    }
+    ctx->tune = best;
+    if (chosen)
+        *chosen = to_public(best);
+    return DC_OK;
 }
 
 } // extern "C"

@@ -193,3 +193,49 @@ def test_repeatable(dev):
     a = P.decolorize(x)
     for _ in range(5):
         assert torch.equal(P.decolorize(x), a)
+
+
+def test_plans_match_direct_calls(dev):
+    """Frozen plans (direct launches and HIP-graph replays) give the results of
+    the direct batched call, bit for bit, on every replay."""
+    rng = np.random.default_rng(70)
+    imgs = [synth.sdr_pixels(rng, 123, 457), synth.hdr_pixels(rng, 64, 64),
+            synth.sdr_pixels(rng, 1, 999)]
+    xs = [to_dev(a, dev) for a in imgs]
+    want = P.decolorize_batch(xs, torch.float32, torch.uint8)
+    for graph in (False, True):
+        o32 = [torch.full(x.shape[:2], -1.0, device=dev) for x in xs]
+        o8 = [torch.zeros(x.shape[:2], dtype=torch.uint8, device=dev) for x in xs]
+        plan = P.Plan(P.PLAN_DECOLORIZE, xs, o32, o8, graph=graph)
+        s = torch.cuda.Stream()
+        for rep in range(4):
+            for o in o32:
+                o.fill_(-1.0)  # eager work between replays
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                plan.run(s)
+            s.synchronize()
+            for (wf, wu), a, b in zip(want, o32, o8):
+                assert torch.equal(a, wf) and torch.equal(b, wu), (graph, rep)
+        plan.close()
+
+
+def test_tuning_roundtrip_and_autotune(dev):
+    t0 = P.get_tuning()
+    try:
+        t = dict(t0, groups=[4, 1, 2], decolor_grid_per_cu=8)
+        P.set_tuning(t)
+        assert P.get_tuning() == t
+        with pytest.raises(P.DecolorError):
+            P.set_tuning(dict(t0, groups=[3, 1, 2]))
+        img = synth.sdr_pixels(np.random.default_rng(71), 1080, 1920)
+        x = to_dev(img, dev)
+        ref = P.decolorize(x)
+        out = torch.empty_like(ref)
+        chosen = P.autotune(P.PLAN_DECOLORIZE, [x], [out])
+        report("autotune chose %s" % chosen)
+        assert chosen["groups"][0] in (1, 2, 4)
+        assert torch.equal(P.decolorize(x), ref)  # launch shape never changes results
+        assert torch.equal(out, ref)
+    finally:
+        P.set_tuning(t0)

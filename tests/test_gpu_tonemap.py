@@ -119,3 +119,43 @@ def test_pitched_and_unaligned_views(dev):
         outs, _, stats = P.tonemap_global([to_dev(big, dev)[:, x0:x0 + 70]], **TM)
         _check_stats(P.stats_to_host(stats)[0], st_ref, name)
         check_f32(outs[0].cpu().numpy(), t_ref, name + " T")
+
+
+def test_tonemap_plan_and_graph_replays(dev):
+    rng = np.random.default_rng(12)
+    imgs = [synth.hdr_pixels(rng, 300, 200), synth.sdr_pixels(rng, 77, 1000)]
+    xs = [to_dev(a, dev) for a in imgs]
+    want, _, want_st = P.tonemap_global(xs, torch.float32, **TM)
+    want_st = want_st.clone()
+    for graph in (False, True):
+        outs = [torch.empty(x.shape[:2], device=dev) for x in xs]
+        st = torch.zeros_like(want_st)
+        plan = P.Plan(P.PLAN_TONEMAP, xs, outs, stats=st, graph=graph, **TM)
+        s = torch.cuda.Stream()
+        for rep in range(4):
+            for o in outs:
+                o.fill_(2.0)
+            st.zero_()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                plan.run(s)
+            s.synchronize()
+            for a, b in zip(outs, want):
+                assert torch.equal(a, b), (graph, rep)
+            assert torch.equal(st, want_st), (graph, rep)
+        plan.close()
+
+
+def test_autotune_tonemap_keeps_results(dev):
+    t0 = P.get_tuning()
+    try:
+        img = synth.hdr_pixels(np.random.default_rng(13), 1024, 1024)
+        x = to_dev(img, dev)
+        ref, _, ref_st = P.tonemap_global([x], **TM)
+        out = torch.empty_like(ref[0])
+        chosen = P.autotune(P.PLAN_TONEMAP, [x], [out], **TM)
+        report("tone-map autotune chose %s" % chosen)
+        t, _, st = P.tonemap_global([x], **TM)
+        assert torch.equal(t[0], ref[0]) and torch.equal(st, ref_st)
+    finally:
+        P.set_tuning(t0)
