@@ -93,13 +93,13 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
                                 int64_t total_tiles, int mixed_src, int src_dtype, int groups,
                                 int64_t grid, hipStream_t s);
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, Part *parts, int64_t grid,
-                           hipStream_t s);
+                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+                           Part *parts, int64_t grid, hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *tile_end,
                               TmArgs tm, const Part *parts, Curve *curves, StatsOut *stats,
                               hipStream_t s);
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, const Curve *curves, int64_t grid,
-                           hipStream_t s);
+                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+                           const Curve *curves, int64_t grid, hipStream_t s);
 
 } // namespace dc

@@ -97,6 +97,17 @@ __device__ __forceinline__ DC_GLOBAL T *gpw(void *p)
 }
 
 // ------------------------------------------------------------ decode
+//
+// Work unit: 12 bytes of interleaved RGB per lane, loaded with one dwordx3
+// (4 pixels of u8, 2 of f16, 1 of f32). Lanes of a wave take consecutive
+// units, so every load instruction reads 768 contiguous bytes and every store
+// instruction writes contiguous bytes too; a thread holds U units of a tile,
+// all loads issued before any arithmetic.
+
+__host__ __device__ constexpr int unit_px(int src_dtype)
+{
+    return src_dtype == 0 ? 4 : (src_dtype == 1 ? 2 : 1);
+}
 
 __device__ __forceinline__ float half_lo(unsigned w)
 {
@@ -107,9 +118,9 @@ __device__ __forceinline__ float half_hi(unsigned w)
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
 }
 
-// Channel c of element e of a 48-byte group held as 12 dwords.
+// Element e (channel value number e) of a 12-byte unit held as 3 dwords.
 template <int SRC>
-__device__ __forceinline__ float chan(const unsigned (&w)[12], int e)
+__device__ __forceinline__ float chan(const unsigned (&w)[3], int e)
 {
     if constexpr (SRC == 0) {
         // The empty asm hides that the value is a small integer, so the
@@ -125,14 +136,13 @@ __device__ __forceinline__ float chan(const unsigned (&w)[12], int e)
     }
 }
 
-template <int SRC>
-__device__ __forceinline__ void load_group(const uint8_t *p, unsigned (&w)[12])
+// One unit: three dwords from a 4-byte aligned address (a single dwordx3).
+__device__ __forceinline__ void load_unit(const uint8_t *p, unsigned (&w)[3])
 {
-    const DC_GLOBAL u32x4 *q = gp<u32x4>(p);
-    const u32x4 a = q[0], b = q[1], c = q[2];
-    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
-    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
-    w[8] = c.x; w[9] = c.y; w[10] = c.z; w[11] = c.w;
+    const DC_GLOBAL unsigned *q = gp<unsigned>(p);
+    w[0] = q[0];
+    w[1] = q[1];
+    w[2] = q[2];
 }
 
 template <int SRC>
@@ -168,18 +178,9 @@ struct Enc {
 };
 
 template <bool SU>
-__device__ __forceinline__ unsigned pack_u8x4(float a, float b, float c, float d, float s)
+__device__ __forceinline__ unsigned u8_of(float v, float s, int byte, unsigned acc)
 {
-    if constexpr (SU) {
-        a *= s;
-        b *= s;
-        c *= s;
-        d *= s;
-    }
-    unsigned w = __builtin_amdgcn_cvt_pk_u8_f32(a, 0, 0u);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(b, 1, w);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(c, 2, w);
-    return __builtin_amdgcn_cvt_pk_u8_f32(d, 3, w);
+    return __builtin_amdgcn_cvt_pk_u8_f32(SU ? v * s : v, byte, acc);
 }
 
 __device__ __forceinline__ unsigned pack_f16x2(float a, float b)
@@ -189,63 +190,60 @@ __device__ __forceinline__ unsigned pack_f16x2(float a, float b)
     return (unsigned)ha | ((unsigned)hb << 16);
 }
 
-// Stores GPX consecutive values at pixel index px of a 1-channel row.
-template <int GPX, bool SF, bool SU>
-__device__ __forceinline__ void store_group(uint8_t *base, int dtype, int64_t px,
-                                            const float (&v)[GPX], Enc e)
+// Stores the PPU values of one unit at pixel index lp of a 1-channel row
+// whose pixel 0 is at base.
+template <int PPU, bool SF, bool SU>
+__device__ __forceinline__ void store_unit(uint8_t *base, int dtype, uint32_t lp,
+                                           const float (&v)[PPU], Enc e)
 {
     if (dtype == 0) {
-        unsigned w[GPX / 4];
+        unsigned w = 0;
 #pragma unroll
-        for (int i = 0; i < GPX / 4; ++i)
-            w[i] = pack_u8x4<SU>(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3], e.u8scale);
-        uint8_t *p = base + px;
-        if constexpr (GPX == 16)
-            *gpw<u32x4>(p) = u32x4{w[0], w[1], w[2], w[3]};
-        else if constexpr (GPX == 8)
-            *gpw<u32x2>(p) = u32x2{w[0], w[1]};
+        for (int i = 0; i < PPU; ++i)
+            w = u8_of<SU>(v[i], e.u8scale, i, w);
+        uint8_t *p = base + lp;
+        if constexpr (PPU == 4)
+            *gpw<unsigned>(p) = w;
+        else if constexpr (PPU == 2)
+            *gpw<unsigned short>(p) = (unsigned short)w;
         else
-            *gpw<unsigned>(p) = w[0];
+            *gpw<uint8_t>(p) = (uint8_t)w;
     } else if (dtype == 1) {
-        unsigned w[GPX / 2];
+        float a[PPU];
 #pragma unroll
-        for (int i = 0; i < GPX / 2; ++i)
-            w[i] = SF ? pack_f16x2(v[2 * i] * e.fscale, v[2 * i + 1] * e.fscale)
-                      : pack_f16x2(v[2 * i], v[2 * i + 1]);
-        uint8_t *p = base + 2 * px;
-        if constexpr (GPX == 4) {
-            *gpw<u32x2>(p) = u32x2{w[0], w[1]};
-        } else {
-#pragma unroll
-            for (int i = 0; i < GPX / 8; ++i)
-                gpw<u32x4>(p)[i] = u32x4{w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]};
-        }
+        for (int i = 0; i < PPU; ++i)
+            a[i] = SF ? v[i] * e.fscale : v[i];
+        uint8_t *p = base + 2 * lp;
+        if constexpr (PPU == 4)
+            *gpw<u32x2>(p) = u32x2{pack_f16x2(a[0], a[1]), pack_f16x2(a[2], a[3])};
+        else if constexpr (PPU == 2)
+            *gpw<unsigned>(p) = pack_f16x2(a[0], a[1]);
+        else
+            *gpw<_Float16>(p) = (_Float16)a[0];
     } else {
-        uint8_t *p = base + 4 * px;
+        unsigned b[PPU];
 #pragma unroll
-        for (int i = 0; i < GPX / 4; ++i) {
-            float a = v[4 * i], b = v[4 * i + 1], c = v[4 * i + 2], d = v[4 * i + 3];
-            if constexpr (SF) {
-                a *= e.fscale;
-                b *= e.fscale;
-                c *= e.fscale;
-                d *= e.fscale;
-            }
-            gpw<u32x4>(p)[i] = u32x4{__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
-                                     __builtin_bit_cast(unsigned, c), __builtin_bit_cast(unsigned, d)};
-        }
+        for (int i = 0; i < PPU; ++i)
+            b[i] = __builtin_bit_cast(unsigned, SF ? v[i] * e.fscale : v[i]);
+        uint8_t *p = base + 4 * lp;
+        if constexpr (PPU == 4)
+            *gpw<u32x4>(p) = u32x4{b[0], b[1], b[2], b[3]};
+        else if constexpr (PPU == 2)
+            *gpw<u32x2>(p) = u32x2{b[0], b[1]};
+        else
+            *gpw<unsigned>(p) = b[0];
     }
 }
 
 template <bool SF, bool SU>
-__device__ __forceinline__ void store_px(uint8_t *base, int dtype, int64_t px, float v, Enc e)
+__device__ __forceinline__ void store_px(uint8_t *base, int dtype, uint32_t lp, float v, Enc e)
 {
     if (dtype == 0)
-        gpw<uint8_t>(base)[px] = (uint8_t)__builtin_amdgcn_cvt_pk_u8_f32(SU ? v * e.u8scale : v, 0, 0u);
+        gpw<uint8_t>(base)[lp] = (uint8_t)u8_of<SU>(v, e.u8scale, 0, 0u);
     else if (dtype == 1)
-        gpw<_Float16>(base)[px] = (_Float16)(SF ? v * e.fscale : v);
+        gpw<_Float16>(base)[lp] = (_Float16)(SF ? v * e.fscale : v);
     else
-        gpw<float>(base)[px] = SF ? v * e.fscale : v;
+        gpw<float>(base)[lp] = SF ? v * e.fscale : v;
 }
 
 // Encoding of Lhat from L (input units): 8-bit input carries L in code units,
@@ -259,122 +257,87 @@ struct LumEnc {
 
 // ------------------------------------------------------------ tile walk
 
-// Addresses of one tile: segment base pointers and the pixel range.
+// One tile: its segment's base pointers advanced to the tile's first pixel
+// (uniform across the workgroup), and how many of the segment's pixels remain
+// from there. Offsets within a tile fit in 32 bits.
 struct TileRef {
     const uint8_t *src;
     uint8_t *dst;
     uint8_t *dst2;
-    int64_t px0; // first pixel of the tile within the segment
-    int64_t n;   // pixels in the segment
+    int64_t rem;
 };
 
 __device__ __forceinline__ TileRef tile_ref(const DevImage &im, int64_t tile, int64_t tile_px)
 {
     const int64_t seg = tile / im.tiles_per_seg;
     const int64_t ts = tile - seg * im.tiles_per_seg;
+    const int64_t px0 = ts * tile_px;
     TileRef t;
-    t.src = im.src + seg * im.src_seg_stride;
-    t.dst = im.dst + seg * im.dst_seg_stride;
-    t.dst2 = im.dst2 ? im.dst2 + seg * im.dst2_seg_stride : nullptr;
-    t.px0 = ts * tile_px;
-    t.n = im.seg_len;
+    t.src = im.src + seg * im.src_seg_stride + px0 * 3 * elem_size(im.src_dtype);
+    t.dst = im.dst + seg * im.dst_seg_stride + px0 * elem_size(im.dst_dtype);
+    t.dst2 = im.dst2 ? im.dst2 + seg * im.dst2_seg_stride + px0 * elem_size(im.dst2_dtype)
+                     : nullptr;
+    t.rem = im.seg_len - px0;
     return t;
 }
 
-// Luminance of all pixels a thread owns in one tile (G vector groups of GPX
-// pixels, or the same count of single pixels on the per-pixel walk). lv holds L
-// in input units; valid marks pixels inside the segment. In both walks the
-// valid slots of a thread form a prefix, and slot 0 of lane 0 of a wave holds
-// the wave's first pixel.
-template <int SRC, int G>
-__device__ __forceinline__ void tile_lum(const DevImage &im, const TileRef &t, Coef k,
-                                         float (&lv)[G * group_px(SRC)],
-                                         bool (&valid)[G * group_px(SRC)])
+// Tile-local pixel of slot (u, j) of this thread: unit u covers pixels
+// (u * kBlock + tid) * PPU + j on the vector walks; the per-pixel walk uses
+// (u * PPU + j) * kBlock + tid. Either way the slots a thread holds are in
+// increasing pixel order, so its valid slots form a prefix, and slot 0 of lane
+// 0 of a wave is the wave's first pixel.
+template <int PPU>
+__device__ __forceinline__ uint32_t slot_lp(bool vec, int u, int j)
 {
-    constexpr int GPX = group_px(SRC);
+    const uint32_t tid = threadIdx.x;
+    return vec ? (uint32_t)(u * kBlock + tid) * PPU + j : (uint32_t)(u * PPU + j) * kBlock + tid;
+}
+
+// Luminance of all U * PPU pixels a thread owns in a FULL tile on a vector
+// walk (every slot inside the segment): all U loads are issued first. lv holds
+// L in input units.
+template <int SRC, int U>
+__device__ __forceinline__ void tile_lum_full(const TileRef &t, Coef k,
+                                              float (&lv)[U * unit_px(SRC)])
+{
+    constexpr int PPU = unit_px(SRC);
     constexpr int ES = elem_size(SRC);
-    const int tid = threadIdx.x;
-    if (im.walk != kWalkScalar) {
-        unsigned w[G][12];
-        bool full[G];
+    unsigned w[U][3];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t gp = t.px0 + (int64_t)(g * kBlock + tid) * GPX;
-            full[g] = gp + GPX <= t.n;
-            if (full[g])
-                load_group<SRC>(t.src + gp * 3 * ES, w[g]);
-        }
+    for (int u = 0; u < U; ++u)
+        load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t gp = t.px0 + (int64_t)(g * kBlock + tid) * GPX;
-            if (full[g]) {
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int i = 0; i < GPX; ++i) {
-                    lv[g * GPX + i] = lum<SRC>(chan<SRC>(w[g], 3 * i), chan<SRC>(w[g], 3 * i + 1),
-                                               chan<SRC>(w[g], 3 * i + 2), k);
-                    valid[g * GPX + i] = true;
-                }
-            } else {
+        for (int j = 0; j < PPU; ++j)
+            lv[u * PPU + j] = lum<SRC>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
+                                       chan<SRC>(w[u], 3 * j + 2), k);
+}
+
+// Writes the per-slot values of a full tile (laid out as tile_lum_full
+// produced them) to one output.
+template <int SRC, int U, bool SF, bool SU>
+__device__ __forceinline__ void tile_store_full(uint8_t *out, int dtype,
+                                                const float (&v)[U * unit_px(SRC)], Enc e)
+{
+    constexpr int PPU = unit_px(SRC);
 #pragma unroll
-                for (int i = 0; i < GPX; ++i) {
-                    const int64_t p = gp + i;
-                    valid[g * GPX + i] = p < t.n;
-                    lv[g * GPX + i] = 0.0f;
-                    if (p < t.n) {
-                        float R, G_, B;
-                        load_px<SRC>(t.src + p * 3 * ES, R, G_, B);
-                        lv[g * GPX + i] = lum<SRC>(R, G_, B, k);
-                    }
-                }
-            }
-        }
-    } else {
+    for (int u = 0; u < U; ++u) {
+        float vv[PPU];
 #pragma unroll
-        for (int j = 0; j < G * GPX; ++j) {
-            const int64_t p = t.px0 + (int64_t)j * kBlock + tid;
-            valid[j] = p < t.n;
-            lv[j] = 0.0f;
-            if (p < t.n) {
-                float R, G_, B;
-                load_px<SRC>(t.src + p * 3 * ES, R, G_, B);
-                lv[j] = lum<SRC>(R, G_, B, k);
-            }
-        }
+        for (int j = 0; j < PPU; ++j)
+            vv[j] = v[u * PPU + j];
+        store_unit<PPU, SF, SU>(out, dtype, slot_lp<PPU>(true, u, 0), vv, e);
     }
 }
 
-// Writes per-pixel values v (laid out as tile_lum produced them) to one output.
-template <int SRC, int G, bool SF, bool SU>
-__device__ __forceinline__ void tile_store(const DevImage &im, const TileRef &t, uint8_t *out,
-                                           int dtype, const float (&v)[G * group_px(SRC)], Enc e)
+// L (input units) of tile-local pixel p, loaded channel by channel.
+template <int SRC>
+__device__ __forceinline__ float lum_at(const TileRef &t, uint32_t p, Coef k)
 {
-    constexpr int GPX = group_px(SRC);
-    const int tid = threadIdx.x;
-    if (im.walk != kWalkScalar) {
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t gp = t.px0 + (int64_t)(g * kBlock + tid) * GPX;
-            if (gp + GPX <= t.n) {
-                float vv[GPX];
-#pragma unroll
-                for (int i = 0; i < GPX; ++i)
-                    vv[i] = v[g * GPX + i];
-                store_group<GPX, SF, SU>(out, dtype, gp, vv, e);
-            } else {
-#pragma unroll
-                for (int i = 0; i < GPX; ++i)
-                    if (gp + i < t.n)
-                        store_px<SF, SU>(out, dtype, gp + i, v[g * GPX + i], e);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < G * GPX; ++j) {
-            const int64_t p = t.px0 + (int64_t)j * kBlock + tid;
-            if (p < t.n)
-                store_px<SF, SU>(out, dtype, p, v[j], e);
-        }
-    }
+    float R, G_, B;
+    load_px<SRC>(t.src + p * (3 * elem_size(SRC)), R, G_, B);
+    return lum<SRC>(R, G_, B, k);
 }
 
 // Visits the global tiles of a persistent block (blockIdx.x, blockIdx.x +
@@ -406,79 +369,59 @@ __device__ __forceinline__ void for_each_tile(const int64_t *__restrict__ tile_e
 
 // ------------------------------------------------------- decolorization
 
-// Luminance of one full vector group (GPX pixels) held as 12 dwords.
-template <int SRC>
-__device__ __forceinline__ void group_lum(const unsigned (&w)[12], Coef k,
-                                          float (&v)[group_px(SRC)])
-{
-#pragma unroll
-    for (int i = 0; i < group_px(SRC); ++i)
-        v[i] = lum<SRC>(chan<SRC>(w, 3 * i), chan<SRC>(w, 3 * i + 1), chan<SRC>(w, 3 * i + 2), k);
-}
-
-// Decolorization of one tile: every load of the thread's G groups is issued
-// first, then each group is evaluated and stored while later loads are still
-// in flight.
-template <int SRC, int G>
+// Decolorization of one tile of kBlock * U units. On a full tile every load of
+// the thread's U units is issued first, then each unit is evaluated and stored
+// while later loads are still in flight; a partial tile (the segment's end) and
+// the per-pixel walk go pixel by pixel with bounds checks.
+template <int SRC, int U>
 __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile)
 {
-    constexpr int GPX = group_px(SRC);
+    constexpr int PPU = unit_px(SRC);
     constexpr int ES = elem_size(SRC);
+    constexpr int64_t TILE = (int64_t)kBlock * U * PPU;
     constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
-    const TileRef t = tile_ref(im, tile, (int64_t)kBlock * G * GPX);
+    const TileRef t = tile_ref(im, tile, TILE);
     const Enc e{im.unit, 255.0f};
     const Coef k = im.k;
-    const int tid = threadIdx.x;
-    if (im.walk != kWalkScalar) {
-        unsigned w[G][12];
-        bool full[G];
+    const bool vec = im.walk != kWalkScalar;
+    if (vec && t.rem >= TILE) {
+        unsigned w[U][3];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t gp = t.px0 + (int64_t)(g * kBlock + tid) * GPX;
-            full[g] = gp + GPX <= t.n;
-            if (full[g])
-                load_group<SRC>(t.src + gp * 3 * ES, w[g]);
-        }
+        for (int u = 0; u < U; ++u)
+            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t gp = t.px0 + (int64_t)(g * kBlock + tid) * GPX;
-            if (full[g]) {
-                float v[GPX];
-                group_lum<SRC>(w[g], k, v);
-                store_group<GPX, SF, SU>(t.dst, im.dst_dtype, gp, v, e);
-                if (t.dst2)
-                    store_group<GPX, SF, SU>(t.dst2, im.dst2_dtype, gp, v, e);
-            } else {
-                for (int64_t p = gp; p < t.n && p < gp + GPX; ++p) {
-                    float R, G_, B;
-                    load_px<SRC>(t.src + p * 3 * ES, R, G_, B);
-                    const float v = lum<SRC>(R, G_, B, k);
-                    store_px<SF, SU>(t.dst, im.dst_dtype, p, v, e);
-                    if (t.dst2)
-                        store_px<SF, SU>(t.dst2, im.dst2_dtype, p, v, e);
-                }
-            }
+        for (int u = 0; u < U; ++u) {
+            float v[PPU];
+#pragma unroll
+            for (int j = 0; j < PPU; ++j)
+                v[j] = lum<SRC>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
+                                chan<SRC>(w[u], 3 * j + 2), k);
+            const uint32_t lp = slot_lp<PPU>(true, u, 0);
+            store_unit<PPU, SF, SU>(t.dst, im.dst_dtype, lp, v, e);
+            if (t.dst2)
+                store_unit<PPU, SF, SU>(t.dst2, im.dst2_dtype, lp, v, e);
         }
-    } else {
-        for (int j = 0; j < G * GPX; ++j) {
-            const int64_t p = t.px0 + (int64_t)j * kBlock + tid;
-            if (p < t.n) {
-                float R, G_, B;
-                load_px<SRC>(t.src + p * 3 * ES, R, G_, B);
-                const float v = lum<SRC>(R, G_, B, k);
-                store_px<SF, SU>(t.dst, im.dst_dtype, p, v, e);
-                if (t.dst2)
-                    store_px<SF, SU>(t.dst2, im.dst2_dtype, p, v, e);
-            }
+        return;
+    }
+    const uint32_t rem = (uint32_t)(t.rem < TILE ? t.rem : TILE);
+#pragma unroll 1
+    for (int s = 0; s < U * PPU; ++s) {
+        const uint32_t p = slot_lp<PPU>(vec, s / PPU, s % PPU);
+        if (p < rem) {
+            const float v = lum_at<SRC>(t, p, k);
+            store_px<SF, SU>(t.dst, im.dst_dtype, p, v, e);
+            if (t.dst2)
+                store_px<SF, SU>(t.dst2, im.dst2_dtype, p, v, e);
         }
     }
 }
 
+// Kernel template argument G = 48-byte groups per thread = 4 units.
 template <int SRC, int G>
 __global__ __launch_bounds__(kBlock) void k_decolor_single(DevImage im, int64_t ntiles)
 {
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        decolor_tile<SRC, G>(im, tile);
+        decolor_tile<SRC, 4 * G>(im, tile);
 }
 
 // One launch over the tiles of many images. MIXED = the input element type
@@ -492,15 +435,15 @@ __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__rest
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
-            // Tile sizes are per image: G groups of its own group width.
+            // Tile sizes are per image: 4G units of its own unit width.
             if (im.src_dtype == 0)
-                decolor_tile<0, G>(im, lt);
+                decolor_tile<0, 4 * G>(im, lt);
             else if (im.src_dtype == 1)
-                decolor_tile<1, G>(im, lt);
+                decolor_tile<1, 4 * G>(im, lt);
             else
-                decolor_tile<2, G>(im, lt);
+                decolor_tile<2, 4 * G>(im, lt);
         } else {
-            decolor_tile<SRC, G>(im, lt);
+            decolor_tile<SRC, 4 * G>(im, lt);
         }
     });
 }
@@ -571,27 +514,24 @@ template <int SRC>
 __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                               Part *__restrict__ parts)
 {
-    constexpr int G = kStatsPxPerThread / group_px(SRC);
+    constexpr int PPU = unit_px(SRC);
+    constexpr int U = kStatsPxPerThread / PPU;
     constexpr int NV = kStatsPxPerThread;
+    constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
     const TileRef t = tile_ref(im, tile, kStatsChunkPx);
-    float lv[NV];
-    bool valid[NV];
-    tile_lum<SRC, G>(im, t, im.k, lv, valid);
-    if (t.dst2)
-        tile_store<SRC, G, LumEnc<SRC>::SF, LumEnc<SRC>::SU>(im, t, t.dst2, im.dst2_dtype, lv,
-                                                            Enc{im.unit, 255.0f});
-    float x[NV];
+    const Enc e{im.unit, 255.0f};
+    const bool vec = im.walk != kWalkScalar;
+    float K, s = 0.0f, q = 0.0f, cnt, lo = __builtin_inff(), hi = -__builtin_inff();
+    if (vec && t.rem >= kStatsChunkPx) {
+        float lv[NV];
+        tile_lum_full<SRC, U>(t, im.k, lv);
+        if (t.dst2)
+            tile_store_full<SRC, U, SF, SU>(t.dst2, im.dst2_dtype, lv, e);
+        float x[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-        x[i] = xlog2(lv[i], im.unit, tm.eps);
-    const float K = __builtin_bit_cast(
-        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x[0])));
-    float s = 0.0f, q = 0.0f, lo = lv[0], hi = lv[0];
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-        cnt += valid[i] ? 1 : 0;
-    if (cnt == NV) {
+        for (int i = 0; i < NV; ++i)
+            x[i] = xlog2(lv[i], im.unit, tm.eps);
+        K = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x[0])));
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const float d = x[i] - K;
@@ -600,27 +540,38 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
             lo = fminf(lo, lv[i]);
             hi = fmaxf(hi, lv[i]);
         }
-    } else if (cnt > 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const float d = valid[i] ? x[i] - K : 0.0f;
-            const float l = valid[i] ? lv[i] : lv[0];
-            s += d;
-            q = fmaf(d, d, q);
-            lo = fminf(lo, l);
-            hi = fmaxf(hi, l);
-        }
+        cnt = (float)NV;
     } else {
-        lo = __builtin_inff();
-        hi = -__builtin_inff();
+        // Partial tile or per-pixel walk: one pixel at a time. Slot 0 of lane
+        // 0 is the wave's first pixel, valid whenever any pixel of the wave is.
+        const uint32_t rem = (uint32_t)(t.rem < kStatsChunkPx ? t.rem : kStatsChunkPx);
+        const uint32_t p0 = slot_lp<PPU>(vec, 0, 0);
+        const float l0 = p0 < rem ? lum_at<SRC>(t, p0, im.k) : 0.0f;
+        K = __builtin_bit_cast(
+            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, xlog2(l0, im.unit, tm.eps))));
+        cnt = 0.0f;
+#pragma unroll 1
+        for (int i = 0; i < NV; ++i) {
+            const uint32_t p = slot_lp<PPU>(vec, i / PPU, i % PPU);
+            if (p < rem) {
+                const float l = lum_at<SRC>(t, p, im.k);
+                if (t.dst2)
+                    store_px<SF, SU>(t.dst2, im.dst2_dtype, p, l, e);
+                const float d = xlog2(l, im.unit, tm.eps) - K;
+                s += d;
+                q = fmaf(d, d, q);
+                lo = fminf(lo, l);
+                hi = fmaxf(hi, l);
+                cnt += 1.0f;
+            }
+        }
     }
     s = wave_sum(s);
     q = wave_sum(q);
-    const float n = wave_sum((float)cnt);
+    const float n = wave_sum(cnt);
     lo = wave_min(lo);
     hi = wave_max(hi);
-    const int lane = threadIdx.x & 63;
-    if (lane == 0) {
+    if ((threadIdx.x & 63) == 0) {
         Part p = part_empty();
         if (n > 0.0f) {
             const float m = s / n;
@@ -630,6 +581,9 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
     }
 }
 
+// MIXED = the input element type varies per image; otherwise it is SRC (one
+// instantiation per type keeps the register count of the uniform case low).
+template <int SRC, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
                                                      int nimg, int64_t total_tiles, TmArgs tm,
@@ -638,12 +592,16 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict_
     for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
-        if (im.src_dtype == 0)
-            tm_pass1_tile<0>(im, lt, tm, parts);
-        else if (im.src_dtype == 1)
-            tm_pass1_tile<1>(im, lt, tm, parts);
-        else
-            tm_pass1_tile<2>(im, lt, tm, parts);
+        if constexpr (MIXED) {
+            if (im.src_dtype == 0)
+                tm_pass1_tile<0>(im, lt, tm, parts);
+            else if (im.src_dtype == 1)
+                tm_pass1_tile<1>(im, lt, tm, parts);
+            else
+                tm_pass1_tile<2>(im, lt, tm, parts);
+        } else {
+            tm_pass1_tile<SRC>(im, lt, tm, parts);
+        }
     });
 }
 
@@ -690,21 +648,41 @@ __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restri
     }
 }
 
+// T = 1 / (1 + exp2(a (x2 - mu2))) of one pixel.
+__device__ __forceinline__ float curve(float l, float unit, TmArgs tm, Curve cv)
+{
+    return hw_rcp(1.0f + hw_exp2(cv.a * (xlog2(l, unit, tm.eps) - cv.mu2)));
+}
+
 template <int SRC>
 __device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, TmArgs tm, Curve cv)
 {
-    constexpr int G = kStatsPxPerThread / group_px(SRC);
+    constexpr int PPU = unit_px(SRC);
+    constexpr int U = kStatsPxPerThread / PPU;
     constexpr int NV = kStatsPxPerThread;
     const TileRef t = tile_ref(im, tile, kStatsChunkPx);
-    float lv[NV];
-    bool valid[NV];
-    tile_lum<SRC, G>(im, t, im.k, lv, valid);
+    const Enc e{1.0f, 255.0f};
+    const bool vec = im.walk != kWalkScalar;
+    if (vec && t.rem >= kStatsChunkPx) {
+        float lv[NV];
+        tile_lum_full<SRC, U>(t, im.k, lv);
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-        lv[i] = hw_rcp(1.0f + hw_exp2(cv.a * (xlog2(lv[i], im.unit, tm.eps) - cv.mu2)));
-    tile_store<SRC, G, false, true>(im, t, t.dst, im.dst_dtype, lv, Enc{1.0f, 255.0f});
+        for (int i = 0; i < NV; ++i)
+            lv[i] = curve(lv[i], im.unit, tm, cv);
+        tile_store_full<SRC, U, false, true>(t.dst, im.dst_dtype, lv, e);
+        return;
+    }
+    const uint32_t rem = (uint32_t)(t.rem < kStatsChunkPx ? t.rem : kStatsChunkPx);
+#pragma unroll 1
+    for (int i = 0; i < NV; ++i) {
+        const uint32_t p = slot_lp<PPU>(vec, i / PPU, i % PPU);
+        if (p < rem)
+            store_px<false, true>(t.dst, im.dst_dtype, p,
+                                  curve(lum_at<SRC>(t, p, im.k), im.unit, tm, cv), e);
+    }
 }
 
+template <int SRC, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
                                                      int nimg, int64_t total_tiles, TmArgs tm,
@@ -714,12 +692,16 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
         const DevImage im = table[i];
         const Curve cv = curves[i];
         const int64_t lt = tile - im.tile_begin;
-        if (im.src_dtype == 0)
-            tm_pass2_tile<0>(im, lt, tm, cv);
-        else if (im.src_dtype == 1)
-            tm_pass2_tile<1>(im, lt, tm, cv);
-        else
-            tm_pass2_tile<2>(im, lt, tm, cv);
+        if constexpr (MIXED) {
+            if (im.src_dtype == 0)
+                tm_pass2_tile<0>(im, lt, tm, cv);
+            else if (im.src_dtype == 1)
+                tm_pass2_tile<1>(im, lt, tm, cv);
+            else
+                tm_pass2_tile<2>(im, lt, tm, cv);
+        } else {
+            tm_pass2_tile<SRC>(im, lt, tm, cv);
+        }
     });
 }
 
@@ -789,10 +771,22 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
 }
 
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, Part *parts, int64_t grid, hipStream_t s)
+                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+                           Part *parts, int64_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tm_pass1, dim3(grid_of(total_tiles, grid)), dim3(kBlock), 0, s, table,
-                       tile_end, nimg, total_tiles, tm, parts);
+    const dim3 g(grid_of(total_tiles, grid));
+    if (mixed_src)
+        hipLaunchKernelGGL((k_tm_pass1<0, true>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, parts);
+    else if (src_dtype == 0)
+        hipLaunchKernelGGL((k_tm_pass1<0, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, parts);
+    else if (src_dtype == 1)
+        hipLaunchKernelGGL((k_tm_pass1<1, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, parts);
+    else
+        hipLaunchKernelGGL((k_tm_pass1<2, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, parts);
     return hipGetLastError();
 }
 
@@ -806,11 +800,22 @@ hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *ti
 }
 
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, TmArgs tm, const Curve *curves, int64_t grid,
-                           hipStream_t s)
+                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+                           const Curve *curves, int64_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tm_pass2, dim3(grid_of(total_tiles, grid)), dim3(kBlock), 0, s, table,
-                       tile_end, nimg, total_tiles, tm, curves);
+    const dim3 g(grid_of(total_tiles, grid));
+    if (mixed_src)
+        hipLaunchKernelGGL((k_tm_pass2<0, true>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, curves);
+    else if (src_dtype == 0)
+        hipLaunchKernelGGL((k_tm_pass2<0, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, curves);
+    else if (src_dtype == 1)
+        hipLaunchKernelGGL((k_tm_pass2<1, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, curves);
+    else
+        hipLaunchKernelGGL((k_tm_pass2<2, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
+                           total_tiles, tm, curves);
     return hipGetLastError();
 }
 

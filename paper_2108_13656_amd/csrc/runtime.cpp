@@ -381,15 +381,15 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
 {
     const int n = (int)h.d.size();
     mark(ctx, marks, 0, st);
-    hipError_t e = dc::launch_tm_pass1(b.table, b.tile_end, n, h.total_tiles, a, b.parts,
-                                       grid_blocks(ctx, t.pass1_gpc), st);
+    hipError_t e = dc::launch_tm_pass1(b.table, b.tile_end, n, h.total_tiles, h.mixed, h.src0, a,
+                                       b.parts, grid_blocks(ctx, t.pass1_gpc), st);
     mark(ctx, marks, 1, st);
     if (e == hipSuccess)
         e = dc::launch_tm_finalize(b.table, n, b.tile_end, a, b.parts, b.curves, stats, st);
     mark(ctx, marks, 2, st);
     if (e == hipSuccess)
-        e = dc::launch_tm_pass2(b.table, b.tile_end, n, h.total_tiles, a, b.curves,
-                                grid_blocks(ctx, t.pass2_gpc), st);
+        e = dc::launch_tm_pass2(b.table, b.tile_end, n, h.total_tiles, h.mixed, h.src0, a,
+                                b.curves, grid_blocks(ctx, t.pass2_gpc), st);
     mark(ctx, marks, 3, st);
     if (e != hipSuccess)
         return hip_fail(e, "tonemap launch");
