@@ -189,14 +189,18 @@ int dc_plan_destroy(dc_plan *plan);
  * groups (48 input bytes each) per thread in a decolorization tile, 1, 2 or 4,
  * per input type (index DC_U8, DC_F16, DC_F32) and for batches mixing input
  * types; *_grid_per_cu: persistent workgroups per compute unit, 0..64, where
- * 0 launches one workgroup per tile. The tone map's statistics chunks are
- * fixed (1024 pixels per partial), so no setting changes any result bit. */
+ * 0 launches one workgroup per tile; tonemap_pipeline 1 runs the tone map
+ * image by image with the curve pass of one image on a second stream beside the
+ * statistics pass of the next. The tone map's statistics chunks are fixed
+ * (1024 pixels per partial, merged in a fixed tree), so no setting changes any
+ * result bit. */
 typedef struct dc_tuning {
     int32_t groups[3];
     int32_t mixed_groups;
     int32_t decolor_grid_per_cu;
     int32_t pass1_grid_per_cu;
     int32_t pass2_grid_per_cu;
+    int32_t tonemap_pipeline; /* 0: each pass over all images; 1: image by image on two streams */
 } dc_tuning;
 
 int dc_get_tuning(dc_ctx *ctx, dc_tuning *out);
@@ -204,7 +208,8 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *tuning);
 
 /* Autotuner: times every candidate launch shape (groups 1/2/4 x grids per CU
  * 0/1/2/4/8/16 for kind DC_PLAN_DECOLORIZE; grids per CU for each tone-map
- * pass for DC_PLAN_TONEMAP) on the given images with HIP events on `stream`
+ * pass, then the two schedules, for DC_PLAN_TONEMAP) on the given images with
+ * HIP events on `stream`
  * (median of 5 runs after a warm-up), keeps the fastest in the context and
  * writes it to *chosen (if not NULL). The candidate runs write the images'
  * outputs. Synchronises `stream`. */
@@ -216,7 +221,8 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
  * every later compute call on ctx records timing events on its stream before
  * and after each kernel it launches: decolorize and decolorize_batch record one
  * interval (the decolorization kernel); tonemap_global records three (the
- * statistics pass, the combine, the curve pass). dc_last_timings waits for the
+ * statistics pass, the two-level combine, the curve pass), or one (the whole
+ * sequence) when the two-stream schedule is selected. dc_last_timings waits for the
  * last such call to finish and writes up to cap interval lengths in
  * milliseconds to ms (host array); it returns how many it wrote, or a negative
  * status. Only the most recent call's intervals are kept. */

@@ -61,13 +61,14 @@ STATS_BYTES = ctypes.sizeof(DcStats)
 class DcTuning(ctypes.Structure):
     _fields_ = [("groups", ctypes.c_int32 * 3), ("mixed_groups", ctypes.c_int32),
                 ("decolor_grid_per_cu", ctypes.c_int32), ("pass1_grid_per_cu", ctypes.c_int32),
-                ("pass2_grid_per_cu", ctypes.c_int32)]
+                ("pass2_grid_per_cu", ctypes.c_int32), ("tonemap_pipeline", ctypes.c_int32)]
 
     def as_dict(self):
         return {"groups": list(self.groups), "mixed_groups": self.mixed_groups,
                 "decolor_grid_per_cu": self.decolor_grid_per_cu,
                 "pass1_grid_per_cu": self.pass1_grid_per_cu,
-                "pass2_grid_per_cu": self.pass2_grid_per_cu}
+                "pass2_grid_per_cu": self.pass2_grid_per_cu,
+                "tonemap_pipeline": self.tonemap_pipeline}
 
     @classmethod
     def from_dict(cls, d):
@@ -78,6 +79,7 @@ class DcTuning(ctypes.Structure):
         t.decolor_grid_per_cu = d["decolor_grid_per_cu"]
         t.pass1_grid_per_cu = d["pass1_grid_per_cu"]
         t.pass2_grid_per_cu = d["pass2_grid_per_cu"]
+        t.tonemap_pipeline = d.get("tonemap_pipeline", 0)
         return t
 
 

@@ -54,6 +54,8 @@ struct DevImage {
     int64_t chunk_begin;    // first statistics partial of this image (tone map)
     int64_t ntiles;         // tiles of this image
     int64_t npx;            // pixels, width * height
+    int64_t grp_begin;      // first level-2 statistics partial of this image
+    int64_t ngrp;           // level-2 partials: ceil(ntiles * kWavesPerBlock / kBlock)
     int32_t src_dtype;
     int32_t dst_dtype;
     int32_t dst2_dtype;     // -1 = none
@@ -92,14 +94,16 @@ hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, h
 hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
                                 int64_t total_tiles, int mixed_src, int src_dtype, int groups,
                                 int64_t grid, hipStream_t s);
-hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            Part *parts, int64_t grid, hipStream_t s);
-hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *tile_end,
-                              TmArgs tm, const Part *parts, Curve *curves, StatsOut *stats,
-                              hipStream_t s);
-hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int img0, int nimg,
+                             int64_t g0, int64_t g1, const Part *parts, Part *parts2,
+                             hipStream_t s);
+hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
+                              const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s);
+hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            const Curve *curves, int64_t grid, hipStream_t s);
 
 } // namespace dc

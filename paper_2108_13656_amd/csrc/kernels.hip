@@ -340,18 +340,19 @@ __device__ __forceinline__ float lum_at(const TileRef &t, uint32_t p, Coef k)
     return lum<SRC>(R, G_, B, k);
 }
 
-// Visits the global tiles of a persistent block (blockIdx.x, blockIdx.x +
-// gridDim.x, ...) with the index of the image that owns each. tile_end is the
-// inclusive prefix sum of the images' tile counts; tiles only grow, so the
-// owner is found once by binary search and then advanced in place.
+// Visits global tiles t0 + blockIdx.x, t0 + blockIdx.x + gridDim.x, ... below
+// t1 with the index of the image that owns each, searching images img0 ..
+// img0 + nimg - 1. tile_end is the inclusive prefix sum of the images' tile
+// counts; tiles only grow, so the owner is found once by binary search and
+// then advanced in place.
 template <typename F>
-__device__ __forceinline__ void for_each_tile(const int64_t *__restrict__ tile_end, int nimg,
-                                              int64_t total_tiles, F &&f)
+__device__ __forceinline__ void for_each_tile(const int64_t *__restrict__ tile_end, int img0,
+                                              int nimg, int64_t t0, int64_t t1, F &&f)
 {
-    int64_t tile = blockIdx.x;
-    if (tile >= total_tiles)
+    int64_t tile = t0 + blockIdx.x;
+    if (tile >= t1)
         return;
-    int lo = 0, hi = nimg - 1;
+    int lo = img0, hi = img0 + nimg - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (tile_end[mid] > tile)
@@ -360,7 +361,7 @@ __device__ __forceinline__ void for_each_tile(const int64_t *__restrict__ tile_e
             lo = mid + 1;
     }
     int i = lo;
-    for (; tile < total_tiles; tile += gridDim.x) {
+    for (; tile < t1; tile += gridDim.x) {
         while (tile_end[i] <= tile)
             ++i;
         f(i, tile);
@@ -431,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__rest
                                                           const int64_t *__restrict__ tile_end,
                                                           int nimg, int64_t total_tiles)
 {
-    for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
+    for_each_tile(tile_end, 0, nimg, 0, total_tiles, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
@@ -581,15 +582,17 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
     }
 }
 
-// MIXED = the input element type varies per image; otherwise it is SRC (one
-// instantiation per type keeps the register count of the uniform case low).
+// Tone-map kernels cover tiles [t0, t1) of images img0 .. img0 + nimg - 1, so
+// one launch can span every image of a call or a single image. MIXED = the
+// input element type varies per image; otherwise it is SRC (one instantiation
+// per type keeps the register count of the uniform case low).
 template <int SRC, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
-                                                     int nimg, int64_t total_tiles, TmArgs tm,
-                                                     Part *__restrict__ parts)
+                                                     int img0, int nimg, int64_t t0, int64_t t1,
+                                                     TmArgs tm, Part *__restrict__ parts)
 {
-    for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
@@ -605,22 +608,56 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict_
     });
 }
 
-// One workgroup per image: fixed-order merge of the image's chunk partials,
-// then the curve coefficients (and optionally the statistics for the caller).
+// Level 1 of the statistics combine: block g merges the fixed group of up to
+// kBlock consecutive wave partials g - grp_begin of its image (one per thread,
+// loaded in parallel) with a fixed LDS tree, and writes one group partial.
+__global__ __launch_bounds__(kBlock) void k_tm_combine(const DevImage *__restrict__ table,
+                                                       const int64_t *__restrict__ grp_end,
+                                                       int img0, int nimg, int64_t g0,
+                                                       const Part *__restrict__ parts,
+                                                       Part *__restrict__ parts2)
+{
+    __shared__ Part sh[kBlock];
+    const int64_t g = g0 + blockIdx.x;
+    int lo = img0, hi = img0 + nimg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (grp_end[mid] > g)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const DevImage im = table[lo];
+    const int64_t nparts = im.ntiles * kWavesPerBlock;
+    const int64_t c = (g - im.grp_begin) * kBlock + threadIdx.x;
+    const int tid = threadIdx.x;
+    sh[tid] = c < nparts ? parts[im.chunk_begin + c] : part_empty();
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] = merge(sh[tid], sh[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0)
+        parts2[g] = sh[0];
+}
+
+// Level 2: one workgroup per image merges the image's group partials in a
+// fixed order, then writes the curve coefficients (and, when asked, the
+// statistics for the caller).
 __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restrict__ table,
-                                                        const int64_t *__restrict__ tile_end,
-                                                        TmArgs tm, const Part *__restrict__ parts,
+                                                        int img0, TmArgs tm,
+                                                        const Part *__restrict__ parts2,
                                                         Curve *__restrict__ curves,
                                                         StatsOut *__restrict__ stats)
 {
     __shared__ Part sh[kBlock];
-    const int img = blockIdx.x;
+    const int img = img0 + blockIdx.x;
     const DevImage im = table[img];
-    const int64_t nch = (tile_end[img] - im.tile_begin) * kWavesPerBlock;
     const int tid = threadIdx.x;
     Part a = part_empty();
-    for (int64_t c = tid; c < nch; c += kBlock)
-        a = merge(a, parts[im.chunk_begin + c]);
+    for (int64_t c = tid; c < im.ngrp; c += kBlock)
+        a = merge(a, parts2[im.grp_begin + c]);
     sh[tid] = a;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
@@ -685,10 +722,10 @@ __device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, 
 template <int SRC, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
-                                                     int nimg, int64_t total_tiles, TmArgs tm,
-                                                     const Curve *__restrict__ curves)
+                                                     int img0, int nimg, int64_t t0, int64_t t1,
+                                                     TmArgs tm, const Curve *__restrict__ curves)
 {
-    for_each_tile(tile_end, nimg, total_tiles, [&](int i, int64_t tile) {
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const Curve cv = curves[i];
         const int64_t lt = tile - im.tile_begin;
@@ -770,52 +807,60 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
     return hipGetLastError();
 }
 
-hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            Part *parts, int64_t grid, hipStream_t s)
 {
-    const dim3 g(grid_of(total_tiles, grid));
+    const dim3 g(grid_of(t1 - t0, grid));
+#define DC_LAUNCH_P1(S, M)                                                                        \
+    hipLaunchKernelGGL((k_tm_pass1<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,     \
+                       t0, t1, tm, parts)
     if (mixed_src)
-        hipLaunchKernelGGL((k_tm_pass1<0, true>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, parts);
+        DC_LAUNCH_P1(0, true);
     else if (src_dtype == 0)
-        hipLaunchKernelGGL((k_tm_pass1<0, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, parts);
+        DC_LAUNCH_P1(0, false);
     else if (src_dtype == 1)
-        hipLaunchKernelGGL((k_tm_pass1<1, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, parts);
+        DC_LAUNCH_P1(1, false);
     else
-        hipLaunchKernelGGL((k_tm_pass1<2, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, parts);
+        DC_LAUNCH_P1(2, false);
+#undef DC_LAUNCH_P1
     return hipGetLastError();
 }
 
-hipError_t launch_tm_finalize(const DevImage *table, int nimg, const int64_t *tile_end,
-                              TmArgs tm, const Part *parts, Curve *curves, StatsOut *stats,
-                              hipStream_t s)
+hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int img0, int nimg,
+                             int64_t g0, int64_t g1, const Part *parts, Part *parts2,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tm_finalize, dim3(nimg), dim3(kBlock), 0, s, table, tile_end, tm, parts,
+    hipLaunchKernelGGL(k_tm_combine, dim3((unsigned)(g1 - g0)), dim3(kBlock), 0, s, table, grp_end,
+                       img0, nimg, g0, parts, parts2);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
+                              const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tm_finalize, dim3(nimg), dim3(kBlock), 0, s, table, img0, tm, parts2,
                        curves, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int nimg,
-                           int64_t total_tiles, int mixed_src, int src_dtype, TmArgs tm,
+hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            const Curve *curves, int64_t grid, hipStream_t s)
 {
-    const dim3 g(grid_of(total_tiles, grid));
+    const dim3 g(grid_of(t1 - t0, grid));
+#define DC_LAUNCH_P2(S, M)                                                                        \
+    hipLaunchKernelGGL((k_tm_pass2<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,     \
+                       t0, t1, tm, curves)
     if (mixed_src)
-        hipLaunchKernelGGL((k_tm_pass2<0, true>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, curves);
+        DC_LAUNCH_P2(0, true);
     else if (src_dtype == 0)
-        hipLaunchKernelGGL((k_tm_pass2<0, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, curves);
+        DC_LAUNCH_P2(0, false);
     else if (src_dtype == 1)
-        hipLaunchKernelGGL((k_tm_pass2<1, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, curves);
+        DC_LAUNCH_P2(1, false);
     else
-        hipLaunchKernelGGL((k_tm_pass2<2, false>), g, dim3(kBlock), 0, s, table, tile_end, nimg,
-                           total_tiles, tm, curves);
+        DC_LAUNCH_P2(2, false);
+#undef DC_LAUNCH_P2
     return hipGetLastError();
 }
 

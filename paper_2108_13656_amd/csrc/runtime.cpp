@@ -228,6 +228,7 @@ struct Tune {
     int decolor_gpc = 0;
     int pass1_gpc = 0;
     int pass2_gpc = 0;
+    int tm_pipeline = 0; // 1 = per-image tone map on two streams
 };
 
 struct dc_ctx {
@@ -243,6 +244,9 @@ struct dc_ctx {
     int device = 0;
     int num_cu = 256;
     Tune tune;
+    // Second stream and fork/join events of the per-image tone-map pipeline.
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> fork;
     Slot slots[kSlots];
     int next = 0;
     // Measurement hooks: timing events recorded around each kernel.
@@ -291,7 +295,9 @@ int64_t grid_blocks(const dc_ctx *ctx, int gpc) { return gpc > 0 ? (int64_t)gpc 
 struct HostTable {
     std::vector<dc::DevImage> d;
     std::vector<int64_t> tile_end;
+    std::vector<int64_t> grp_end; // tone map: inclusive prefix of level-2 partial counts
     int64_t total_tiles = 0;
+    int64_t total_grps = 0;
     bool mixed = false;
     int src0 = 0;
     int groups = 2;  // decolorization only
@@ -303,6 +309,7 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool 
 {
     h.d.resize((size_t)n);
     h.tile_end.resize((size_t)n);
+    h.grp_end.resize((size_t)n);
     h.tonemap = tonemap;
     h.src0 = n > 0 ? imgs[0].src_dtype : 0;
     h.mixed = false;
@@ -320,11 +327,20 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool 
         h.tile_end[i] = total;
     }
     h.total_tiles = total;
+    int64_t grps = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        h.d[i].grp_begin = grps;
+        h.d[i].ngrp = (h.d[i].ntiles * dc::kWavesPerBlock + dc::kBlock - 1) / dc::kBlock;
+        grps += h.d[i].ngrp;
+        h.grp_end[i] = grps;
+    }
+    h.total_grps = tonemap ? grps : 0;
 }
 
-// Byte layout of the device copy: table | tile ends | partials | curves.
+// Byte layout of the device copy: table | tile ends | group ends (uploaded)
+// then the workspace: wave partials | group partials | curves.
 struct Layout {
-    size_t table, ends, parts, curves, upload, total;
+    size_t table, ends, gends, parts, parts2, curves, upload, total;
 };
 
 Layout layout_of(const HostTable &h)
@@ -333,10 +349,12 @@ Layout layout_of(const HostTable &h)
     Layout l;
     l.table = 0;
     l.ends = align_up(sizeof(dc::DevImage) * n, 256);
-    l.parts = l.ends + align_up(sizeof(int64_t) * n, 256);
+    l.gends = l.ends + align_up(sizeof(int64_t) * n, 256);
+    l.parts = l.gends + align_up(sizeof(int64_t) * n, 256);
     l.upload = l.parts;
-    l.curves = l.parts + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_tiles *
+    l.parts2 = l.parts + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_tiles *
                                                    dc::kWavesPerBlock, 256) : 0);
+    l.curves = l.parts2 + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_grps, 256) : 0);
     l.total = l.curves + (h.tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0);
     return l;
 }
@@ -345,12 +363,15 @@ void write_upload(const HostTable &h, const Layout &l, char *dst)
 {
     std::memcpy(dst + l.table, h.d.data(), sizeof(dc::DevImage) * h.d.size());
     std::memcpy(dst + l.ends, h.tile_end.data(), sizeof(int64_t) * h.tile_end.size());
+    std::memcpy(dst + l.gends, h.grp_end.data(), sizeof(int64_t) * h.grp_end.size());
 }
 
 struct DevBufs {
     const dc::DevImage *table;
     const int64_t *tile_end;
+    const int64_t *grp_end;
     dc::Part *parts;
+    dc::Part *parts2;
     dc::Curve *curves;
 };
 
@@ -358,7 +379,8 @@ DevBufs bufs_of(void *dev, const Layout &l)
 {
     char *p = (char *)dev;
     return DevBufs{(const dc::DevImage *)(p + l.table), (const int64_t *)(p + l.ends),
-                   (dc::Part *)(p + l.parts), (dc::Curve *)(p + l.curves)};
+                   (const int64_t *)(p + l.gends), (dc::Part *)(p + l.parts),
+                   (dc::Part *)(p + l.parts2), (dc::Curve *)(p + l.curves)};
 }
 
 // Kernel sequence of a decolorization launch over a staged table.
@@ -375,24 +397,85 @@ int enqueue_decolor(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
     return DC_OK;
 }
 
-// Kernel sequence of a tone map over a staged table.
+// Events for the per-image pipeline: fork[i] marks "statistics pass of image
+// i done" on the main stream; fork[n] marks "side stream done".
+int ensure_fork(dc_ctx *ctx, size_t n)
+{
+    if (!ctx->side) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+    }
+    while (ctx->fork.size() < n + 1) {
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+        ctx->fork.push_back(ev);
+    }
+    return DC_OK;
+}
+
+// Kernel sequence of a tone map over a staged table. Mode 0: the statistics
+// pass over every image, the two-level combine, then the curve pass over every
+// image. Mode 1 (t.tm_pipeline): image by image, the statistics pass runs on
+// the caller's stream and the combine and curve pass of that image on a second
+// stream, so the curve pass of image i overlaps the statistics pass of image
+// i + 1 (and re-reads image i while it is still in the last-level cache).
+// Both modes compute the same values: every kernel's per-image work is fixed.
 int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tune &t,
                     dc::TmArgs a, dc::StatsOut *stats, hipStream_t st, bool marks)
 {
     const int n = (int)h.d.size();
+    const int64_t g1 = grid_blocks(ctx, t.pass1_gpc), g2 = grid_blocks(ctx, t.pass2_gpc);
+    hipError_t e = hipSuccess;
+    if (!t.tm_pipeline || n == 0) {
+        mark(ctx, marks, 0, st);
+        e = dc::launch_tm_pass1(b.table, b.tile_end, 0, n, 0, h.total_tiles, h.mixed, h.src0, a,
+                                b.parts, g1, st);
+        mark(ctx, marks, 1, st);
+        if (e == hipSuccess)
+            e = dc::launch_tm_combine(b.table, b.grp_end, 0, n, 0, h.total_grps, b.parts, b.parts2,
+                                      st);
+        if (e == hipSuccess)
+            e = dc::launch_tm_finalize(b.table, 0, n, a, b.parts2, b.curves, stats, st);
+        mark(ctx, marks, 2, st);
+        if (e == hipSuccess)
+            e = dc::launch_tm_pass2(b.table, b.tile_end, 0, n, 0, h.total_tiles, h.mixed, h.src0, a,
+                                    b.curves, g2, st);
+        mark(ctx, marks, 3, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "tonemap launch");
+        return DC_OK;
+    }
+    int rc = ensure_fork(ctx, (size_t)n);
+    if (rc != DC_OK)
+        return rc;
     mark(ctx, marks, 0, st);
-    hipError_t e = dc::launch_tm_pass1(b.table, b.tile_end, n, h.total_tiles, h.mixed, h.src0, a,
-                                       b.parts, grid_blocks(ctx, t.pass1_gpc), st);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const int64_t t0 = h.d[i].tile_begin, t1 = h.tile_end[i];
+        const int src = h.d[i].src_dtype;
+        e = dc::launch_tm_pass1(b.table, b.tile_end, i, 1, t0, t1, 0, src, a, b.parts, g1, st);
+        if (e == hipSuccess)
+            e = hipEventRecord(ctx->fork[i], st);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(ctx->side, ctx->fork[i], 0);
+        if (e == hipSuccess)
+            e = dc::launch_tm_combine(b.table, b.grp_end, i, 1, h.d[i].grp_begin, h.grp_end[i],
+                                      b.parts, b.parts2, ctx->side);
+        if (e == hipSuccess)
+            e = dc::launch_tm_finalize(b.table, i, 1, a, b.parts2, b.curves, stats, ctx->side);
+        if (e == hipSuccess)
+            e = dc::launch_tm_pass2(b.table, b.tile_end, i, 1, t0, t1, 0, src, a, b.curves, g2,
+                                    ctx->side);
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->fork[n], ctx->side);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(st, ctx->fork[n], 0);
     mark(ctx, marks, 1, st);
-    if (e == hipSuccess)
-        e = dc::launch_tm_finalize(b.table, n, b.tile_end, a, b.parts, b.curves, stats, st);
-    mark(ctx, marks, 2, st);
-    if (e == hipSuccess)
-        e = dc::launch_tm_pass2(b.table, b.tile_end, n, h.total_tiles, h.mixed, h.src0, a,
-                                b.curves, grid_blocks(ctx, t.pass2_gpc), st);
-    mark(ctx, marks, 3, st);
     if (e != hipSuccess)
-        return hip_fail(e, "tonemap launch");
+        return hip_fail(e, "tonemap pipeline launch");
     return DC_OK;
 }
 
@@ -469,7 +552,8 @@ bool tune_ok(const dc_tuning &t)
     auto g_ok = [](int g) { return g == 1 || g == 2 || g == 4; };
     auto c_ok = [](int c) { return c >= 0 && c <= 64; };
     return g_ok(t.groups[0]) && g_ok(t.groups[1]) && g_ok(t.groups[2]) && g_ok(t.mixed_groups) &&
-           c_ok(t.decolor_grid_per_cu) && c_ok(t.pass1_grid_per_cu) && c_ok(t.pass2_grid_per_cu);
+           c_ok(t.decolor_grid_per_cu) && c_ok(t.pass1_grid_per_cu) && c_ok(t.pass2_grid_per_cu) &&
+           (t.tonemap_pipeline == 0 || t.tonemap_pipeline == 1);
 }
 
 dc_tuning to_public(const Tune &t)
@@ -481,6 +565,7 @@ dc_tuning to_public(const Tune &t)
     o.decolor_grid_per_cu = t.decolor_gpc;
     o.pass1_grid_per_cu = t.pass1_gpc;
     o.pass2_grid_per_cu = t.pass2_gpc;
+    o.tonemap_pipeline = t.tm_pipeline;
     return o;
 }
 
@@ -493,6 +578,7 @@ Tune from_public(const dc_tuning &o)
     t.decolor_gpc = o.decolor_grid_per_cu;
     t.pass1_gpc = o.pass1_grid_per_cu;
     t.pass2_gpc = o.pass2_grid_per_cu;
+    t.tm_pipeline = o.tonemap_pipeline;
     return t;
 }
 
@@ -575,7 +661,7 @@ int time_plan(dc_plan *p, hipStream_t st, int reps, std::vector<float> *per_inte
         return ev;
     const bool was = ctx->profiling;
     ctx->profiling = true;
-    const int nint = p->kind == DC_PLAN_TONEMAP ? 3 : 1;
+    const int nint = p->kind == DC_PLAN_TONEMAP && !p->tune.tm_pipeline ? 3 : 1;
     std::vector<std::vector<float>> samples(nint);
     for (int r = 0; r < reps + 1; ++r) {
         int rc = plan_enqueue(p, st, true);
@@ -689,6 +775,10 @@ int dc_destroy(dc_ctx *ctx)
     for (auto &e : ctx->prof)
         if (e)
             (void)hipEventDestroy(e);
+    for (auto &e : ctx->fork)
+        (void)hipEventDestroy(e);
+    if (ctx->side)
+        (void)hipStreamDestroy(ctx->side);
     delete ctx;
     return DC_OK;
 }
@@ -708,7 +798,8 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *t)
     if (!ctx || !t)
         return fail(DC_ERR_INVALID_ARG, "context or tuning is NULL");
     if (!tune_ok(*t))
-        return fail(DC_ERR_INVALID_ARG, "groups must be 1, 2 or 4 and grids per CU in [0, 64]");
+        return fail(DC_ERR_INVALID_ARG, "groups must be 1, 2 or 4, grids per CU in [0, 64] and "
+                                        "tonemap_pipeline 0 or 1");
     ctx->tune = from_public(*t);
     return DC_OK;
 }
@@ -950,6 +1041,7 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
         float b1 = 1e30f, b2 = 1e30f;
         for (int c : gpcs) {
             Tune t = ctx->tune;
+            t.tm_pipeline = 0;
             t.pass1_gpc = c;
             t.pass2_gpc = c;
             rc = run(t, &ms);
@@ -964,6 +1056,19 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 best.pass2_gpc = c;
             }
         }
+        // Whole-sequence time of the two schedules with the chosen grids.
+        float whole[2];
+        for (int pl = 0; pl < 2; ++pl) {
+            Tune t = best;
+            t.tm_pipeline = pl;
+            rc = run(t, &ms);
+            if (rc != DC_OK)
+                return rc;
+            whole[pl] = 0.0f;
+            for (float m : ms)
+                whole[pl] += m;
+        }
+        best.tm_pipeline = whole[1] < whole[0] ? 1 : 0;
     }
     ctx->tune = best;
     if (chosen)

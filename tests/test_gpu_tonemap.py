@@ -159,3 +159,42 @@ def test_autotune_tonemap_keeps_results(dev):
         assert torch.equal(t[0], ref[0]) and torch.equal(st, ref_st)
     finally:
         P.set_tuning(t0)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_two_stream_pipeline_matches_batch_schedule(dev, graph):
+    """The per-image two-stream schedule gives the batch schedule's bits, also
+    when captured into a graph and replayed."""
+    rng = np.random.default_rng(14)
+    imgs = [synth.hdr_pixels(rng, 700, 513), synth.sdr_pixels(rng, 64, 64),
+            synth.hdr_pixels(rng, 1, 4097), synth.sdr_pixels(rng, 333, 1000)]
+    xs = [to_dev(a, dev) for a in imgs]
+    t0 = P.get_tuning()
+    try:
+        P.set_tuning(dict(t0, tonemap_pipeline=0))
+        want, _, want_st = P.tonemap_global(xs, torch.float32, **TM)
+        torch.cuda.synchronize()
+        P.set_tuning(dict(t0, tonemap_pipeline=1, pass1_grid_per_cu=2, pass2_grid_per_cu=4))
+        got, _, got_st = P.tonemap_global(xs, torch.float32, **TM)
+        torch.cuda.synchronize()
+        for a, b in zip(got, want):
+            assert torch.equal(a, b)
+        assert torch.equal(got_st, want_st)
+        outs = [torch.empty(x.shape[:2], device=dev) for x in xs]
+        st = torch.zeros_like(want_st)
+        plan = P.Plan(P.PLAN_TONEMAP, xs, outs, stats=st, graph=graph, **TM)
+        s = torch.cuda.Stream()
+        for rep in range(3):
+            for o in outs:
+                o.fill_(-1.0)
+            st.zero_()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                plan.run(s)
+            s.synchronize()
+            for a, b in zip(outs, want):
+                assert torch.equal(a, b), rep
+            assert torch.equal(st, want_st), rep
+        plan.close()
+    finally:
+        P.set_tuning(t0)
