@@ -38,19 +38,25 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-images", type=int, default=8)
     ap.add_argument("--skip-video", action="store_true")
-    ap.add_argument("--only", choices=["tonemap", "video"], default=None,
+    ap.add_argument("--skip-uneven", action="store_true")
+    ap.add_argument("--only", choices=["tonemap", "video", "uneven"], default=None,
                     help="time one workload only (for profiler runs)")
     ap.add_argument("--tuning", default=None,
                     help="JSON launch shapes to use instead of autotuning (written by --save-tuning)")
     ap.add_argument("--save-tuning", default=None, help="write the autotuned shapes here")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shapes")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
+WORKERS = min(16, os.cpu_count() or 1)
+
+
 def gen_hdr(n, size):
     import synth
-    return [synth.hdr_image(i, shape=(size, size)) for i in range(n)]
+    return synth.hdr_images(count=n, shape=(size, size), workers=WORKERS)
 
 
 def time_steps(fn, steps, warmup, stream):
@@ -115,6 +121,8 @@ def main():
     def tune(kind, *bufs):
         if fixed is not None:
             P.set_tuning(fixed, dev)
+            return P.get_tuning(dev)
+        if args.no_autotune:
             return P.get_tuning(dev)
         t = P.autotune(kind, *bufs, stream=stream)
         saved.update(t)
@@ -209,7 +217,7 @@ def main():
         import synth
         log("generating 64 video frames")
         t0 = time.time()
-        frames = [torch.from_numpy(synth.video_frame(i)).to(dev) for i in range(64)]
+        frames = [torch.from_numpy(f).to(dev) for f in synth.video_frames(workers=WORKERS)]
         log("generated in %.1f s" % (time.time() - t0))
         vpx = sum(f.shape[0] * f.shape[1] for f in frames)
         o8 = [torch.empty(f.shape[:2], dtype=torch.uint8, device=dev) for f in frames]
@@ -257,6 +265,58 @@ def main():
                            "roofline": video["roofline"]})
         else:
             result["video_decolorize"] = video
+    # ---------------------------------------------------- uneven batch decolorize
+    if args.only in (None, "uneven") and not args.skip_uneven:
+        import synth
+        log("generating the uneven 256-image batch")
+        t0 = time.time()
+        imgs = [torch.from_numpy(a).to(dev) for a in synth.uneven_batch(workers=WORKERS)]
+        log("generated in %.1f s" % (time.time() - t0))
+        upx = sum(a.shape[0] * a.shape[1] for a in imgs)
+        ubytes = sum(a.shape[0] * a.shape[1] * (3 * a.element_size() + 4) for a in imgs)
+        uo = [torch.empty(a.shape[:2], dtype=torch.float32, device=dev) for a in imgs]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            utune = tune(P.PLAN_DECOLORIZE, imgs, uo)
+            log("autotuned uneven-batch shape: %s" % utune)
+            uplan = P.Plan(P.PLAN_DECOLORIZE, imgs, uo, graph=True)
+            uplan_ev = P.Plan(P.PLAN_DECOLORIZE, imgs, uo, graph=False)
+            singles = [P.Plan(P.PLAN_DECOLORIZE, [a], [o]) for a, o in zip(imgs, uo)]
+
+            def ustep_single():
+                for sp in singles:
+                    sp.run(stream)
+
+            ums = time_steps(lambda: uplan.run(stream), args.steps, args.warmup, stream)
+            uk = kernel_times(lambda: uplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
+            ums_single = time_steps(ustep_single, max(3, args.steps // 2), 1, stream)
+            for pl in [uplan, uplan_ev] + singles:
+                pl.close()
+        uach = ubytes / (uk * 1e-3) / 1e9
+        uneven = {"workload": "uneven_batch_decolorize", "images": len(imgs), "pixels": upx,
+                  "src": "128 u8 + 128 f16, sides log-uniform 64..4096", "dst": "f32",
+                  "ms_per_step": round(ums, 4), "value": round(upx / (ums * 1e-3) / 1e9, 3),
+                  "unit": "Gpixels/s",
+                  "per_image_launches_gpx": round(upx / (ums_single * 1e-3) / 1e9, 3),
+                  "tuning": {"mixed_groups": utune["mixed_groups"],
+                             "grid_per_cu": utune["decolor_grid_per_cu"]},
+                  "roofline": {"bound": "hbm", "kernel": "decolor_table (mixed)",
+                               "achieved": round(uach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(uach / HBM_PEAK_GBS, 4), "traffic": None}}
+        log("uneven step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %.1f"
+            " Gpx/s" % (ums, uneven["value"], uk, uach, uneven["per_image_launches_gpx"]))
+        if result:
+            result["uneven_batch"] = uneven
+        else:
+            result.update({"metric": METRIC, "value": uneven["value"], "unit": "Gpixels/s",
+                           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                           "ms_per_step": uneven["ms_per_step"], "higher_is_better": True,
+                           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                           "data": "synthetic", "config": {"workload": "uneven_batch_decolorize"},
+                           "roofline": uneven["roofline"]})
+        del imgs, uo
+        torch.cuda.empty_cache()
+
     if args.save_tuning and saved:
         with open(args.save_tuning, "w") as f:
             json.dump(P.get_tuning(dev), f)

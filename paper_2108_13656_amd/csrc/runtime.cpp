@@ -222,12 +222,14 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
 // Launch shapes. groups = vector groups per thread in a decolorization tile
 // (per input type, and one value for batches that mix input types); *_gpc =
 // persistent workgroups per compute unit (0 = one workgroup per tile).
+// Defaults are the shapes the autotuner picked on MI355X for the 64-frame
+// video batch (u8) and the 16 x 4096^2 binary16 tone map.
 struct Tune {
-    int groups[3] = {2, 2, 2};
+    int groups[3] = {1, 2, 2};
     int mixed_groups = 2;
     int decolor_gpc = 0;
-    int pass1_gpc = 0;
-    int pass2_gpc = 0;
+    int pass1_gpc = 16;
+    int pass2_gpc = 16;
     int tm_pipeline = 0; // 1 = per-image tone map on two streams
 };
 

@@ -22,6 +22,8 @@ distributions of the five workloads:
 5. ``serving_trace`` - Poisson arrivals, sizes log-uniform from 256x256 to
    7680x4320, 70 % 8-bit SDR and 30 % binary16 HDR.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 GRADIENT_SEED = 1
@@ -29,6 +31,14 @@ VIDEO_SEED = 2
 HDR_SEED = 3
 UNEVEN_SEED = 4
 SERVING_SEED = 5
+
+
+def _map(fn, items, workers):
+    """fn over items, in order; numpy releases the GIL, so threads overlap."""
+    if workers <= 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
 
 
 def _rng(seed, *spawn_path):
@@ -42,22 +52,20 @@ def hsv_to_rgb8(h_deg, s, v):
     """Hexcone HSV -> RGB in [0, 1], then 8-bit code = floor(255 x + 0.5).
 
     h_deg in degrees [0, 360), s and v in [0, 1]; arrays of equal shape.
+    Uses the closed form of the hexcone model: channel n in {5, 3, 1} (R, G, B)
+    is v - v s max(0, min(k, 4 - k, 1)) with k = (n + h / 60) mod 6.
     Returns uint8 with a trailing axis of 3.
     """
     h6 = np.mod(np.asarray(h_deg, np.float64), 360.0) / 60.0
-    s = np.asarray(s, np.float64)
+    vs = np.asarray(v, np.float64) * np.asarray(s, np.float64)
     v = np.asarray(v, np.float64)
-    sector = np.floor(h6).astype(np.int64) % 6
-    f = h6 - np.floor(h6)
-    p = v * (1.0 - s)
-    q = v * (1.0 - s * f)
-    t = v * (1.0 - s * (1.0 - f))
-    # channel order per sector: (v,t,p) (q,v,p) (p,v,t) (p,q,v) (t,p,v) (v,p,q)
-    r = np.choose(sector, [v, q, p, p, t, v])
-    g = np.choose(sector, [t, v, v, q, p, p])
-    b = np.choose(sector, [p, p, t, v, v, q])
-    rgb = np.stack([r, g, b], axis=-1)
-    return np.minimum(np.floor(rgb * 255.0 + 0.5), 255.0).astype(np.uint8)
+    out = np.empty(h6.shape + (3,), np.uint8)
+    for c, n in enumerate((5.0, 3.0, 1.0)):
+        k = np.mod(n + h6, 6.0)
+        ramp = np.clip(np.minimum(k, 4.0 - k), 0.0, 1.0)
+        x = v - vs * ramp
+        out[..., c] = np.minimum(np.floor(x * 255.0 + 0.5), 255.0)
+    return out
 
 
 # --------------------------------------------------------------- workload 1
@@ -100,8 +108,8 @@ def video_frame(index, seed=VIDEO_SEED):
     return sdr_pixels(_rng(seed, index), h, w)
 
 
-def video_frames(seed=VIDEO_SEED, count=64):
-    return [video_frame(i, seed) for i in range(count)]
+def video_frames(seed=VIDEO_SEED, count=64, workers=1):
+    return _map(lambda i: video_frame(i, seed), range(count), workers)
 
 
 # --------------------------------------------------------------- workload 3
@@ -124,8 +132,8 @@ def hdr_image(index, seed=HDR_SEED, shape=HDR_SHAPE):
     return hdr_pixels(_rng(seed, index), h, w)
 
 
-def hdr_images(seed=HDR_SEED, count=16, shape=HDR_SHAPE):
-    return [hdr_image(i, seed, shape) for i in range(count)]
+def hdr_images(seed=HDR_SEED, count=16, shape=HDR_SHAPE, workers=1):
+    return _map(lambda i: hdr_image(i, seed, shape), range(count), workers)
 
 
 # --------------------------------------------------------------- workload 4
@@ -141,13 +149,17 @@ def uneven_shapes(seed=UNEVEN_SEED, count=256, lo=64, hi=4096):
     return shapes
 
 
-def uneven_batch(seed=UNEVEN_SEED, count=256, lo=64, hi=4096):
+def uneven_image(i, shape, seed=UNEVEN_SEED):
+    """Image i of the uneven batch: even index 8-bit SDR, odd index binary16 HDR."""
+    h, w = shape
+    rng = _rng(seed, 1, i)
+    return sdr_pixels(rng, h, w) if i % 2 == 0 else hdr_pixels(rng, h, w)
+
+
+def uneven_batch(seed=UNEVEN_SEED, count=256, lo=64, hi=4096, workers=1):
     """List of images: even index 8-bit SDR, odd index binary16 HDR."""
-    imgs = []
-    for i, (h, w) in enumerate(uneven_shapes(seed, count, lo, hi)):
-        rng = _rng(seed, 1, i)
-        imgs.append(sdr_pixels(rng, h, w) if i % 2 == 0 else hdr_pixels(rng, h, w))
-    return imgs
+    shapes = uneven_shapes(seed, count, lo, hi)
+    return _map(lambda i: uneven_image(i, shapes[i], seed), range(count), workers)
 
 
 # --------------------------------------------------------------- workload 5

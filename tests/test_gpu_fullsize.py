@@ -1,0 +1,127 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times: autotuned launch shapes and a HIP-graph plan over resident buffers.
+
+- 64-frame video batch (32 x 1920x1080 + 32 x 3840x2160, 8-bit): every pixel of
+  both outputs (8-bit and FP32) against the oracle's value of its colour (the
+  oracle's table of all 2^24 colours, computed by the FP64 oracle).
+- 16 x 4096^2 binary16 tone map: every image's statistics against the FP64
+  oracle over all its pixels, and T at 65536 sampled pixels per image against
+  the oracle's curve evaluated with the oracle's own statistics.
+- uneven batch of 256 images (half 8-bit, half binary16, 64..4096 per side),
+  one persistent launch: every pixel against the oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2108_13656_amd as P
+import synth
+from gpuhelp import check_f32, check_u8, need_gpu, report, to_dev
+
+pytestmark = pytest.mark.gpu
+WORKERS = min(16, os.cpu_count() or 1)
+TM = dict(eps=1e-4, contrast=2.0, sigma_floor=1e-3)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+@pytest.fixture(scope="module")
+def lut():
+    return oracle.all_colours(0.55, 0.8)
+
+
+def _run_plan(kind, xs, outs, outs2=None, **kw):
+    t0 = P.get_tuning()
+    try:
+        chosen = P.autotune(kind, xs, outs, outs2, **{k: v for k, v in kw.items() if k in TM})
+        report("autotuned: %s" % chosen)
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        plan = P.Plan(kind, xs, outs, outs2, graph=True, **kw)
+        with torch.cuda.stream(s):
+            plan.run(s)
+        s.synchronize()
+        plan.close()
+    finally:
+        P.set_tuning(t0)
+
+
+def _codes(img):
+    c = img.astype(np.int64)
+    return (c[..., 0] << 16) | (c[..., 1] << 8) | c[..., 2]
+
+
+@pytest.mark.timeout(600)
+def test_video_batch_every_pixel(dev, lut):
+    frames = synth.video_frames(workers=WORKERS)
+    xs = [to_dev(f, dev) for f in frames]
+    o8 = [torch.empty(f.shape[:2], dtype=torch.uint8, device=dev) for f in frames]
+    o32 = [torch.empty(f.shape[:2], dtype=torch.float32, device=dev) for f in frames]
+    _run_plan(P.PLAN_DECOLORIZE, xs, o8, o32)
+    worst, off, total = 0.0, 0, 0
+    for f, a, b in zip(frames, o8, o32):
+        want = lut[_codes(f)]
+        err = np.abs(b.cpu().numpy().astype(np.float64) - want / 255.0)
+        worst = max(worst, float(err.max()))
+        d = np.abs(a.cpu().numpy().astype(np.int32) - oracle.encode_u8(want / 255.0).astype(np.int32))
+        assert d.max() <= 1
+        off += int(np.count_nonzero(d))
+        total += d.size
+    report("video batch: %d px, max |dL| %.3e, u8 codes off by one: %d (fraction %.3e)" %
+           (total, worst, off, off / total))
+    assert worst <= 1e-5
+    assert off / total <= 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_hdr_tonemap_full(dev):
+    imgs = synth.hdr_images(workers=WORKERS)
+    xs = [to_dev(a, dev) for a in imgs]
+    outs = [torch.empty(a.shape[:2], dtype=torch.float32, device=dev) for a in imgs]
+    stats = torch.zeros((len(imgs), P.STATS_BYTES), dtype=torch.uint8, device=dev)
+    _run_plan(P.PLAN_TONEMAP, xs, outs, stats=stats, **TM)
+    st = P.stats_to_host(stats)
+    rng = np.random.default_rng(99)
+    worst_t, worst_mu, worst_sig = 0.0, 0.0, 0.0
+    for i, img in enumerate(imgs):
+        lhat = oracle.decolorize(img, nthreads=WORKERS)
+        ref = oracle.tonemap_stats(lhat, TM["eps"])
+        worst_mu = max(worst_mu, abs(st[i]["mu"] - ref["mu"]))
+        worst_sig = max(worst_sig, abs(st[i]["sigma"] - ref["sigma"]) / ref["sigma"])
+        assert st[i]["count"] == ref["count"]
+        assert st[i]["l_min"] == pytest.approx(ref["l_min"], rel=1e-5)
+        assert st[i]["l_max"] == pytest.approx(ref["l_max"], rel=1e-5)
+        idx = rng.integers(0, lhat.size, 65536)
+        t_ref = oracle.tonemap_curve(lhat.ravel()[idx], ref["mu"], ref["sigma"], **TM)
+        t_gpu = outs[i].view(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        worst_t = max(worst_t, float(np.max(np.abs(t_gpu - t_ref))))
+    report("hdr tone map 16x4096^2: max |d mu| %.2e, max |d sigma|/sigma %.2e, max |dT| %.2e "
+           "(65536 sampled px per image)" % (worst_mu, worst_sig, worst_t))
+    assert worst_mu <= 2e-5 and worst_sig <= 2e-5 and worst_t <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_uneven_batch_every_pixel(dev, lut):
+    imgs = synth.uneven_batch(workers=WORKERS)
+    xs = [to_dev(a, dev) for a in imgs]
+    outs = [torch.empty(a.shape[:2], dtype=torch.float32, device=dev) for a in imgs]
+    _run_plan(P.PLAN_DECOLORIZE, xs, outs)
+    worst8, worst16 = 0.0, 0.0
+    for img, o in zip(imgs, outs):
+        got = o.cpu().numpy().astype(np.float64)
+        if img.dtype == np.uint8:
+            worst8 = max(worst8, float(np.max(np.abs(got - lut[_codes(img)] / 255.0))))
+        else:
+            want = oracle.decolorize(img, nthreads=WORKERS)
+            worst16 = max(worst16, float(np.max(np.abs(got - want) / np.maximum(1.0, want))))
+    report("uneven batch: %d px, max |dL| u8 %.3e, f16 scaled %.3e" %
+           (sum(a.shape[0] * a.shape[1] for a in imgs), worst8, worst16))
+    assert worst8 <= 1e-5 and worst16 <= 1e-5
