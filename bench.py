@@ -39,7 +39,12 @@ def parse():
     ap.add_argument("--cpu-sample-images", type=int, default=8)
     ap.add_argument("--skip-video", action="store_true")
     ap.add_argument("--skip-uneven", action="store_true")
-    ap.add_argument("--only", choices=["tonemap", "video", "uneven"], default=None,
+    ap.add_argument("--no-per-image", action="store_true",
+                    help="skip the per-image-launch comparison (profiler runs)")
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--requests", type=int, default=10000, help="serving trace length")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="serving memory budget")
+    ap.add_argument("--only", choices=["tonemap", "video", "uneven", "serve"], default=None,
                     help="time one workload only (for profiler runs)")
     ap.add_argument("--tuning", default=None,
                     help="JSON launch shapes to use instead of autotuning (written by --save-tuning)")
@@ -86,6 +91,74 @@ def kernel_times(fn, reps, P, dev):
     P.set_profiling(False, dev)
     torch.cuda.synchronize()
     return [a / reps for a in acc]
+
+
+def serve_leg(args, P, dev):
+    """Poisson trace through the native continuous-batching server: saturated
+    throughput first, then arrivals at 0.7 of it; FIFO one-image-per-launch
+    baseline on the same trace."""
+    import torch
+    import synth
+    log("serving: building device-resident source pools")
+    rng = np.random.default_rng(synth.SERVING_SEED)
+    pool_bytes = 2 << 30
+    pools = {}
+    for fmt, base, dt in (("u8", synth.sdr_pixels(rng, 4096, 4096), P.DC_U8),
+                          ("f16", synth.hdr_pixels(rng, 4096, 4096), P.DC_F16)):
+        flat = torch.from_numpy(base).to(dev).view(-1)
+        reps = -(-pool_bytes // (flat.numel() * flat.element_size()))
+        pool = flat.repeat(reps)
+        pools[fmt] = (pool, dt, 3 * pool.element_size(), pool.numel() // 3)
+    trace = synth.serving_trace(n_requests=args.requests, rate_per_s=1.0)
+    reqs, px = [], []
+    for r in trace:
+        pool, dt, bpp, npx = pools[r["fmt"]]
+        n = r["w"] * r["h"]
+        off = int(rng.integers(0, (npx - n) // 16)) * 16
+        reqs.append(P.make_request(r["id"], pool.data_ptr() + off * bpp, dt, r["w"], r["h"],
+                                   r["w"] * bpp, P.DC_U8 if r["fmt"] == "u8" else P.DC_F32))
+        px.append(n)
+    px = np.array(px, np.float64)
+    unit_arrivals = np.array([r["arrival"] for r in trace])
+    budget = int(args.budget_gib * (1 << 30))
+    torch.cuda.synchronize()
+
+    def run(max_batch, max_inflight, arrivals):
+        srv = P.Server(budget, max_batch=max_batch, max_inflight=max_inflight, device=dev)
+        srv.replay(reqs[:64], [0.0] * 64)  # warm-up (workspace growth)
+        done = srv.replay(reqs, list(arrivals))
+        srv.close()
+        ok = [c for c in done if c.status == P.DC_OK]
+        lat = np.array([c.t_done - c.t_submit for c in ok])
+        t_first = min(c.t_submit for c in done)
+        t_last = max(c.t_done for c in done)
+        sizes = np.array([c.batch_size for c in ok])
+        return {"gpx_s": round(float(px.sum()) / (t_last - t_first) / 1e9, 2),
+                "p50_ms": round(1e3 * float(np.median(lat)), 3),
+                "p99_ms": round(1e3 * float(np.quantile(lat, 0.99)), 3),
+                "mean_batch": round(float(sizes.mean()), 2), "rejected": len(done) - len(ok),
+                "wall_s": round(t_last - t_first, 4)}
+
+    sat = run(64, 4, np.zeros(len(reqs)))
+    rate = 0.7 * sat["gpx_s"] * 1e9 / px.mean()
+    arrivals = unit_arrivals / rate
+    served = run(64, 4, arrivals)
+    fifo = run(1, 1, arrivals)
+    out = {"workload": "serving_tonemap", "requests": len(reqs),
+           "mix": "70% u8 SDR -> u8 T, 30% f16 HDR -> f32 T",
+           "sizes": "w log-uniform 256..7680, h log-uniform 256..4320",
+           "mean_mpx": round(px.mean() / 1e6, 3), "budget_gib": args.budget_gib,
+           "saturated_gpx_s": sat["gpx_s"], "rate_req_s": round(rate, 1),
+           "gpx_s": served["gpx_s"], "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
+           "mean_batch": served["mean_batch"], "rejected": served["rejected"],
+           "fifo_per_image": fifo}
+    log("serving: saturated %.1f Gpx/s; at %.0f req/s: %.1f Gpx/s p50 %.3f ms p99 %.3f ms "
+        "(mean batch %.1f); FIFO per-image: %.1f Gpx/s p50 %.3f ms p99 %.3f ms" %
+        (sat["gpx_s"], rate, served["gpx_s"], served["p50_ms"], served["p99_ms"],
+         served["mean_batch"], fifo["gpx_s"], fifo["p50_ms"], fifo["p99_ms"]))
+    del pools
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -238,7 +311,8 @@ def main():
 
             vms = time_steps(lambda: vplan.run(stream), args.steps, args.warmup, stream)
             vk = kernel_times(lambda: vplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
-            vms_single = time_steps(vstep_single, max(3, args.steps // 2), 1, stream)
+            vms_single = None if args.no_per_image else \
+                time_steps(vstep_single, max(3, args.steps // 2), 1, stream)
             vplan.close()
             vplan_ev.close()
             for sp in singles:
@@ -248,13 +322,14 @@ def main():
         video = {"workload": "video_decolorize", "frames": "32x1920x1080 + 32x3840x2160",
                  "src": "u8 sRGB", "dst": "u8 + f32", "ms_per_step": round(vms, 4),
                  "value": round(vpx / (vms * 1e-3) / 1e9, 3), "unit": "Gpixels/s",
-                 "per_image_launches_gpx": round(vpx / (vms_single * 1e-3) / 1e9, 3),
+                 "per_image_launches_gpx": round(vpx / (vms_single * 1e-3) / 1e9, 3)
+                 if vms_single else None,
                  "tuning": {"groups_u8": vtune["groups"][0],
                             "grid_per_cu": vtune["decolor_grid_per_cu"]},
                  "roofline": {"bound": "hbm", "kernel": "decolor_table", "achieved": round(vach, 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(vach / HBM_PEAK_GBS, 4), "traffic": None}}
-        log("video step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %.3f "
+        log("video step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %s "
             "Gpx/s" % (vms, video["value"], vk, vach, video["per_image_launches_gpx"]))
         if not result:
             result.update({"metric": METRIC, "value": video["value"], "unit": "Gpixels/s",
@@ -289,7 +364,8 @@ def main():
 
             ums = time_steps(lambda: uplan.run(stream), args.steps, args.warmup, stream)
             uk = kernel_times(lambda: uplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
-            ums_single = time_steps(ustep_single, max(3, args.steps // 2), 1, stream)
+            ums_single = None if args.no_per_image else \
+                time_steps(ustep_single, max(3, args.steps // 2), 1, stream)
             for pl in [uplan, uplan_ev] + singles:
                 pl.close()
         uach = ubytes / (uk * 1e-3) / 1e9
@@ -297,13 +373,14 @@ def main():
                   "src": "128 u8 + 128 f16, sides log-uniform 64..4096", "dst": "f32",
                   "ms_per_step": round(ums, 4), "value": round(upx / (ums * 1e-3) / 1e9, 3),
                   "unit": "Gpixels/s",
-                  "per_image_launches_gpx": round(upx / (ums_single * 1e-3) / 1e9, 3),
+                  "per_image_launches_gpx": round(upx / (ums_single * 1e-3) / 1e9, 3)
+                  if ums_single else None,
                   "tuning": {"mixed_groups": utune["mixed_groups"],
-                             "grid_per_cu": utune["decolor_grid_per_cu"]},
+                             "grid_per_cu": utune["mixed_grid_per_cu"]},
                   "roofline": {"bound": "hbm", "kernel": "decolor_table (mixed)",
                                "achieved": round(uach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(uach / HBM_PEAK_GBS, 4), "traffic": None}}
-        log("uneven step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %.1f"
+        log("uneven step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %s"
             " Gpx/s" % (ums, uneven["value"], uk, uach, uneven["per_image_launches_gpx"]))
         if result:
             result["uneven_batch"] = uneven
@@ -316,6 +393,18 @@ def main():
                            "roofline": uneven["roofline"]})
         del imgs, uo
         torch.cuda.empty_cache()
+
+    # ---------------------------------------------------- serving loop
+    if args.only in (None, "serve") and not args.skip_serve:
+        result_serve = serve_leg(args, P, dev)
+        if result:
+            result["serving"] = result_serve
+        else:
+            result.update({"metric": METRIC, "value": result_serve["gpx_s"], "unit": "Gpixels/s",
+                           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None,
+                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                           "dtype": "f32", "data": "synthetic",
+                           "config": {"workload": "serving_tonemap"}, "serving": result_serve})
 
     if args.save_tuning and saved:
         with open(args.save_tuning, "w") as f:

@@ -197,7 +197,8 @@ int dc_plan_destroy(dc_plan *plan);
 typedef struct dc_tuning {
     int32_t groups[3];
     int32_t mixed_groups;
-    int32_t decolor_grid_per_cu;
+    int32_t decolor_grid_per_cu;  /* batches of one input type */
+    int32_t mixed_grid_per_cu;    /* batches mixing input types */
     int32_t pass1_grid_per_cu;
     int32_t pass2_grid_per_cu;
     int32_t tonemap_pipeline; /* 0: each pass over all images; 1: image by image on two streams */
@@ -209,13 +210,78 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *tuning);
 /* Autotuner: times every candidate launch shape (groups 1/2/4 x grids per CU
  * 0/1/2/4/8/16 for kind DC_PLAN_DECOLORIZE; grids per CU for each tone-map
  * pass, then the two schedules, for DC_PLAN_TONEMAP) on the given images with
- * HIP events on `stream`
- * (median of 5 runs after a warm-up), keeps the fastest in the context and
+ * HIP events on `stream` (fastest of 10 runs after a warm-up), keeps the best
+ * in the context (the fields of the given batch's class only) and
  * writes it to *chosen (if not NULL). The candidate runs write the images'
  * outputs. Synchronises `stream`. */
 int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 const dc_params *params, const dc_tm_params *tm, void *stream,
                 dc_tuning *chosen);
+
+/* -------------------------------------------------------------- serving
+ * Continuous-batching server for the global tone map of single-image requests
+ * of any size and element type (each request: decolorization + statistics +
+ * curve). Requests wait in FIFO order and are admitted when their output fits
+ * the server's device-memory budget (a first-fit arena allocated once at
+ * creation); whenever one of max_inflight launch lanes (each its own stream) is
+ * idle, every admitted request, up to max_batch, goes into one launch on it;
+ * when a launch's completion event fires its requests complete and their
+ * memory returns to the budget, admitting more. Work of different lanes
+ * overlaps on the device. Each request's result is bit-identical to
+ * dc_tonemap_global on that image alone (the statistics of an image never
+ * depend on its batch). Not thread-safe; one host thread drives a server. */
+typedef struct dc_server dc_server;
+
+typedef struct dc_server_config {
+    int64_t budget_bytes;  /* device bytes for server-allocated outputs, > 0 */
+    int32_t max_batch;     /* images per launch, >= 1 */
+    int32_t max_inflight;  /* launch lanes, 1..8 */
+    int32_t flags;         /* reserved, 0 */
+    dc_params params;      /* Eqs. (3), (6) weights */
+    dc_tm_params tm;       /* tone curve */
+} dc_server_config;
+
+/* One request. img.src (DEVICE), size, src_dtype and dst_dtype as in
+ * dc_image; dst2 must be NULL (dst2_dtype DC_NONE). With img.dst NULL the
+ * server allocates the output (rows padded to 16 bytes) from its budget and
+ * frees it when the request completes (the output is not kept); with img.dst
+ * set (caller memory, dst_pitch given) the output stays there and takes no
+ * budget. */
+typedef struct dc_request {
+    int64_t id;
+    dc_image img;
+} dc_request;
+
+/* A finished request. Times are seconds on the server clock (dc_server_clock):
+ * submitted (for replays: the scheduled arrival), admitted, launched, and the
+ * step that saw its launch complete. status is DC_OK, or DC_ERR_NO_MEMORY for a
+ * request whose output is larger than the whole budget (rejected at once). */
+typedef struct dc_completion {
+    int64_t id;
+    int32_t status;
+    int32_t batch_size;
+    double t_submit, t_admit, t_launch, t_done;
+} dc_completion;
+
+int dc_server_create(dc_ctx *ctx, const dc_server_config *cfg, dc_server **server);
+/* Waits for the server's lanes and frees its arena. NULL is a no-op. */
+int dc_server_destroy(dc_server *server);
+/* Queues n HOST request descriptors (copied); t_submit < 0 means now. Each is
+ * checked like dc_validate (its input part, and its output when given). */
+int dc_server_submit(dc_server *server, const dc_request *reqs, int32_t n, double t_submit);
+/* Non-blocking: retires finished launches, admits what fits, launches on idle
+ * lanes. Returns the number of requests still queued or running (>= 0), or
+ * a negative status. */
+int dc_server_step(dc_server *server);
+/* Moves up to cap completions (oldest first) into out (HOST); returns the count. */
+int dc_server_poll(dc_server *server, dc_completion *out, int32_t cap);
+double dc_server_clock(dc_server *server);
+/* Trace replay: submits reqs[i] when arrival_s[i] (seconds from the call,
+ * non-decreasing) has passed, stepping the server in a busy loop until all n
+ * have completed; out (HOST, n entries) receives the completions in the
+ * order they finished. */
+int dc_server_replay(dc_server *server, const dc_request *reqs, const double *arrival_s,
+                     int32_t n, dc_completion *out);
 
 /* Measurement hooks (instrumentation, not part of the method). With on != 0,
  * every later compute call on ctx records timing events on its stream before

@@ -60,12 +60,14 @@ STATS_BYTES = ctypes.sizeof(DcStats)
 
 class DcTuning(ctypes.Structure):
     _fields_ = [("groups", ctypes.c_int32 * 3), ("mixed_groups", ctypes.c_int32),
-                ("decolor_grid_per_cu", ctypes.c_int32), ("pass1_grid_per_cu", ctypes.c_int32),
+                ("decolor_grid_per_cu", ctypes.c_int32), ("mixed_grid_per_cu", ctypes.c_int32),
+                ("pass1_grid_per_cu", ctypes.c_int32),
                 ("pass2_grid_per_cu", ctypes.c_int32), ("tonemap_pipeline", ctypes.c_int32)]
 
     def as_dict(self):
         return {"groups": list(self.groups), "mixed_groups": self.mixed_groups,
                 "decolor_grid_per_cu": self.decolor_grid_per_cu,
+                "mixed_grid_per_cu": self.mixed_grid_per_cu,
                 "pass1_grid_per_cu": self.pass1_grid_per_cu,
                 "pass2_grid_per_cu": self.pass2_grid_per_cu,
                 "tonemap_pipeline": self.tonemap_pipeline}
@@ -77,6 +79,7 @@ class DcTuning(ctypes.Structure):
             t.groups[i] = g
         t.mixed_groups = d["mixed_groups"]
         t.decolor_grid_per_cu = d["decolor_grid_per_cu"]
+        t.mixed_grid_per_cu = d.get("mixed_grid_per_cu", 4)
         t.pass1_grid_per_cu = d["pass1_grid_per_cu"]
         t.pass2_grid_per_cu = d["pass2_grid_per_cu"]
         t.tonemap_pipeline = d.get("tonemap_pipeline", 0)
@@ -84,6 +87,22 @@ class DcTuning(ctypes.Structure):
 
 
 PLAN_DECOLORIZE, PLAN_TONEMAP, PLAN_GRAPH = 0, 1, 1
+
+
+class DcServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("params", DcParams), ("tm", DcTmParams)]
+
+
+class DcRequest(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("img", DcImage)]
+
+
+class DcCompletion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class DecolorError(RuntimeError):
@@ -125,12 +144,23 @@ def lib():
     L.dc_get_tuning.argtypes = [vp, tun_p]
     L.dc_set_tuning.argtypes = [vp, tun_p]
     L.dc_autotune.argtypes = [vp, i32, img_p, i32, par_p, tm_p, vp, tun_p]
+    req_p = ctypes.POINTER(DcRequest)
+    comp_p = ctypes.POINTER(DcCompletion)
+    L.dc_server_create.argtypes = [vp, ctypes.POINTER(DcServerConfig), ctypes.POINTER(vp)]
+    L.dc_server_destroy.argtypes = [vp]
+    L.dc_server_submit.argtypes = [vp, req_p, i32, ctypes.c_double]
+    L.dc_server_step.argtypes = [vp]
+    L.dc_server_poll.argtypes = [vp, comp_p, i32]
+    L.dc_server_clock.argtypes = [vp]
+    L.dc_server_clock.restype = ctypes.c_double
+    L.dc_server_replay.argtypes = [vp, req_p, ctypes.POINTER(ctypes.c_double), i32, comp_p]
     L.dc_set_profiling.argtypes = [vp, ctypes.c_int]
     L.dc_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     for name in ("dc_create", "dc_destroy", "dc_validate", "dc_decolorize", "dc_decolorize_batch",
                  "dc_tonemap_global", "dc_version", "dc_set_profiling", "dc_last_timings",
                  "dc_plan_create", "dc_plan_run", "dc_plan_destroy", "dc_get_tuning",
-                 "dc_set_tuning", "dc_autotune"):
+                 "dc_set_tuning", "dc_autotune", "dc_server_create", "dc_server_destroy",
+                 "dc_server_submit", "dc_server_step", "dc_server_poll", "dc_server_replay"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -364,6 +394,87 @@ class Plan:
     def close(self):
         if self._h:
             lib().dc_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_request(rid, src, src_dtype, width, height, src_pitch, dst_dtype, dst=None, dst_pitch=0):
+    """A DcRequest for a device image given by raw pointer (dst None: the
+    server allocates and frees the output)."""
+    r = DcRequest()
+    r.id = rid
+    r.img.src = src
+    r.img.src_pitch = src_pitch
+    r.img.width, r.img.height = width, height
+    r.img.src_dtype = src_dtype
+    r.img.dst = dst
+    r.img.dst_pitch = dst_pitch
+    r.img.dst_dtype = dst_dtype
+    r.img.dst2, r.img.dst2_pitch, r.img.dst2_dtype, r.img.flags = None, 0, DC_NONE, 0
+    return r
+
+
+def request_for(rid, x, out=None, out_dtype=torch.float32):
+    """A DcRequest for an HxWx3 device tensor (and an optional HxW output)."""
+    _check_rgb(x)
+    if out is not None:
+        _check_gray(out, x.shape[0], x.shape[1], x.device)
+    return make_request(rid, x.data_ptr(), _dc_dtype(x.dtype), x.shape[1], x.shape[0],
+                        x.stride(0) * x.element_size(),
+                        _dc_dtype(out.dtype if out is not None else out_dtype),
+                        None if out is None else out.data_ptr(),
+                        0 if out is None else out.stride(0) * out.element_size())
+
+
+class Server:
+    """Continuous-batching tone-map server (``dc_server_*``)."""
+
+    def __init__(self, budget_bytes, max_batch=64, max_inflight=4, beta_r=BETA_R, beta_k=BETA_K,
+                 eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        cfg = DcServerConfig(budget_bytes, max_batch, max_inflight, 0, DcParams(beta_r, beta_k),
+                             DcTmParams(eps, contrast, sigma_floor))
+        self._h = ctypes.c_void_p()
+        _check(lib().dc_server_create(context(self.device).handle, ctypes.byref(cfg),
+                                      ctypes.byref(self._h)))
+
+    def submit(self, reqs, t_submit=-1.0):
+        arr = (DcRequest * len(reqs))(*reqs)
+        _check(lib().dc_server_submit(self._h, arr, len(reqs), t_submit))
+
+    def step(self):
+        n = lib().dc_server_step(self._h)
+        if n < 0:
+            _check(n)
+        return n
+
+    def poll(self, cap=4096):
+        buf = (DcCompletion * cap)()
+        n = lib().dc_server_poll(self._h, buf, cap)
+        if n < 0:
+            _check(n)
+        return [buf[i] for i in range(n)]
+
+    def clock(self):
+        return lib().dc_server_clock(self._h)
+
+    def replay(self, reqs, arrivals):
+        """Replays a trace natively; returns the completions in finishing order."""
+        n = len(reqs)
+        arr = (DcRequest * n)(*reqs)
+        times = (ctypes.c_double * n)(*arrivals)
+        out = (DcCompletion * n)()
+        _check(lib().dc_server_replay(self._h, arr, times, n, out))
+        return [out[i] for i in range(n)]
+
+    def close(self):
+        if self._h:
+            lib().dc_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

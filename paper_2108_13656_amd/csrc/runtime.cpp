@@ -5,9 +5,12 @@
 #include "dc_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -68,6 +71,26 @@ int validate_tm(const dc_tm_params *tm)
     return DC_OK;
 }
 
+// Checks of the input half of a descriptor; fills its byte extent.
+int check_src(const dc_image &m, const std::string &at, Range &r)
+{
+    if (!m.src)
+        return fail(DC_ERR_INVALID_ARG, "src must not be NULL" + at);
+    if (m.width < 1 || m.height < 1)
+        return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + at);
+    if (!dtype_ok(m.src_dtype))
+        return fail(DC_ERR_INVALID_ARG, "src_dtype must be DC_U8, DC_F16 or DC_F32" + at);
+    const int64_t es = dc::elem_size(m.src_dtype);
+    const int64_t row_in = 3 * es * (int64_t)m.width;
+    if (m.src_pitch < row_in)
+        return fail(DC_ERR_INVALID_ARG, "src_pitch is smaller than 3 * width * element size" + at);
+    if ((uintptr_t)m.src % es || m.src_pitch % es)
+        return fail(DC_ERR_INVALID_ARG, "src and src_pitch must be multiples of the element size" + at);
+    if (!extent(m.src, m.src_pitch, row_in, m.height, r))
+        return fail(DC_ERR_INVALID_ARG, "src extent overflows" + at);
+    return DC_OK;
+}
+
 int validate_images(const dc_image *imgs, int32_t n)
 {
     if (n < 0)
@@ -97,15 +120,10 @@ int validate_images(const dc_image *imgs, int32_t n)
             if (!m.dst2)
                 return fail(DC_ERR_INVALID_ARG, "dst2 is NULL but dst2_dtype is set" + at);
         }
-        const int64_t es = dc::elem_size(m.src_dtype);
-        const int64_t row_in = 3 * es * (int64_t)m.width;
-        if (m.src_pitch < row_in)
-            return fail(DC_ERR_INVALID_ARG, "src_pitch is smaller than 3 * width * element size" + at);
-        if ((uintptr_t)m.src % es || m.src_pitch % es)
-            return fail(DC_ERR_INVALID_ARG, "src and src_pitch must be multiples of the element size" + at);
         Range r;
-        if (!extent(m.src, m.src_pitch, row_in, m.height, r))
-            return fail(DC_ERR_INVALID_ARG, "src extent overflows" + at);
+        const int src_rc = check_src(m, at, r);
+        if (src_rc != DC_OK)
+            return src_rc;
         r.image = i;
         r.kind = 0;
         ins.push_back(r);
@@ -226,15 +244,16 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
 // video batch (u8) and the 16 x 4096^2 binary16 tone map.
 struct Tune {
     int groups[3] = {1, 2, 2};
-    int mixed_groups = 2;
+    int mixed_groups = 1;
     int decolor_gpc = 0;
+    int mixed_gpc = 4;
     int pass1_gpc = 16;
     int pass2_gpc = 16;
     int tm_pipeline = 0; // 1 = per-image tone map on two streams
 };
 
 struct dc_ctx {
-    static constexpr int kSlots = 8;
+    static constexpr int kSlots = 16;
     struct Slot {
         void *host = nullptr;  // pinned staging of the descriptor table
         size_t host_cap = 0;
@@ -392,7 +411,8 @@ int enqueue_decolor(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
     mark(ctx, marks, 0, st);
     hipError_t e = dc::launch_decolor_table(b.table, b.tile_end, (int)h.d.size(), h.total_tiles,
                                             h.mixed, h.src0, h.groups,
-                                            grid_blocks(ctx, t.decolor_gpc), st);
+                                            grid_blocks(ctx, h.mixed ? t.mixed_gpc : t.decolor_gpc),
+                                            st);
     if (e != hipSuccess)
         return hip_fail(e, "decolorize launch");
     mark(ctx, marks, 1, st);
@@ -554,7 +574,8 @@ bool tune_ok(const dc_tuning &t)
     auto g_ok = [](int g) { return g == 1 || g == 2 || g == 4; };
     auto c_ok = [](int c) { return c >= 0 && c <= 64; };
     return g_ok(t.groups[0]) && g_ok(t.groups[1]) && g_ok(t.groups[2]) && g_ok(t.mixed_groups) &&
-           c_ok(t.decolor_grid_per_cu) && c_ok(t.pass1_grid_per_cu) && c_ok(t.pass2_grid_per_cu) &&
+           c_ok(t.decolor_grid_per_cu) && c_ok(t.mixed_grid_per_cu) && c_ok(t.pass1_grid_per_cu) &&
+           c_ok(t.pass2_grid_per_cu) &&
            (t.tonemap_pipeline == 0 || t.tonemap_pipeline == 1);
 }
 
@@ -565,6 +586,7 @@ dc_tuning to_public(const Tune &t)
         o.groups[i] = t.groups[i];
     o.mixed_groups = t.mixed_groups;
     o.decolor_grid_per_cu = t.decolor_gpc;
+    o.mixed_grid_per_cu = t.mixed_gpc;
     o.pass1_grid_per_cu = t.pass1_gpc;
     o.pass2_grid_per_cu = t.pass2_gpc;
     o.tonemap_pipeline = t.tm_pipeline;
@@ -578,6 +600,7 @@ Tune from_public(const dc_tuning &o)
         t.groups[i] = o.groups[i];
     t.mixed_groups = o.mixed_groups;
     t.decolor_gpc = o.decolor_grid_per_cu;
+    t.mixed_gpc = o.mixed_grid_per_cu;
     t.pass1_gpc = o.pass1_grid_per_cu;
     t.pass2_gpc = o.pass2_grid_per_cu;
     t.tm_pipeline = o.tonemap_pipeline;
@@ -654,7 +677,7 @@ int plan_build(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n, const
     return DC_OK;
 }
 
-// Median over reps of the summed duration of event intervals [first, last).
+// Per-interval durations of `reps` timed runs of a plan after one warm-up.
 int time_plan(dc_plan *p, hipStream_t st, int reps, std::vector<float> *per_interval)
 {
     dc_ctx *ctx = p->ctx;
@@ -684,11 +707,10 @@ int time_plan(dc_plan *p, hipStream_t st, int reps, std::vector<float> *per_inte
         }
     }
     ctx->profiling = was;
+    // The fastest run of each interval: the least disturbed measurement.
     per_interval->assign(nint, 0.0f);
-    for (int i = 0; i < nint; ++i) {
-        std::sort(samples[i].begin(), samples[i].end());
-        (*per_interval)[i] = samples[i][samples[i].size() / 2];
-    }
+    for (int i = 0; i < nint; ++i)
+        (*per_interval)[i] = *std::min_element(samples[i].begin(), samples[i].end());
     return DC_OK;
 }
 
@@ -1003,7 +1025,7 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
         return rc;
     const hipStream_t st = (hipStream_t)stream;
     const int gpcs[] = {0, 1, 2, 4, 8, 16};
-    const int reps = 5;
+    const int reps = 10;
     Tune best = ctx->tune;
     std::vector<float> ms;
     auto run = [&](const Tune &t, std::vector<float> *out) -> int {
@@ -1025,11 +1047,13 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
         for (int g : {1, 2, 4}) {
             for (int c : gpcs) {
                 Tune t = ctx->tune;
-                if (mixed)
+                if (mixed) {
                     t.mixed_groups = g;
-                else
+                    t.mixed_gpc = c;
+                } else {
                     t.groups[imgs[0].src_dtype] = g;
-                t.decolor_gpc = c;
+                    t.decolor_gpc = c;
+                }
                 rc = run(t, &ms);
                 if (rc != DC_OK)
                     return rc;
@@ -1075,6 +1099,344 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
     ctx->tune = best;
     if (chosen)
         *chosen = to_public(best);
+    return DC_OK;
+}
+
+} // extern "C"
+
+// ------------------------------------------------------------------ serving
+
+// Continuous-batching server. Requests wait in FIFO order; a request is
+// admitted when its output fits the server's device-memory arena (first fit,
+// 256-byte granules, coalescing free list); whenever one of the launch lanes
+// (each its own stream) is idle, every admitted request (up to max_batch)
+// goes into one tone-map launch on that lane; a lane whose completion event
+// has fired retires its requests and frees their memory, which admits more.
+// Each image's result does not depend on the batch it lands in.
+struct dc_server {
+    struct Req {
+        dc_request r;
+        double t_submit = 0, t_admit = 0, t_launch = 0;
+        size_t off = 0, bytes = 0;
+        bool owned = false;
+    };
+    struct Lane {
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+        std::vector<Req> batch;
+        bool busy = false;
+    };
+    dc_ctx *ctx = nullptr;
+    dc_server_config cfg{};
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    std::map<size_t, size_t> free_blocks; // offset -> size
+    std::deque<Req> waiting, admitted;
+    std::vector<Lane> lanes;
+    std::vector<dc_completion> done;
+    std::chrono::steady_clock::time_point t0;
+    int64_t in_system = 0;
+};
+
+namespace {
+
+constexpr size_t kGranule = 256;
+
+double server_now(const dc_server *sv)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+}
+
+bool arena_alloc(dc_server *sv, size_t bytes, size_t *off)
+{
+    for (auto it = sv->free_blocks.begin(); it != sv->free_blocks.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            sv->free_blocks.erase(it);
+            if (rest)
+                sv->free_blocks[at] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(dc_server *sv, size_t off, size_t bytes)
+{
+    auto it = sv->free_blocks.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != sv->free_blocks.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        sv->free_blocks.erase(next);
+    }
+    if (it != sv->free_blocks.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            sv->free_blocks.erase(it);
+        }
+    }
+}
+
+// Output bytes of a server-allocated output: rows padded to 16 bytes.
+size_t out_bytes(const dc_image &m, int64_t *pitch)
+{
+    const int64_t row = (int64_t)dc::elem_size(m.dst_dtype) * m.width;
+    *pitch = (row + 15) / 16 * 16;
+    const size_t b = (size_t)*pitch * (size_t)m.height;
+    return (b + kGranule - 1) / kGranule * kGranule;
+}
+
+void complete(dc_server *sv, const dc_server::Req &q, int status, int batch, double t_done)
+{
+    dc_completion c;
+    c.id = q.r.id;
+    c.status = status;
+    c.batch_size = batch;
+    c.t_submit = q.t_submit;
+    c.t_admit = q.t_admit;
+    c.t_launch = q.t_launch;
+    c.t_done = t_done;
+    sv->done.push_back(c);
+    --sv->in_system;
+}
+
+int server_step(dc_server *sv)
+{
+    // 1. retire finished launches
+    for (auto &ln : sv->lanes) {
+        if (!ln.busy)
+            continue;
+        const hipError_t q = hipEventQuery(ln.done);
+        if (q == hipErrorNotReady)
+            continue;
+        if (q != hipSuccess)
+            return hip_fail(q, "server launch failed");
+        const double t = server_now(sv);
+        for (auto &r : ln.batch) {
+            if (r.owned)
+                arena_free(sv, r.off, r.bytes);
+            complete(sv, r, DC_OK, (int)ln.batch.size(), t);
+        }
+        ln.batch.clear();
+        ln.busy = false;
+    }
+    // 2. admit in FIFO order while outputs fit
+    while (!sv->waiting.empty()) {
+        dc_server::Req &q = sv->waiting.front();
+        if (q.r.img.dst) {
+            q.t_admit = server_now(sv);
+            sv->admitted.push_back(q);
+            sv->waiting.pop_front();
+            continue;
+        }
+        int64_t pitch = 0;
+        const size_t bytes = out_bytes(q.r.img, &pitch);
+        if (bytes > sv->arena_bytes) {
+            complete(sv, q, DC_ERR_NO_MEMORY, 0, server_now(sv));
+            sv->waiting.pop_front();
+            continue;
+        }
+        size_t off = 0;
+        if (!arena_alloc(sv, bytes, &off))
+            break;
+        q.off = off;
+        q.bytes = bytes;
+        q.owned = true;
+        q.r.img.dst = sv->arena + off;
+        q.r.img.dst_pitch = pitch;
+        q.t_admit = server_now(sv);
+        sv->admitted.push_back(q);
+        sv->waiting.pop_front();
+    }
+    // 3. launch admitted work on idle lanes
+    for (auto &ln : sv->lanes) {
+        if (sv->admitted.empty())
+            break;
+        if (ln.busy)
+            continue;
+        const size_t k = std::min<size_t>(sv->admitted.size(), (size_t)sv->cfg.max_batch);
+        std::vector<dc_image> imgs(k);
+        const double t = server_now(sv);
+        for (size_t i = 0; i < k; ++i) {
+            ln.batch.push_back(sv->admitted.front());
+            sv->admitted.pop_front();
+            ln.batch.back().t_launch = t;
+            imgs[i] = ln.batch.back().r.img;
+        }
+        HostTable h;
+        build_table(imgs.data(), (int32_t)k, &sv->cfg.params, true, sv->ctx->tune, h);
+        dc_ctx::Slot *slot = nullptr;
+        DevBufs b;
+        int rc = stage(sv->ctx, h, ln.s, &slot, &b);
+        if (rc == DC_OK)
+            rc = enqueue_tonemap(sv->ctx, h, b, sv->ctx->tune, tm_of(&sv->cfg.tm), nullptr, ln.s,
+                                 false);
+        if (rc == DC_OK)
+            rc = release_slot(slot, ln.s);
+        if (rc != DC_OK)
+            return rc;
+        const hipError_t e = hipEventRecord(ln.done, ln.s);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventRecord");
+        ln.busy = true;
+    }
+    return DC_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int dc_server_create(dc_ctx *ctx, const dc_server_config *cfg, dc_server **out)
+{
+    g_last_error.clear();
+    if (!out)
+        return fail(DC_ERR_INVALID_ARG, "server out-pointer is NULL");
+    *out = nullptr;
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    if (!cfg || cfg->budget_bytes <= 0 || cfg->max_batch < 1 || cfg->max_inflight < 1 ||
+        cfg->max_inflight > 8 || cfg->flags != 0)
+        return fail(DC_ERR_INVALID_ARG,
+                    "budget_bytes > 0, max_batch >= 1, max_inflight in [1, 8] and flags 0 are required");
+    rc = validate_params(&cfg->params);
+    if (rc == DC_OK)
+        rc = validate_tm(&cfg->tm);
+    if (rc != DC_OK)
+        return rc;
+    dc_server *sv = new (std::nothrow) dc_server();
+    if (!sv)
+        return fail(DC_ERR_NO_MEMORY, "server allocation failed");
+    sv->ctx = ctx;
+    sv->cfg = *cfg;
+    sv->arena_bytes = (size_t)cfg->budget_bytes / kGranule * kGranule;
+    if (hipMalloc((void **)&sv->arena, sv->arena_bytes) != hipSuccess) {
+        delete sv;
+        return fail(DC_ERR_NO_MEMORY, "server arena allocation failed");
+    }
+    sv->free_blocks[0] = sv->arena_bytes;
+    sv->lanes.resize((size_t)cfg->max_inflight);
+    for (auto &ln : sv->lanes) {
+        if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+            dc_server_destroy(sv);
+            return fail(DC_ERR_HIP, "server stream or event creation failed");
+        }
+    }
+    sv->t0 = std::chrono::steady_clock::now();
+    *out = sv;
+    return DC_OK;
+}
+
+int dc_server_destroy(dc_server *sv)
+{
+    if (!sv)
+        return DC_OK;
+    (void)hipSetDevice(sv->ctx->device);
+    for (auto &ln : sv->lanes) {
+        if (ln.s) {
+            (void)hipStreamSynchronize(ln.s);
+            (void)hipStreamDestroy(ln.s);
+        }
+        if (ln.done)
+            (void)hipEventDestroy(ln.done);
+    }
+    if (sv->arena)
+        (void)hipFree(sv->arena);
+    delete sv;
+    return DC_OK;
+}
+
+double dc_server_clock(dc_server *sv) { return sv ? server_now(sv) : 0.0; }
+
+int dc_server_submit(dc_server *sv, const dc_request *reqs, int32_t n, double t_submit)
+{
+    g_last_error.clear();
+    if (!sv || n < 0 || (n > 0 && !reqs))
+        return fail(DC_ERR_INVALID_ARG, "bad server or request list");
+    for (int32_t i = 0; i < n; ++i) {
+        const dc_image &m = reqs[i].img;
+        const std::string at = " (request " + std::to_string(reqs[i].id) + ")";
+        Range r;
+        int rc = check_src(m, at, r);
+        if (rc != DC_OK)
+            return rc;
+        if (!dtype_ok(m.dst_dtype) || m.dst2 || m.dst2_dtype != DC_NONE || m.flags != 0)
+            return fail(DC_ERR_INVALID_ARG, "dst_dtype must be set; dst2 must be absent; flags 0" + at);
+        if (m.dst) {
+            rc = validate_images(&m, 1);
+            if (rc != DC_OK)
+                return rc;
+        }
+    }
+    const double t = t_submit >= 0.0 ? t_submit : server_now(sv);
+    for (int32_t i = 0; i < n; ++i) {
+        dc_server::Req q;
+        q.r = reqs[i];
+        q.t_submit = t;
+        sv->waiting.push_back(q);
+        ++sv->in_system;
+    }
+    return DC_OK;
+}
+
+int dc_server_step(dc_server *sv)
+{
+    g_last_error.clear();
+    if (!sv)
+        return fail(DC_ERR_INVALID_ARG, "server is NULL");
+    int rc = check_ctx(sv->ctx);
+    if (rc == DC_OK)
+        rc = server_step(sv);
+    return rc != DC_OK ? rc : (int)std::min<int64_t>(sv->in_system, 0x7fffffff);
+}
+
+int dc_server_poll(dc_server *sv, dc_completion *out, int32_t cap)
+{
+    g_last_error.clear();
+    if (!sv || cap < 0 || (cap > 0 && !out))
+        return fail(DC_ERR_INVALID_ARG, "bad server or output array");
+    const int32_t n = (int32_t)std::min<size_t>(sv->done.size(), (size_t)cap);
+    std::copy(sv->done.begin(), sv->done.begin() + n, out);
+    sv->done.erase(sv->done.begin(), sv->done.begin() + n);
+    return n;
+}
+
+int dc_server_replay(dc_server *sv, const dc_request *reqs, const double *arrival_s, int32_t n,
+                     dc_completion *out)
+{
+    g_last_error.clear();
+    if (!sv || n < 0 || (n > 0 && (!reqs || !arrival_s || !out)))
+        return fail(DC_ERR_INVALID_ARG, "bad replay arguments");
+    for (int32_t i = 1; i < n; ++i)
+        if (!(arrival_s[i] >= arrival_s[i - 1]))
+            return fail(DC_ERR_INVALID_ARG, "arrival times must be non-decreasing");
+    int rc = check_ctx(sv->ctx);
+    if (rc != DC_OK)
+        return rc;
+    const double base = server_now(sv);
+    int32_t next = 0, got = 0;
+    while (got < n) {
+        const double now = server_now(sv) - base;
+        int32_t k = next;
+        while (k < n && arrival_s[k] <= now)
+            ++k;
+        for (int32_t i = next; i < k; ++i) {
+            rc = dc_server_submit(sv, &reqs[i], 1, base + arrival_s[i]);
+            if (rc != DC_OK)
+                return rc;
+        }
+        next = k;
+        rc = server_step(sv);
+        if (rc != DC_OK)
+            return rc;
+        const int32_t m = dc_server_poll(sv, out + got, n - got);
+        got += m;
+    }
     return DC_OK;
 }
 

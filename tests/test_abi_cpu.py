@@ -154,3 +154,16 @@ def test_binding_refuses_cpu_tensors():
     x = torch.zeros((4, 4, 3), dtype=torch.uint8)
     with pytest.raises(TypeError):
         P.decolorize(x)
+
+
+def test_server_calls_reject_bad_arguments(lib):
+    cfg = P.DcServerConfig(1 << 20, 8, 2, 0, P.DcParams(0.55, 0.8), P.DcTmParams(1e-4, 2.0, 1e-3))
+    h = ctypes.c_void_p()
+    assert lib.dc_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_create(None, ctypes.byref(cfg), None) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_step(None) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_submit(None, None, 0, -1.0) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_poll(None, None, 0) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_destroy(None) == P.DC_OK
+    assert lib.dc_plan_destroy(None) == P.DC_OK
+    assert lib.dc_plan_run(None, None) == P.DC_ERR_INVALID_ARG

@@ -1,0 +1,99 @@
+"""GPU tests of the continuous-batching tone-map server (dc_server_*): every
+request's result is bit-identical alone and inside a mixed continuous batch,
+admission by the device-memory budget never deadlocks, oversized requests are
+rejected, and trace replay completes every request."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2108_13656_amd as P
+import synth
+from gpuhelp import need_gpu, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def _mixed_requests(dev, n, seed):
+    rng = np.random.default_rng(seed)
+    xs, outs = [], []
+    for i in range(n):
+        h, w = (int(v) for v in np.rint(np.exp(rng.uniform(np.log(16), np.log(700), 2))))
+        if i % 3 == 2:
+            xs.append(to_dev(synth.hdr_pixels(rng, h, w), dev))
+            outs.append(torch.full((h, w), -1.0, device=dev))
+        else:
+            xs.append(to_dev(synth.sdr_pixels(rng, h, w), dev))
+            outs.append(torch.zeros((h, w), dtype=torch.uint8, device=dev))
+    return xs, outs
+
+
+def test_results_identical_alone_and_in_mix(dev):
+    xs, outs = _mixed_requests(dev, 40, 1)
+    srv = P.Server(budget_bytes=64 << 20, max_batch=16, max_inflight=3)
+    srv.submit([P.request_for(i, x, o) for i, (x, o) in enumerate(zip(xs, outs))])
+    done = []
+    while len(done) < len(xs):
+        srv.step()
+        done += srv.poll()
+    srv.close()
+    torch.cuda.synchronize()
+    assert sorted(c.id for c in done) == list(range(len(xs)))
+    assert all(c.status == P.DC_OK for c in done)
+    sizes = [c.batch_size for c in done]
+    report("batch sizes seen: %s" % sorted(set(sizes)))
+    assert max(sizes) > 1
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        alone, _, _ = P.tonemap_global([x], o.dtype)
+        assert torch.equal(alone[0], o), i
+
+
+def test_budget_admission_and_rejection(dev):
+    rng = np.random.default_rng(2)
+    xs = [to_dev(synth.sdr_pixels(rng, 300, 400), dev) for _ in range(30)]
+    big = to_dev(synth.sdr_pixels(rng, 700, 800), dev)
+    # budget holds two 300x400 f32 outputs (rows padded to 16 bytes), not the big one
+    budget = 2 * 300 * 1600 + 4096
+    srv = P.Server(budget_bytes=budget, max_batch=8, max_inflight=2)
+    reqs = [P.request_for(i, x, out_dtype=torch.float32) for i, x in enumerate(xs)]
+    reqs.append(P.request_for(99, big, out_dtype=torch.float32))
+    srv.submit(reqs)
+    done = []
+    for _ in range(1000000):
+        srv.step()
+        done += srv.poll()
+        if len(done) == len(reqs):
+            break
+    srv.close()
+    by_id = {c.id: c for c in done}
+    assert len(by_id) == len(reqs)
+    assert by_id[99].status == P.DC_ERR_NO_MEMORY
+    ok = [by_id[i] for i in range(len(xs))]
+    assert all(c.status == P.DC_OK for c in ok)
+    assert max(c.batch_size for c in ok) <= 2  # never more admitted than the budget holds
+    admits = [c.t_admit for c in ok]
+    assert admits == sorted(admits)  # FIFO admission
+
+
+def test_replay_trace_completes(dev):
+    xs, outs = _mixed_requests(dev, 60, 3)
+    reqs = [P.request_for(i, x, o) for i, (x, o) in enumerate(zip(xs, outs))]
+    arrivals = list(np.cumsum(np.random.default_rng(4).exponential(2e-5, len(reqs))) - 2e-5)
+    srv = P.Server(budget_bytes=64 << 20, max_batch=32, max_inflight=4)
+    done = srv.replay(reqs, arrivals)
+    srv.close()
+    torch.cuda.synchronize()
+    assert sorted(c.id for c in done) == list(range(len(reqs)))
+    lat = np.array([c.t_done - c.t_submit for c in done])
+    report("replay latency p50 %.1f us p99 %.1f us" % (1e6 * np.median(lat),
+                                                       1e6 * np.quantile(lat, 0.99)))
+    assert np.all(lat > 0)
+    for c in done:
+        assert c.t_submit <= c.t_admit <= c.t_launch <= c.t_done
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        alone, _, _ = P.tonemap_global([x], o.dtype)
+        assert torch.equal(alone[0], o), i
