@@ -436,7 +436,9 @@ class Server:
 
     def __init__(self, budget_bytes, max_batch=64, max_inflight=4, beta_r=BETA_R, beta_k=BETA_K,
                  eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, device=None):
-        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device if isinstance(device, torch.device) else torch.device("cuda", device)
         cfg = DcServerConfig(budget_bytes, max_batch, max_inflight, 0, DcParams(beta_r, beta_k),
                              DcTmParams(eps, contrast, sigma_floor))
         self._h = ctypes.c_void_p()

@@ -674,13 +674,15 @@ __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restri
         // T = 1 / (1 + exp(-c (x - mu) / s)) = 1 / (1 + exp2(a (x2 - mu2)))
         curves[img] = Curve{-tm.contrast * log2e / s2, tot.mean};
         if (stats) {
+            // The table may be reordered by input type; stats follow the
+            // caller's image order.
             StatsOut o;
             o.log_mean = tot.mean * ln2;
             o.log_std = sigma2 * ln2;
             o.l_min = tot.lo;
             o.l_max = tot.hi;
             o.count = im.npx;
-            stats[img] = o;
+            stats[im.image] = o;
         }
     }
 }

@@ -323,6 +323,13 @@ struct HostTable {
     int src0 = 0;
     int groups = 2;  // decolorization only
     bool tonemap = false;
+    // Tone map: the table is stably sorted by input type; runs[k] = {first
+    // image, end image, type} of each run, so each pass launches its
+    // per-type kernel once per run.
+    struct Run {
+        int img0, img1, src;
+    };
+    std::vector<Run> runs;
 };
 
 void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool tonemap,
@@ -337,11 +344,24 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool 
     for (int32_t i = 0; i < n; ++i)
         h.mixed |= imgs[i].src_dtype != h.src0;
     h.groups = h.mixed ? tune.mixed_groups : tune.groups[h.src0];
+    std::vector<int32_t> order((size_t)n);
+    for (int32_t i = 0; i < n; ++i)
+        order[i] = i;
+    if (tonemap)
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return imgs[a].src_dtype < imgs[b].src_dtype;
+        });
+    h.runs.clear();
     int64_t total = 0;
     for (int32_t i = 0; i < n; ++i) {
+        const dc_image &m = imgs[order[i]];
         const int64_t tile_px =
-            tonemap ? dc::kStatsChunkPx : (int64_t)dc::kBlock * h.groups * dc::group_px(imgs[i].src_dtype);
-        h.d[i] = describe(imgs[i], i, tile_px, params);
+            tonemap ? dc::kStatsChunkPx : (int64_t)dc::kBlock * h.groups * dc::group_px(m.src_dtype);
+        h.d[i] = describe(m, order[i], tile_px, params);
+        if (h.runs.empty() || h.runs.back().src != m.src_dtype)
+            h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype});
+        else
+            h.runs.back().img1 = i + 1;
         h.d[i].tile_begin = total;
         h.d[i].chunk_begin = total * dc::kWavesPerBlock; // tone map: one partial per wave
         total += h.d[i].ntiles;
@@ -453,8 +473,12 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
     hipError_t e = hipSuccess;
     if (!t.tm_pipeline || n == 0) {
         mark(ctx, marks, 0, st);
-        e = dc::launch_tm_pass1(b.table, b.tile_end, 0, n, 0, h.total_tiles, h.mixed, h.src0, a,
-                                b.parts, g1, st);
+        for (const auto &r : h.runs) {
+            const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
+            if (e == hipSuccess)
+                e = dc::launch_tm_pass1(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, 0,
+                                        r.src, a, b.parts, g1, st);
+        }
         mark(ctx, marks, 1, st);
         if (e == hipSuccess)
             e = dc::launch_tm_combine(b.table, b.grp_end, 0, n, 0, h.total_grps, b.parts, b.parts2,
@@ -462,9 +486,12 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
         if (e == hipSuccess)
             e = dc::launch_tm_finalize(b.table, 0, n, a, b.parts2, b.curves, stats, st);
         mark(ctx, marks, 2, st);
-        if (e == hipSuccess)
-            e = dc::launch_tm_pass2(b.table, b.tile_end, 0, n, 0, h.total_tiles, h.mixed, h.src0, a,
-                                    b.curves, g2, st);
+        for (const auto &r : h.runs) {
+            const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
+            if (e == hipSuccess)
+                e = dc::launch_tm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, 0,
+                                        r.src, a, b.curves, g2, st);
+        }
         mark(ctx, marks, 3, st);
         if (e != hipSuccess)
             return hip_fail(e, "tonemap launch");
@@ -1180,11 +1207,11 @@ void arena_free(dc_server *sv, size_t off, size_t bytes)
     }
 }
 
-// Output bytes of a server-allocated output: rows padded to 16 bytes.
+// Bytes of a server-allocated output. Rows are packed (pitch = row bytes), so a
+// packed input keeps the packed vector walk; blocks start on 256-byte granules.
 size_t out_bytes(const dc_image &m, int64_t *pitch)
 {
-    const int64_t row = (int64_t)dc::elem_size(m.dst_dtype) * m.width;
-    *pitch = (row + 15) / 16 * 16;
+    *pitch = (int64_t)dc::elem_size(m.dst_dtype) * m.width;
     const size_t b = (size_t)*pitch * (size_t)m.height;
     return (b + kGranule - 1) / kGranule * kGranule;
 }
