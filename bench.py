@@ -24,6 +24,29 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 METRIC = "Gpixels/s + % of HBM peak (decolorize+tonemap); p50/p99 latency served"
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def profiled_traffic():
+    """HBM bytes per launch measured with rocprofv3 counters, from the
+    summaries under profiles/ that were taken on the current kernel source
+    (an empty dict when none matches, i.e. the kernels changed since)."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2108_13656_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    found = {}
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        text = open(fn).read()
+        m = re.search(r"source sha256 \(paper_2108_13656_amd/csrc/kernels.hip\): ([0-9a-f]+)", text)
+        if not m or m.group(1) != digest:
+            continue
+        for key, val in re.findall(r"^traffic_bytes (\S+) (\d+)$", text, re.M):
+            found[key] = int(val)
+    return found
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -176,6 +199,7 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(dev)
     result = {}
+    traffic = profiled_traffic()
     if args.calibrate_copy:
         n = args.calibrate_copy << 20
         a = torch.ones(n, dtype=torch.uint8, device=dev)
@@ -258,7 +282,7 @@ def main():
                        "per_call_api_ms_per_step": round(dyn_ms, 4)},
             "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "traffic": None},
+                         "traffic": traffic.get(dom[0]), "algorithmic_bytes": dom[2]},
         })
 
         # CPU baseline: the FP64 oracle, single thread, on a sample of images.
@@ -328,7 +352,9 @@ def main():
                             "grid_per_cu": vtune["decolor_grid_per_cu"]},
                  "roofline": {"bound": "hbm", "kernel": "decolor_table", "achieved": round(vach, 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(vach / HBM_PEAK_GBS, 4), "traffic": None}}
+                              "frac": round(vach / HBM_PEAK_GBS, 4),
+                              "traffic": traffic.get("decolor_table"),
+                              "algorithmic_bytes": vbytes}}
         log("video step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %s "
             "Gpx/s" % (vms, video["value"], vk, vach, video["per_image_launches_gpx"]))
         if not result:
@@ -379,7 +405,9 @@ def main():
                              "grid_per_cu": utune["mixed_grid_per_cu"]},
                   "roofline": {"bound": "hbm", "kernel": "decolor_table (mixed)",
                                "achieved": round(uach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": round(uach / HBM_PEAK_GBS, 4), "traffic": None}}
+                               "frac": round(uach / HBM_PEAK_GBS, 4),
+                               "traffic": traffic.get("decolor_table_mixed"),
+                               "algorithmic_bytes": ubytes}}
         log("uneven step %.3f ms (%.1f Gpx/s), kernel %.3f ms, %.0f GB/s; per-image launches %s"
             " Gpx/s" % (ums, uneven["value"], uk, uach, uneven["per_image_launches_gpx"]))
         if result:
