@@ -422,6 +422,22 @@ def main():
         del imgs, uo
         torch.cuda.empty_cache()
 
+    # ---------------------------------------------------- one small image (latency)
+    if args.only is None:
+        import synth
+        x = torch.from_numpy(synth.gradient_rects()).to(dev)
+        o = torch.empty(x.shape[:2], dtype=torch.float32, device=dev)
+        with torch.cuda.stream(stream):
+            sp = P.Plan(P.PLAN_DECOLORIZE, [x], [o], graph=False)
+            lat_ms = time_steps(lambda: sp.run(stream), 200, 20, stream)
+            sp.close()
+            call_ms = time_steps(lambda: P.decolorize(x, out=o, stream=stream), 200, 20, stream)
+        small = {"workload": "gradient_rects_512x512_u8_to_f32", "pixels": 512 * 512,
+                 "plan_launch_us": round(lat_ms * 1e3, 2), "per_call_api_us": round(call_ms * 1e3, 2)}
+        log("512x512 u8 -> f32: %.2f us per plan launch, %.2f us per dc_decolorize call" %
+            (small["plan_launch_us"], small["per_call_api_us"]))
+        result["small_image"] = small
+
     # ---------------------------------------------------- serving loop
     if args.only in (None, "serve") and not args.skip_serve:
         result_serve = serve_leg(args, P, dev)

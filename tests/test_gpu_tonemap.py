@@ -198,3 +198,23 @@ def test_two_stream_pipeline_matches_batch_schedule(dev, graph):
         plan.close()
     finally:
         P.set_tuning(t0)
+
+
+def test_low_variance_image_within_derived_bound(dev):
+    """sigma far below the 0.1 of the other tests: T moves by up to c / (4 s)
+    times the FP32 error of x, s = max(sigma, sigma_floor). The bound below is
+    that slope times 4e-7 (1 + |x|) (log2, rcp and sqrt rounding of x and of the
+    statistics), plus the 1e-5 of well-conditioned images."""
+    rng = np.random.default_rng(15)
+    base = np.array([0.4, 0.35, 0.3])
+    img = (base * (1.0 + 0.002 * rng.standard_normal((96, 80, 3)))).astype(np.float32)
+    t_ref, lhat_ref, st_ref = oracle.tonemap(img, **TM)
+    outs, _, stats = P.tonemap_global([to_dev(img, dev)], **TM)
+    st = P.stats_to_host(stats)[0]
+    s = max(st_ref["sigma"], TM["sigma_floor"])
+    xmax = float(np.max(np.abs(np.log(lhat_ref + TM["eps"]))))
+    bound = 1e-5 + TM["contrast"] / (4 * s) * 4e-7 * (1 + xmax)
+    err = float(np.max(np.abs(outs[0].cpu().numpy() - t_ref)))
+    report("low-variance image: sigma %.2e, |dT| %.2e, derived bound %.2e" % (st_ref["sigma"], err,
+                                                                          bound))
+    assert err <= bound
