@@ -58,6 +58,10 @@ def _load():
     lib.ref_decolorize_image.argtypes = [vp, i32, i32, i32, i64, d, d, vp, i32]
     lib.ref_all_colours.restype = None
     lib.ref_all_colours.argtypes = [d, d, vp]
+    lib.ref_comparator_px.restype = d
+    lib.ref_comparator_px.argtypes = [d, d, d, i32]
+    lib.ref_comparator_image.restype = i32
+    lib.ref_comparator_image.argtypes = [vp, i32, i32, i32, i64, i32, vp]
     lib.ref_tonemap_stats.restype = None
     lib.ref_tonemap_stats.argtypes = [vp, i64, d, vp]
     lib.ref_tonemap_curve.restype = d
@@ -108,6 +112,24 @@ def decolorize(img, beta_r=0.55, beta_k=0.8, nthreads=1):
     rc = _load().ref_decolorize_image(_ptr(img), code, w, h, pitch, beta_r, beta_k, _ptr(out),
                                       int(nthreads))
     if rc != 0:
+        raise ValueError("oracle rejected the image")
+    return out
+
+
+COMPARATORS = {"y601": 1, "hsv_v": 2, "cielab_l": 3}
+
+
+def comparator(r, g, b, kind):
+    """One comparator channel (normalised inputs and output): 'y601', 'hsv_v'
+    or 'cielab_l' (L* / 100)."""
+    return _load().ref_comparator_px(r, g, b, COMPARATORS[kind])
+
+
+def comparator_image(img, kind):
+    """Comparator channel (float64 HxW, normalised units) of an HxWx3 image."""
+    img, code, w, h, pitch = _image_args(img)
+    out = np.empty((h, w), np.float64)
+    if _load().ref_comparator_image(_ptr(img), code, w, h, pitch, COMPARATORS[kind], _ptr(out)):
         raise ValueError("oracle rejected the image")
     return out
 

@@ -159,6 +159,73 @@ void ref_decolor_px_terms(double R, double G, double B, double beta_r, double be
     out[4] = ref_decolor_px(R, G, B, beta_r, beta_k);
 }
 
+/* ------------------------------------------------- comparator channels */
+
+/* Gray channels the paper compares its L with, in normalised units (inputs
+ * already divided by 255 for 8-bit data):
+ *   kind 1: Gray = 0.2989 R + 0.5870 G + 0.1140 B, the weighted sum of the
+ *           MATLAB rgb2gray function quoted in Sec. I;
+ *   kind 2: V of HSV = max(R, G, B) (Sec. III-B.1, Fig. GTMO);
+ *   kind 3: CIE 1976 L* / 100 with Y = the kind-1 gray of the normalised
+ *           values (the paper notes CIELAB L builds on the Y of YCbCr) and white
+ *           Y_n = 1: 116 f(Y) - 16 with f(t) = t^(1/3) above (6/29)^3 and
+ *           t / (3 (6/29)^2) + 4/29 below it.
+ * NaN and negative channels read as 0. */
+double ref_comparator_px(double r, double g, double b, int kind)
+{
+    r = sanitise(r);
+    g = sanitise(g);
+    b = sanitise(b);
+    double y = 0.2989 * r + 0.5870 * g + 0.1140 * b;
+    if (kind == 1)
+        return y;
+    if (kind == 2)
+        return r > g ? (r > b ? r : b) : (g > b ? g : b);
+    const double d = 6.0 / 29.0;
+    double f = y > d * d * d ? cbrt(y) : y / (3.0 * d * d) + 4.0 / 29.0;
+    return (116.0 * f - 16.0) / 100.0;
+}
+
+/* A comparator channel of every pixel of an interleaved HWC image, in
+ * normalised units (row-major, packed out). Returns 0, or -1 on a bad
+ * argument. */
+int ref_comparator_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes, int kind,
+                         double *out)
+{
+    if (!src || !out || W < 0 || H < 0 || dtype < 0 || dtype > 2 || kind < 1 || kind > 3)
+        return -1;
+    int es = dtype == REF_U8 ? 1 : dtype == REF_F16 ? 2 : 4;
+    if (pitch_bytes < (int64_t)3 * es * W)
+        return -1;
+    double unit = dtype == REF_U8 ? 255.0 : 1.0;
+    for (int y = 0; y < H; ++y) {
+        const unsigned char *row = (const unsigned char *)src + (int64_t)y * pitch_bytes;
+        for (int x = 0; x < W; ++x) {
+            const unsigned char *p = row + (int64_t)3 * es * x;
+            double r = 0, g = 0, b = 0;
+            if (dtype == REF_U8) {
+                r = p[0];
+                g = p[1];
+                b = p[2];
+            } else if (dtype == REF_F16) {
+                uint16_t h[3];
+                memcpy(h, p, 6);
+                r = ref_half_to_double(h[0]);
+                g = ref_half_to_double(h[1]);
+                b = ref_half_to_double(h[2]);
+            } else {
+                float f[3];
+                memcpy(f, p, 12);
+                r = f[0];
+                g = f[1];
+                b = f[2];
+            }
+            out[(int64_t)y * W + x] = ref_comparator_px(r / unit, g / unit, b / unit, kind);
+        }
+    }
+    return 0;
+}
+
 /* --------------------------------------------------------------- encoders */
 
 /* Normalised Lhat -> 8-bit code: round half up, clamp to [0, 255]. */

@@ -101,3 +101,20 @@ def tonemap_curve(lhat, eps, contrast, mu, sigma, sigma_floor):
     scale = max(sigma, sigma_floor)
     x = math.log(lhat + eps)
     return 1.0 / (1.0 + math.exp(-contrast * (x - mu) / scale))
+
+
+def comparator(r, g, b, kind):
+    """Comparator gray channels on normalised RGB: rgb2gray weighted sum, V of
+    HSV, CIE L* / 100 built on the rgb2gray Y with white Y_n = 1."""
+    r, g, b = _clean(r), _clean(g), _clean(b)
+    gray = 0.2989 * r + 0.5870 * g + 0.1140 * b
+    if kind == "y601":
+        return gray
+    if kind == "hsv_v":
+        return max(r, g, b)
+    knee = (6.0 / 29.0) ** 3
+    if gray > knee:
+        f = gray ** (1.0 / 3.0)
+    else:
+        f = gray / (3.0 * (6.0 / 29.0) ** 2) + 4.0 / 29.0
+    return (116.0 * f - 16.0) / 100.0
