@@ -341,6 +341,19 @@ def main():
             vplan_ev.close()
             for sp in singles:
                 sp.close()
+            # Same-GPU comparison with the gray channels the paper compares its
+            # L against (u8 in, f32 out, kernel time from the library's events).
+            comp = {}
+            cplan = P.Plan(P.PLAN_DECOLORIZE, frames, o32)
+            comp["decolor_L"] = vpx / (kernel_times(lambda: cplan.run(stream), 10, P, dev)[0]
+                                       * 1e-3) / 1e9
+            cplan.close()
+            for ch in ("y601", "hsv_v", "cielab_l"):
+                t = kernel_times(lambda: P.channel_batch(frames, ch, outs=o32, stream=stream), 10,
+                                 P, dev)[0]
+                comp[ch] = vpx / (t * 1e-3) / 1e9
+            comp = {k: round(v, 1) for k, v in comp.items()}
+            log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
         vbytes = vpx * 8
         vach = vbytes / (vk * 1e-3) / 1e9
         video = {"workload": "video_decolorize", "frames": "32x1920x1080 + 32x3840x2160",
@@ -350,6 +363,7 @@ def main():
                  if vms_single else None,
                  "tuning": {"groups_u8": vtune["groups"][0],
                             "grid_per_cu": vtune["decolor_grid_per_cu"]},
+                 "gray_channels_u8_to_f32_gpx": comp,
                  "roofline": {"bound": "hbm", "kernel": "decolor_table", "achieved": round(vach, 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(vach / HBM_PEAK_GBS, 4),

@@ -157,6 +157,20 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
 int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                       const dc_tm_params *tm, dc_stats *stats, void *stream);
 
+/* Comparator gray channels on the same data path, for side-by-side
+ * comparison with Eqs. (1)-(6) on the same GPU (the paper's run-time table
+ * compares its method with CIELAB L on one CPU; Sec. I quotes the rgb2gray
+ * weights; Sec. III-B.1 tone-maps Y and V as well):
+ *   DC_CH_Y601:     0.2989 R + 0.5870 G + 0.1140 B
+ *   DC_CH_HSV_V:    max(R, G, B)
+ *   DC_CH_CIELAB_L: CIE 1976 L* / 100 on that Y with white Y_n = 1
+ * on normalised inputs (8-bit / 255), written to dst (and dst2) in the same
+ * encodings as dc_decolorize. imgs is a HOST array; n == 0 is a no-op. */
+#define DC_CH_Y601 1
+#define DC_CH_HSV_V 2
+#define DC_CH_CIELAB_L 3
+int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t channel, void *stream);
+
 /* ---------------------------------------------------------------- plans
  * A plan freezes one call's images, parameters and launch shape: the
  * descriptor table is built, validated and copied to the device once, and

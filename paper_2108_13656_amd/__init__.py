@@ -154,13 +154,15 @@ def lib():
     L.dc_server_clock.argtypes = [vp]
     L.dc_server_clock.restype = ctypes.c_double
     L.dc_server_replay.argtypes = [vp, req_p, ctypes.POINTER(ctypes.c_double), i32, comp_p]
+    L.dc_channel_batch.argtypes = [vp, img_p, i32, i32, vp]
     L.dc_set_profiling.argtypes = [vp, ctypes.c_int]
     L.dc_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     for name in ("dc_create", "dc_destroy", "dc_validate", "dc_decolorize", "dc_decolorize_batch",
                  "dc_tonemap_global", "dc_version", "dc_set_profiling", "dc_last_timings",
                  "dc_plan_create", "dc_plan_run", "dc_plan_destroy", "dc_get_tuning",
                  "dc_set_tuning", "dc_autotune", "dc_server_create", "dc_server_destroy",
-                 "dc_server_submit", "dc_server_step", "dc_server_poll", "dc_server_replay"):
+                 "dc_server_submit", "dc_server_step", "dc_server_poll", "dc_server_replay",
+                 "dc_channel_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -321,6 +323,27 @@ def decolorize_batch(xs, out_dtype=torch.float32, out2_dtype=None, beta_r=BETA_R
     p = _params(beta_r, beta_k)
     _check(lib().dc_decolorize_batch(context(dev).handle, arr, len(xs), ctypes.byref(p),
                                      _stream_ptr(stream, dev)))
+    return outs if outs2 is None else list(zip(outs, outs2))
+
+
+CHANNELS = {"y601": 1, "hsv_v": 2, "cielab_l": 3}
+
+
+def channel_batch(xs, channel, out_dtype=torch.float32, out2_dtype=None, outs=None, outs2=None,
+                  stream=None):
+    """Comparator gray channel ('y601', 'hsv_v' or 'cielab_l' = L*/100) of a
+    list of images, on the same data path as the decolorization."""
+    xs = list(xs)
+    if not xs:
+        return []
+    dev = xs[0].device
+    if outs is None:
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+    if outs2 is None and out2_dtype is not None:
+        outs2 = [_alloc(x, out2_dtype, x.shape[0], x.shape[1]) for x in xs]
+    arr = _image_array(xs, outs, outs2)
+    _check(lib().dc_channel_batch(context(dev).handle, arr, len(xs), CHANNELS[channel],
+                                  _stream_ptr(stream, dev)))
     return outs if outs2 is None else list(zip(outs, outs2))
 
 

@@ -94,6 +94,9 @@ hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, h
 hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
                                 int64_t total_tiles, int mixed_src, int src_dtype, int groups,
                                 int64_t grid, hipStream_t s);
+hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                          int64_t t0, int64_t t1, int src_dtype, int channel, int64_t grid,
+                          hipStream_t s);
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                            int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            Part *parts, int64_t grid, hipStream_t s);

@@ -449,6 +449,90 @@ __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__rest
     });
 }
 
+// ---------------------------------------------------- comparator channels
+
+// Gray channels the paper compares its L with, evaluated on the same data
+// path (Table I's same-machine comparison, on the GPU): CH 1 = the rgb2gray
+// weighted sum quoted in Sec. I, CH 2 = V of HSV, CH 3 = CIE 1976 L* / 100
+// built on that Y with white Y_n = 1 (cube root as exp2(log2(y) / 3)).
+// Inputs are scaled to normalised units first; NaN and negatives read as 0.
+template <int CH>
+__device__ __forceinline__ float comparator_px(float R, float G, float B, float unit)
+{
+    R = fmaxf(R, 0.0f) * unit;
+    G = fmaxf(G, 0.0f) * unit;
+    B = fmaxf(B, 0.0f) * unit;
+    if constexpr (CH == 2) {
+        return fmaxf(R, fmaxf(G, B));
+    } else {
+        const float y = fmaf(0.2989f, R, fmaf(0.5870f, G, 0.1140f * B));
+        if constexpr (CH == 1)
+            return y;
+        const float knee = 0.008856451679035631f; // (6/29)^3
+        const float f = y > knee ? hw_exp2(hw_log2(y) * (1.0f / 3.0f))
+                                 : fmaf(y, 7.787037037037037f, 0.13793103448275862f);
+        return fmaf(1.16f, f, -0.16f);
+    }
+}
+
+// One tile of a comparator channel (4 units per thread), same walks and
+// encodings as the decolorization; values are already normalised.
+template <int SRC, int CH>
+__device__ __forceinline__ void channel_tile(const DevImage &im, int64_t tile)
+{
+    constexpr int U = 4;
+    constexpr int PPU = unit_px(SRC);
+    constexpr int ES = elem_size(SRC);
+    constexpr int64_t TILE = (int64_t)kBlock * U * PPU;
+    const TileRef t = tile_ref(im, tile, TILE);
+    const Enc e{1.0f, 255.0f};
+    const bool vec = im.walk != kWalkScalar;
+    if (vec && t.rem >= TILE) {
+        unsigned w[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float v[PPU];
+#pragma unroll
+            for (int j = 0; j < PPU; ++j)
+                v[j] = comparator_px<CH>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
+                                         chan<SRC>(w[u], 3 * j + 2), im.unit);
+            const uint32_t lp = slot_lp<PPU>(true, u, 0);
+            store_unit<PPU, false, true>(t.dst, im.dst_dtype, lp, v, e);
+            if (t.dst2)
+                store_unit<PPU, false, true>(t.dst2, im.dst2_dtype, lp, v, e);
+        }
+        return;
+    }
+    const uint32_t rem = (uint32_t)(t.rem < TILE ? t.rem : TILE);
+#pragma unroll 1
+    for (int s = 0; s < U * PPU; ++s) {
+        const uint32_t p = slot_lp<PPU>(vec, s / PPU, s % PPU);
+        if (p < rem) {
+            float R, G_, B;
+            load_px<SRC>(t.src + p * (3 * ES), R, G_, B);
+            const float v = comparator_px<CH>(R, G_, B, im.unit);
+            store_px<false, true>(t.dst, im.dst_dtype, p, v, e);
+            if (t.dst2)
+                store_px<false, true>(t.dst2, im.dst2_dtype, p, v, e);
+        }
+    }
+}
+
+template <int SRC, int CH>
+__global__ __launch_bounds__(kBlock) void k_channel_table(const DevImage *__restrict__ table,
+                                                          const int64_t *__restrict__ tile_end,
+                                                          int img0, int nimg, int64_t t0,
+                                                          int64_t t1)
+{
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
+        const DevImage im = table[i];
+        channel_tile<SRC, CH>(im, tile - im.tile_begin);
+    });
+}
+
 // ------------------------------------------------------------ tone map
 
 __device__ __forceinline__ Part part_empty()
@@ -806,6 +890,30 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
         }
     }
 #undef DC_LAUNCH_TABLE
+    return hipGetLastError();
+}
+
+hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                          int64_t t0, int64_t t1, int src_dtype, int channel, int64_t grid,
+                          hipStream_t s)
+{
+    const dim3 g(grid_of(t1 - t0, grid));
+#define DC_LAUNCH_CH(S, C)                                                                        \
+    hipLaunchKernelGGL((k_channel_table<S, C>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg, \
+                       t0, t1)
+    switch (src_dtype * 4 + channel) {
+    case 0 * 4 + 1: DC_LAUNCH_CH(0, 1); break;
+    case 0 * 4 + 2: DC_LAUNCH_CH(0, 2); break;
+    case 0 * 4 + 3: DC_LAUNCH_CH(0, 3); break;
+    case 1 * 4 + 1: DC_LAUNCH_CH(1, 1); break;
+    case 1 * 4 + 2: DC_LAUNCH_CH(1, 2); break;
+    case 1 * 4 + 3: DC_LAUNCH_CH(1, 3); break;
+    case 2 * 4 + 1: DC_LAUNCH_CH(2, 1); break;
+    case 2 * 4 + 2: DC_LAUNCH_CH(2, 2); break;
+    case 2 * 4 + 3: DC_LAUNCH_CH(2, 3); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DC_LAUNCH_CH
     return hipGetLastError();
 }
 

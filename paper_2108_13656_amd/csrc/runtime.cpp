@@ -332,9 +332,15 @@ struct HostTable {
     std::vector<Run> runs;
 };
 
-void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool tonemap,
+// kind of table: decolorization (tiles of the tuned group count), tone map
+// (fixed 4096-pixel tiles, sorted by input type) or comparator channel (one
+// 48-byte group per thread, sorted by input type).
+enum TableKind { kTabDecolor = 0, kTabTonemap = 1, kTabChannel = 2 };
+
+void build_table(const dc_image *imgs, int32_t n, const dc_params *params, TableKind kind,
                  const Tune &tune, HostTable &h)
 {
+    const bool tonemap = kind == kTabTonemap;
     h.d.resize((size_t)n);
     h.tile_end.resize((size_t)n);
     h.grp_end.resize((size_t)n);
@@ -347,7 +353,7 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool 
     std::vector<int32_t> order((size_t)n);
     for (int32_t i = 0; i < n; ++i)
         order[i] = i;
-    if (tonemap)
+    if (kind != kTabDecolor)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
             return imgs[a].src_dtype < imgs[b].src_dtype;
         });
@@ -356,7 +362,9 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, bool 
     for (int32_t i = 0; i < n; ++i) {
         const dc_image &m = imgs[order[i]];
         const int64_t tile_px =
-            tonemap ? dc::kStatsChunkPx : (int64_t)dc::kBlock * h.groups * dc::group_px(m.src_dtype);
+            tonemap ? dc::kStatsChunkPx
+                    : (int64_t)dc::kBlock * (kind == kTabChannel ? 1 : h.groups) *
+                          dc::group_px(m.src_dtype);
         h.d[i] = describe(m, order[i], tile_px, params);
         if (h.runs.empty() || h.runs.back().src != m.src_dtype)
             h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype});
@@ -685,7 +693,7 @@ int plan_build(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n, const
     p->tm = tm_of(tm);
     p->stats = (dc::StatsOut *)stats;
     p->graph = (flags & DC_PLAN_GRAPH) != 0;
-    build_table(imgs, n, params, kind == DC_PLAN_TONEMAP, tune, p->h);
+    build_table(imgs, n, params, kind == DC_PLAN_TONEMAP ? kTabTonemap : kTabDecolor, tune, p->h);
     const Layout l = layout_of(p->h);
     std::vector<char> up(l.upload);
     write_upload(p->h, l, up.data());
@@ -925,7 +933,7 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
         return rc;
     const hipStream_t st = (hipStream_t)stream;
     HostTable h;
-    build_table(imgs, n, params, false, ctx->tune, h);
+    build_table(imgs, n, params, kTabDecolor, ctx->tune, h);
     dc_ctx::Slot *slot = nullptr;
     DevBufs b;
     rc = stage(ctx, h, st, &slot, &b);
@@ -949,7 +957,7 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
         return rc;
     const hipStream_t st = (hipStream_t)stream;
     HostTable h;
-    build_table(imgs, n, params, true, ctx->tune, h);
+    build_table(imgs, n, params, kTabTonemap, ctx->tune, h);
     dc_ctx::Slot *slot = nullptr;
     DevBufs b;
     rc = stage(ctx, h, st, &slot, &b);
@@ -958,6 +966,39 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
     rc = enqueue_tonemap(ctx, h, b, ctx->tune, tm_of(tm), (dc::StatsOut *)stats, st, true);
     if (rc != DC_OK)
         return rc;
+    return release_slot(slot, st);
+}
+
+int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t channel, void *stream)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    if (channel < DC_CH_Y601 || channel > DC_CH_CIELAB_L)
+        return fail(DC_ERR_INVALID_ARG, "channel must be DC_CH_Y601, DC_CH_HSV_V or DC_CH_CIELAB_L");
+    rc = dc_validate(imgs, n, nullptr, nullptr);
+    if (rc != DC_OK || n == 0)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    HostTable h;
+    build_table(imgs, n, nullptr, kTabChannel, ctx->tune, h);
+    dc_ctx::Slot *slot = nullptr;
+    DevBufs b;
+    rc = stage(ctx, h, st, &slot, &b);
+    if (rc != DC_OK)
+        return rc;
+    mark(ctx, true, 0, st);
+    hipError_t e = hipSuccess;
+    for (const auto &r : h.runs) {
+        if (e == hipSuccess)
+            e = dc::launch_channel(b.table, b.tile_end, r.img0, r.img1 - r.img0,
+                                   h.d[r.img0].tile_begin, h.tile_end[r.img1 - 1], r.src, channel,
+                                   0, st);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "channel launch");
+    mark(ctx, true, 1, st);
     return release_slot(slot, st);
 }
 
@@ -1294,7 +1335,7 @@ int server_step(dc_server *sv)
             imgs[i] = ln.batch.back().r.img;
         }
         HostTable h;
-        build_table(imgs.data(), (int32_t)k, &sv->cfg.params, true, sv->ctx->tune, h);
+        build_table(imgs.data(), (int32_t)k, &sv->cfg.params, kTabTonemap, sv->ctx->tune, h);
         dc_ctx::Slot *slot = nullptr;
         DevBufs b;
         int rc = stage(sv->ctx, h, ln.s, &slot, &b);
