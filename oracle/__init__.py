@@ -6,7 +6,7 @@ library and its Python binding) never does, and the two share no code.
 
 Every function here marshals arguments and calls the C oracle, whose header
 comment cites the passages of arXiv 2108.13656 it follows (Sec. II-B, Eqs.
-(1)-(6); Sec. III-B.1 for the tone curve).
+(1)-(6); Sec. III-B.1 for the tone curve and its colour output).
 """
 import ctypes
 import os
@@ -70,6 +70,11 @@ def _load():
     lib.ref_tonemap_curve_array.argtypes = [vp, i64, d, d, d, d, d, vp]
     lib.ref_tonemap_image.restype = i32
     lib.ref_tonemap_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, vp, vp, vp, i32]
+    lib.ref_colour_channel.restype = d
+    lib.ref_colour_channel.argtypes = [d, d, d, d]
+    lib.ref_tonemap_colour_image.restype = i32
+    lib.ref_tonemap_colour_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, d, vp, vp, vp,
+                                             vp, i32]
     _lib = lib
     return lib
 
@@ -195,3 +200,26 @@ def tonemap(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_floor=1e
         raise ValueError("oracle rejected the image")
     stats = {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": w * h}
     return t, lhat, stats
+
+
+def colour_channel(c, lhat, t, saturation=1.0):
+    """One re-coloured channel min(1, T (C / Lhat)^s); grey T where Lhat == 0."""
+    return _load().ref_colour_channel(c, lhat, t, saturation)
+
+
+def tonemap_colour(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_floor=1e-3,
+                   saturation=1.0, nthreads=1):
+    """Colour global tone map of one image: (rgb float64 HxWx3, T HxW, Lhat HxW,
+    stats dict)."""
+    img, code, w, h, pitch = _image_args(img)
+    t = np.empty((h, w), np.float64)
+    lhat = np.empty((h, w), np.float64)
+    rgb = np.empty((h, w, 3), np.float64)
+    st = np.zeros(4, np.float64)
+    rc = _load().ref_tonemap_colour_image(_ptr(img), code, w, h, pitch, beta_r, beta_k, eps,
+                                          contrast, sigma_floor, saturation, _ptr(lhat), _ptr(t),
+                                          _ptr(rgb), _ptr(st), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the image or the saturation")
+    stats = {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": w * h}
+    return rgb, t, lhat, stats

@@ -430,3 +430,63 @@ int ref_tonemap_image(const void *src, int dtype, int W, int H, int64_t pitch_by
         free(lhat);
     return rc;
 }
+
+/* ------------------------------------------------- colour re-synthesis */
+
+/* Colour output of the global tone map. Sec. III-B.1 shows its tone-mapped
+ * results in colour but gives no re-colouring formula; the reading used here
+ * is the classic ratio re-colouring of a tone-mapped luminance: each channel
+ * C of the pixel, in the same normalised units as Lhat, becomes
+ *     C_out = min(1, T (C / Lhat)^s),
+ * with saturation exponent s >= 0 and 0^0 = 1. With s = 1 every channel ratio
+ * is kept and, Eqs. (1)-(6) being homogeneous of degree 1, the luminance of the
+ * unclamped output is T itself; s = 0 gives the grey T. A pixel with
+ * Lhat == 0 has no defined ratio and becomes grey T. NaN and negative channel
+ * values read as 0, as in the luminance. */
+double ref_colour_channel(double c, double lhat, double t, double s)
+{
+    c = sanitise(c);
+    if (!(lhat > 0.0))
+        return t;
+    double v = t * pow(c / lhat, s);
+    return v < 1.0 ? v : 1.0;
+}
+
+/* Colour global tone map of one image: T, Lhat and the statistics as
+ * ref_tonemap_image, then the re-coloured RGB of every pixel into rgb_out
+ * (W*H*3 doubles, row-major, channels interleaved). lhat_out may be NULL.
+ * Returns 0, or -1 on a bad argument or allocation failure. */
+int ref_tonemap_colour_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes,
+                             double beta_r, double beta_k, double eps, double contrast,
+                             double sigma_floor, double saturation, double *lhat_out,
+                             double *t_out, double *rgb_out, double *stats, int nthreads)
+{
+    int64_t n = (int64_t)W * H;
+    double *lhat = lhat_out;
+    if (!t_out || !rgb_out || !stats || !(saturation >= 0.0))
+        return -1;
+    if (!lhat) {
+        lhat = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        if (!lhat)
+            return -1;
+    }
+    int rc = ref_tonemap_image(src, dtype, W, H, pitch_bytes, beta_r, beta_k, eps, contrast,
+                               sigma_floor, lhat, t_out, stats, nthreads);
+    if (rc == 0) {
+        int es = dtype_size(dtype);
+        double unit = dtype == REF_U8 ? 255.0 : 1.0;
+        for (int y = 0; y < H; ++y) {
+            const unsigned char *row = (const unsigned char *)src + (int64_t)y * pitch_bytes;
+            for (int x = 0; x < W; ++x) {
+                const unsigned char *p = row + (int64_t)3 * es * x;
+                int64_t i = (int64_t)y * W + x;
+                for (int c = 0; c < 3; ++c)
+                    rgb_out[3 * i + c] = ref_colour_channel(load_channel(p, dtype, c) / unit,
+                                                            lhat[i], t_out[i], saturation);
+            }
+        }
+    }
+    if (!lhat_out)
+        free(lhat);
+    return rc;
+}

@@ -7,7 +7,8 @@ product path imports it.
 Follows Sec. II-B, Eqs. (1)-(6) of arXiv 2108.13656 for the luminance, and this
 project's reading of the centred-sigmoid global tone curve of Sec. III-B.1 (log
 domain, centred on the mean of ln(Lhat + eps), slope normalised by the
-population standard deviation).
+population standard deviation) and of its colour output (ratio re-colouring
+C_out = min(1, T (C / Lhat)^s)).
 """
 import math
 
@@ -118,3 +119,36 @@ def comparator(r, g, b, kind):
     else:
         f = gray / (3.0 * (6.0 / 29.0) ** 2) + 4.0 / 29.0
     return (116.0 * f - 16.0) / 100.0
+
+
+def colour_channel(c, lhat, t, s):
+    """One re-coloured channel: min(1, T (C / Lhat)^s), grey T where Lhat == 0,
+    0^0 = 1 (normalised units)."""
+    c = _clean(c)
+    if not lhat > 0.0:
+        return t
+    ratio = c / lhat
+    v = t * (1.0 if s == 0.0 else (0.0 if ratio == 0.0 else ratio ** s))
+    return min(v, 1.0)
+
+
+def tonemap_colour(pixels, dtype, eps, contrast, sigma_floor, saturation,
+                   beta_r=BETA_R, beta_k=BETA_K):
+    """Colour global tone map of a nested-list image (same conventions as
+    decolorize_image): returns (rgb rows of (r, g, b), T rows)."""
+    lhat = decolorize_image(pixels, dtype, beta_r, beta_k)
+    flat = [v for row in lhat for v in row]
+    mu, sigma, _, _ = tonemap_stats(flat, eps)
+    unit = 255.0 if dtype == "u8" else 1.0
+    rgb, t_rows = [], []
+    for row, lrow in zip(pixels, lhat):
+        out_row, t_row = [], []
+        for px, lh in zip(row, lrow):
+            if dtype == "f16":
+                px = [half_bits_to_float(int(v)) for v in px]
+            t = tonemap_curve(lh, eps, contrast, mu, sigma, sigma_floor)
+            out_row.append(tuple(colour_channel(float(v) / unit, lh, t, saturation) for v in px))
+            t_row.append(t)
+        rgb.append(out_row)
+        t_rows.append(t_row)
+    return rgb, t_rows
