@@ -67,7 +67,9 @@ def parse():
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--requests", type=int, default=10000, help="serving trace length")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serving memory budget")
-    ap.add_argument("--only", choices=["tonemap", "video", "uneven", "serve"], default=None,
+    ap.add_argument("--skip-colour", action="store_true")
+    ap.add_argument("--only", choices=["tonemap", "colour", "video", "uneven", "serve"],
+                    default=None,
                     help="time one workload only (for profiler runs)")
     ap.add_argument("--tuning", default=None,
                     help="JSON launch shapes to use instead of autotuning (written by --save-tuning)")
@@ -228,12 +230,17 @@ def main():
     # ---------------------------------------------------- HDR tone map (headline)
     n_img, size = args.images, args.size
     hdr_px = n_img * size * size
-    if args.only in (None, "tonemap"):
+    run_gray = args.only in (None, "tonemap")
+    run_colour = args.only in (None, "colour") and not args.skip_colour
+    if run_gray or run_colour:
         log("generating %d HDR images %dx%d" % (n_img, size, size))
         t0 = time.time()
         imgs = gen_hdr(n_img, size)
         log("generated in %.1f s" % (time.time() - t0))
         xs = [torch.from_numpy(a).to(dev) for a in imgs]
+        torch.cuda.synchronize()
+    tuning = None
+    if run_gray:
         outs = [torch.empty((size, size), dtype=torch.float32, device=dev) for _ in xs]
         stats = torch.empty((n_img, P.STATS_BYTES), dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
@@ -306,7 +313,57 @@ def main():
             log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
         plan.close()
         plan_ev.close()
-        del xs, outs
+        del outs
+        torch.cuda.empty_cache()
+
+    # ------------------------------------- HDR tone map with re-coloured RGB output
+    if run_colour:
+        # Same images and launch shapes as the gray tone map; the curve pass
+        # writes min(1, T (C / L)^s) per channel as 8-bit RGB.
+        couts = [torch.empty((size, size, 3), dtype=torch.uint8, device=dev) for _ in xs]
+        with torch.cuda.stream(stream):
+            if tuning is None:
+                tuning = tune(P.PLAN_TONEMAP, xs, couts)
+        legs = {}
+        for sat in (1.0, 0.6):
+            with torch.cuda.stream(stream):
+                cplan = P.Plan(P.PLAN_TONEMAP, xs, couts, graph=True, saturation=sat)
+                cms = time_steps(lambda: cplan.run(stream), args.steps, args.warmup, stream)
+                P.set_tuning(dict(tuning, tonemap_pipeline=0), dev)
+                cev = P.Plan(P.PLAN_TONEMAP, xs, couts, graph=False, saturation=sat)
+                ck = kernel_times(lambda: cev.run(stream), max(5, args.steps // 2), P, dev)
+                P.set_tuning(tuning, dev)
+                cplan.close()
+                cev.close()
+            key = "tonemap_colour_s1" if sat == 1.0 else "tonemap_colour_pow"
+            cach = hdr_px * 9 / (ck[2] * 1e-3) / 1e9
+            legs["s=%g" % sat] = {
+                "ms_per_step": round(cms, 4), "value": round(hdr_px / (cms * 1e-3) / 1e9, 3),
+                "unit": "Gpixels/s",
+                "kernel_ms": {"tonemap_pass1": round(ck[0], 4), "tonemap_combine": round(ck[1], 4),
+                              "tonemap_colour": round(ck[2], 4)},
+                "roofline": {"bound": "hbm", "kernel": key, "achieved": round(cach, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(cach / HBM_PEAK_GBS, 4), "traffic": traffic.get(key),
+                             "algorithmic_bytes": hdr_px * 9}}
+            log("colour tone map s=%g: step %.3f ms (%.1f Gpx/s); kernels %s ms; curve pass %.0f GB/s"
+                % (sat, cms, legs["s=%g" % sat]["value"], ", ".join("%.3f" % t for t in ck), cach))
+        colour = {"workload": "hdr_tonemap_colour", "images": n_img, "height": size, "width": size,
+                  "src": "f16 linear RGB", "dst": "u8 RGB, min(1, T (C / L)^s) per channel",
+                  "legs": legs}
+        if result:
+            result["colour_tonemap"] = colour
+        else:
+            first = legs["s=1"]
+            result.update({"metric": METRIC, "value": first["value"], "unit": "Gpixels/s",
+                           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                           "ms_per_step": first["ms_per_step"], "higher_is_better": True,
+                           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                           "data": "synthetic", "config": {"workload": "hdr_tonemap_colour"},
+                           "roofline": first["roofline"], "colour_tonemap": colour})
+        del couts
+    if run_gray or run_colour:
+        del xs
         torch.cuda.empty_cache()
 
     # ---------------------------------------------------- video batch decolorize

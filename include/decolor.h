@@ -18,6 +18,12 @@
  *       x = ln(Lhat + eps) over all pixels of one image,
  *       mu = mean(x), sigma = population standard deviation of x,
  *       T  = 1 / (1 + exp(-contrast (x - mu) / max(sigma, sigma_floor))).
+ *     The paper shows its tone-mapped results in colour without a formula;
+ *     the colour output (DC_IMG_RGB_OUT) is read as the ratio re-colouring
+ *       C_out = min(1, T (C / Lhat)^s)   for C = R, G, B (normalised units),
+ *     saturation s >= 0; a pixel with Lhat == 0 becomes grey T. With s = 1
+ *     the channel ratios are kept and the output's Eqs. (1)-(6) luminance is
+ *     T wherever no channel was clamped.
  *
  * Units. 8-bit inputs are code values 0..255 (no gamma linearisation); binary16
  * and binary32 inputs are linear values as stored. Lhat, the "normalised"
@@ -84,17 +90,26 @@ typedef struct dc_params {
 
 /* Global tone-curve parameters (Sec. III-B.1 reading above). eps > 0 keeps the
  * logarithm finite on black pixels; contrast > 0 is the slope in units of the
- * image's standard deviation; sigma_floor > 0 bounds the slope on flat images. */
+ * image's standard deviation; sigma_floor > 0 bounds the slope on flat images;
+ * saturation in [0, 2] is the exponent s of the colour output (used only by
+ * images flagged DC_IMG_RGB_OUT; note that a zero-filled struct asks for s = 0,
+ * a grey result). */
 typedef struct dc_tm_params {
     float eps;         /* default 1e-4 */
     float contrast;    /* default 2.0  */
     float sigma_floor; /* default 1e-3 */
+    float saturation;  /* default 1.0  */
 } dc_tm_params;
 
 /* One image. width, height >= 1. src_pitch >= 3 * width * sizeof(src element);
  * dst_pitch >= width * sizeof(dst element); dst2 (optional, NULL with
  * dst2_dtype = DC_NONE) likewise. Outputs must not overlap the input or each
- * other. flags must be 0. */
+ * other. flags is 0, or DC_IMG_RGB_OUT in a tone-map call (dc_tonemap_global,
+ * DC_PLAN_TONEMAP plans, server requests): dst then receives the re-coloured
+ * interleaved RGB (3 channels, R first, dst_pitch >= 3 * width * sizeof(dst
+ * element)) instead of the gray T; dst2 keeps its meaning. Other calls reject
+ * the flag with DC_ERR_UNSUPPORTED; unknown bits are DC_ERR_INVALID_ARG. */
+#define DC_IMG_RGB_OUT 1
 typedef struct dc_image {
     const void *src; /* device, interleaved RGB, row y at src + y * src_pitch */
     void *dst;       /* device, 1 channel */
@@ -107,7 +122,7 @@ typedef struct dc_image {
     int32_t src_dtype;  /* DC_U8, DC_F16 or DC_F32 */
     int32_t dst_dtype;  /* DC_U8, DC_F16 or DC_F32 */
     int32_t dst2_dtype; /* DC_NONE, DC_U8, DC_F16 or DC_F32 */
-    int32_t flags;      /* reserved, 0 */
+    int32_t flags;      /* 0 or DC_IMG_RGB_OUT */
 } dc_image;
 
 /* Per-image statistics of the global tone map (FP32 accumulation). */
@@ -150,7 +165,8 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
 /* Global tone map (Sec. III-B.1 reading above) of n images: per image, one
  * statistics pass fused with the decolorization (Eqs. (1)-(6)), a fixed-order
  * combine of per-chunk partials, and a curve pass that recomputes L and writes
- * T to dst (and Lhat to dst2 if set). imgs is a HOST array; tm NULL means the
+ * T to dst, or the re-coloured RGB for images flagged DC_IMG_RGB_OUT (and
+ * Lhat to dst2 if set). imgs is a HOST array; tm NULL means the
  * defaults; stats, if not NULL, is a DEVICE array of n dc_stats that receives
  * each image's statistics. Results of an image do not depend on which other
  * images share the call. */

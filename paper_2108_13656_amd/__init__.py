@@ -29,7 +29,8 @@ _TORCH_TO_DC = {torch.uint8: DC_U8, torch.float16: DC_F16, torch.float32: DC_F32
 
 BETA_R = 0.55  # Eq. (3) weight chosen after Eq. (6)
 BETA_K = 0.80  # Eq. (6) weight
-TM_EPS, TM_CONTRAST, TM_SIGMA_FLOOR = 1e-4, 2.0, 1e-3
+TM_EPS, TM_CONTRAST, TM_SIGMA_FLOOR, TM_SATURATION = 1e-4, 2.0, 1e-3, 1.0
+DC_IMG_RGB_OUT = 1  # dc_image.flags: tone-map dst holds re-coloured RGB
 
 
 class DcImage(ctypes.Structure):
@@ -47,7 +48,7 @@ class DcParams(ctypes.Structure):
 
 class DcTmParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("contrast", ctypes.c_float),
-                ("sigma_floor", ctypes.c_float)]
+                ("sigma_floor", ctypes.c_float), ("saturation", ctypes.c_float)]
 
 
 class DcStats(ctypes.Structure):
@@ -242,6 +243,18 @@ def _check_gray(y, h, w, device):
         raise ValueError("output rows must be packed (strides (pitch, 1))")
 
 
+def _check_out(y, h, w, device):
+    """HxW gray output, or HxWx3 colour output (tone map only)."""
+    if y.dim() == 3:
+        if tuple(y.shape) != (h, w, 3) or y.device != device:
+            raise ValueError("colour output must be an HxWx3 tensor on the input's device")
+        if y.stride(2) != 1 or y.stride(1) != 3 or y.stride(0) < 3 * w:
+            raise ValueError("colour output must have strides (pitch, 3, 1)")
+        return DC_IMG_RGB_OUT
+    _check_gray(y, h, w, device)
+    return 0
+
+
 def _image(x, out, out2):
     h, w = x.shape[0], x.shape[1]
     d = DcImage()
@@ -249,7 +262,7 @@ def _image(x, out, out2):
     d.src_pitch = x.stride(0) * x.element_size()
     d.width, d.height = w, h
     d.src_dtype = _dc_dtype(x.dtype)
-    _check_gray(out, h, w, x.device)
+    flags = _check_out(out, h, w, x.device)
     d.dst = out.data_ptr()
     d.dst_pitch = out.stride(0) * out.element_size()
     d.dst_dtype = _dc_dtype(out.dtype)
@@ -260,7 +273,7 @@ def _image(x, out, out2):
         d.dst2 = out2.data_ptr()
         d.dst2_pitch = out2.stride(0) * out2.element_size()
         d.dst2_dtype = _dc_dtype(out2.dtype)
-    d.flags = 0
+    d.flags = flags
     return d
 
 
@@ -273,8 +286,8 @@ def _stream_ptr(stream, device):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _alloc(x, dtype, h, w):
-    return torch.empty((h, w), dtype=dtype, device=x.device)
+def _alloc(x, dtype, h, w, colour=False):
+    return torch.empty((h, w, 3) if colour else (h, w), dtype=dtype, device=x.device)
 
 
 # ------------------------------------------------------------- public API
@@ -349,23 +362,26 @@ def channel_batch(xs, channel, out_dtype=torch.float32, out2_dtype=None, outs=No
 
 def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
                    eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, outs=None,
-                   lhats=None, stats=None, want_stats=True, stream=None):
+                   lhats=None, stats=None, want_stats=True, stream=None, colour=False,
+                   saturation=TM_SATURATION):
     """Global tone map (Sec. III-B.1, centred sigmoid on ln(Lhat + eps)) of a
-    list of images. Returns (T outputs, Lhat outputs or None, stats) where
-    stats is a uint8 device tensor of n x 24 bytes (see ``stats_to_host``)."""
+    list of images. Returns (outputs, Lhat outputs or None, stats) where stats
+    is a uint8 device tensor of n x 24 bytes (see ``stats_to_host``). Outputs
+    are HxW T, or HxWx3 re-coloured RGB min(1, T (C / Lhat)^saturation) with
+    colour=True (given ``outs`` may mix both shapes)."""
     xs = list(xs)
     if not xs:
         return [], None, None
     dev = xs[0].device
     if outs is None:
-        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1], colour) for x in xs]
     if lhats is None and lhat_dtype is not None:
         lhats = [_alloc(x, lhat_dtype, x.shape[0], x.shape[1]) for x in xs]
     if stats is None and want_stats:
         stats = torch.empty((len(xs), STATS_BYTES), dtype=torch.uint8, device=dev)
     arr = _image_array(xs, outs, lhats)
     p = _params(beta_r, beta_k)
-    tm = DcTmParams(eps, contrast, sigma_floor)
+    tm = DcTmParams(eps, contrast, sigma_floor, saturation)
     _check(lib().dc_tonemap_global(context(dev).handle, arr, len(xs), ctypes.byref(p),
                                    ctypes.byref(tm),
                                    ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
@@ -387,6 +403,8 @@ def validate(images, beta_r=BETA_R, beta_k=BETA_K, tm=None):
     """Host-only check of DcImage descriptors (no GPU needed). Returns the status."""
     arr = (DcImage * len(images))(*images) if images else None
     p = _params(beta_r, beta_k)
+    if tm is not None and len(tm) == 3:
+        tm = tuple(tm) + (TM_SATURATION,)
     tmp = DcTmParams(*tm) if tm is not None else None
     return lib().dc_validate(arr, len(images), ctypes.byref(p),
                              ctypes.byref(tmp) if tmp is not None else None)
@@ -398,13 +416,14 @@ class Plan:
     enqueues only the kernels (or replays a captured HIP graph)."""
 
     def __init__(self, kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
-                 contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stats=None, graph=False):
+                 contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stats=None, graph=False,
+                 saturation=TM_SATURATION):
         xs = list(xs)
         self.device = xs[0].device
         self._keep = (xs, list(outs), None if outs2 is None else list(outs2), stats)
         arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
         p = _params(beta_r, beta_k)
-        tm = DcTmParams(eps, contrast, sigma_floor) if kind == PLAN_TONEMAP else None
+        tm = DcTmParams(eps, contrast, sigma_floor, saturation) if kind == PLAN_TONEMAP else None
         self._h = ctypes.c_void_p()
         _check(lib().dc_plan_create(context(self.device).handle, kind, arr, len(xs),
                                     ctypes.byref(p), ctypes.byref(tm) if tm is not None else None,
@@ -426,9 +445,11 @@ class Plan:
             pass
 
 
-def make_request(rid, src, src_dtype, width, height, src_pitch, dst_dtype, dst=None, dst_pitch=0):
+def make_request(rid, src, src_dtype, width, height, src_pitch, dst_dtype, dst=None, dst_pitch=0,
+                 flags=0):
     """A DcRequest for a device image given by raw pointer (dst None: the
-    server allocates and frees the output)."""
+    server allocates and frees the output; flags DC_IMG_RGB_OUT asks for the
+    re-coloured RGB)."""
     r = DcRequest()
     r.id = rid
     r.img.src = src
@@ -438,32 +459,35 @@ def make_request(rid, src, src_dtype, width, height, src_pitch, dst_dtype, dst=N
     r.img.dst = dst
     r.img.dst_pitch = dst_pitch
     r.img.dst_dtype = dst_dtype
-    r.img.dst2, r.img.dst2_pitch, r.img.dst2_dtype, r.img.flags = None, 0, DC_NONE, 0
+    r.img.dst2, r.img.dst2_pitch, r.img.dst2_dtype, r.img.flags = None, 0, DC_NONE, flags
     return r
 
 
-def request_for(rid, x, out=None, out_dtype=torch.float32):
-    """A DcRequest for an HxWx3 device tensor (and an optional HxW output)."""
+def request_for(rid, x, out=None, out_dtype=torch.float32, colour=False):
+    """A DcRequest for an HxWx3 device tensor (and an optional HxW, or with
+    colour HxWx3, output)."""
     _check_rgb(x)
+    flags = DC_IMG_RGB_OUT if colour else 0
     if out is not None:
-        _check_gray(out, x.shape[0], x.shape[1], x.device)
+        flags = _check_out(out, x.shape[0], x.shape[1], x.device)
     return make_request(rid, x.data_ptr(), _dc_dtype(x.dtype), x.shape[1], x.shape[0],
                         x.stride(0) * x.element_size(),
                         _dc_dtype(out.dtype if out is not None else out_dtype),
                         None if out is None else out.data_ptr(),
-                        0 if out is None else out.stride(0) * out.element_size())
+                        0 if out is None else out.stride(0) * out.element_size(), flags)
 
 
 class Server:
     """Continuous-batching tone-map server (``dc_server_*``)."""
 
     def __init__(self, budget_bytes, max_batch=64, max_inflight=4, beta_r=BETA_R, beta_k=BETA_K,
-                 eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, device=None):
+                 eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, device=None,
+                 saturation=TM_SATURATION):
         if device is None:
             device = torch.cuda.current_device()
         self.device = device if isinstance(device, torch.device) else torch.device("cuda", device)
         cfg = DcServerConfig(budget_bytes, max_batch, max_inflight, 0, DcParams(beta_r, beta_k),
-                             DcTmParams(eps, contrast, sigma_floor))
+                             DcTmParams(eps, contrast, sigma_floor, saturation))
         self._h = ctypes.c_void_p()
         _check(lib().dc_server_create(context(self.device).handle, ctypes.byref(cfg),
                                       ctypes.byref(self._h)))
@@ -521,14 +545,15 @@ def set_tuning(d, device=None):
 
 
 def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
-             contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stream=None):
+             contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stream=None,
+             saturation=TM_SATURATION):
     """Runs the library's launch-shape search on these buffers and returns the
     tuning it kept (a dict, see ``get_tuning``)."""
     xs = list(xs)
     dev = xs[0].device
     arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
     p = _params(beta_r, beta_k)
-    tm = DcTmParams(eps, contrast, sigma_floor)
+    tm = DcTmParams(eps, contrast, sigma_floor, saturation)
     t = DcTuning()
     _check(lib().dc_autotune(context(dev).handle, kind, arr, len(xs), ctypes.byref(p),
                              ctypes.byref(tm), _stream_ptr(stream, dev), ctypes.byref(t)))

@@ -61,6 +61,7 @@ struct DevImage {
     int32_t dst2_dtype;     // -1 = none
     int32_t walk;
     int32_t image;          // index within the call
+    int32_t rgb_out;        // tone map: dst holds 3 channels (re-coloured RGB)
     float unit;             // Lhat = L * unit (1/255 for 8-bit input)
     Coef k;                 // per-pixel constants for this image's input type
 };
@@ -81,7 +82,11 @@ struct TmArgs {
     float eps;
     float contrast;
     float sigma_floor;
+    float saturation; // exponent s of the colour output
 };
+
+// Colour output modes: s = 0 (grey T), s = 1 (ratio kept), any other s.
+enum ColourMode : int { kColourGrey = 0, kColourRatio = 1, kColourPow = 2 };
 
 // Output statistics, laid out as dc_stats.
 struct StatsOut {
@@ -105,6 +110,9 @@ hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int 
                              hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
                               const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s);
+hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                            int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
+                            const Curve *curves, int64_t grid, hipStream_t s);
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                            int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            const Curve *curves, int64_t grid, hipStream_t s);

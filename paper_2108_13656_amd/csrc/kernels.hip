@@ -267,6 +267,8 @@ struct TileRef {
     int64_t rem;
 };
 
+// DST_CH = channels per pixel of dst (3 for the re-coloured tone map).
+template <int DST_CH = 1>
 __device__ __forceinline__ TileRef tile_ref(const DevImage &im, int64_t tile, int64_t tile_px)
 {
     const int64_t seg = tile / im.tiles_per_seg;
@@ -274,7 +276,7 @@ __device__ __forceinline__ TileRef tile_ref(const DevImage &im, int64_t tile, in
     const int64_t px0 = ts * tile_px;
     TileRef t;
     t.src = im.src + seg * im.src_seg_stride + px0 * 3 * elem_size(im.src_dtype);
-    t.dst = im.dst + seg * im.dst_seg_stride + px0 * elem_size(im.dst_dtype);
+    t.dst = im.dst + seg * im.dst_seg_stride + px0 * DST_CH * elem_size(im.dst_dtype);
     t.dst2 = im.dst2 ? im.dst2 + seg * im.dst2_seg_stride + px0 * elem_size(im.dst2_dtype)
                      : nullptr;
     t.rem = im.seg_len - px0;
@@ -828,6 +830,188 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
     });
 }
 
+// ------------------------------------------------- colour re-synthesis
+
+// Colour output of the tone map for one pixel: every channel C becomes
+// T (C / L)^s, clamped to at most 1, with C and L in the input's units (their
+// ratio is unit-free); E is the curve's exponential, T = 1 / (1 + E). A pixel
+// with no colour to carry (all channels 0, or L at most 1e-6 S, which only
+// the degenerate weights 0 produce) becomes grey T. The ratio is formed
+// first, so its logarithm stays small for ordinary colours and the power is
+// accurate: MODE kColourRatio (s = 1) is C (T / L); kColourPow is
+// exp2(min(s log2(C / L) + log2 T, 0)) with log2 T = -log2(1 + E), which
+// stays finite where T underflows; kColourGrey (s = 0) is T everywhere.
+template <int SRC, int MODE>
+__device__ __forceinline__ void colour_px(float R, float G, float B, float l, float E, float s,
+                                          float *o)
+{
+    if constexpr (SRC != 0) {
+        R = fmaxf(R, 0.0f);
+        G = fmaxf(G, 0.0f);
+        B = fmaxf(B, 0.0f);
+    }
+    const float T = hw_rcp(1.0f + E);
+    if constexpr (MODE == kColourGrey) {
+        o[0] = o[1] = o[2] = T;
+        return;
+    }
+    const float S = (R + G) + B;
+    const bool grey = !(S > 0.0f) || !(l > S * 1e-6f);
+    const float C[3] = {R, G, B};
+    if constexpr (MODE == kColourRatio) {
+        const float k = T * hw_rcp(l);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            o[c] = grey ? T : fminf(C[c] * k, 1.0f);
+    } else {
+        const float lT = -hw_log2(1.0f + E);
+        const float il = hw_rcp(l);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            o[c] = grey ? T : hw_exp2(fminf(fmaf(s, hw_log2(C[c] * il), lT), 0.0f));
+    }
+}
+
+// Stores the 3 * PPU channel values of one unit (PPU pixels) at pixel lp of
+// an interleaved RGB row whose pixel 0 is at base (16-byte aligned on the
+// vector walks, so every unit is aligned to its own size's largest power of
+// two up to 16). 8-bit values are v * 255 by v_cvt_pk_u8_f32.
+template <int PPU>
+__device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_t lp,
+                                               const float (&o)[3 * PPU])
+{
+    if (dtype == 0) {
+        uint8_t *p = base + 3 * lp;
+        if constexpr (PPU == 4) {
+            unsigned w[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                w[j] = 0u;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    w[j] = u8_of<true>(o[4 * j + i], 255.0f, i, w[j]);
+            }
+            DC_GLOBAL unsigned *q = gpw<unsigned>(p);
+            q[0] = w[0];
+            q[1] = w[1];
+            q[2] = w[2];
+        } else if constexpr (PPU == 2) {
+            DC_GLOBAL unsigned short *q = gpw<unsigned short>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = (unsigned short)u8_of<true>(o[2 * j + 1], 255.0f, 1,
+                                                   u8_of<true>(o[2 * j], 255.0f, 0, 0u));
+        } else {
+            DC_GLOBAL uint8_t *q = gpw<uint8_t>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = (uint8_t)u8_of<true>(o[j], 255.0f, 0, 0u);
+        }
+    } else if (dtype == 1) {
+        uint8_t *p = base + 6 * lp;
+        if constexpr (PPU == 4) {
+            DC_GLOBAL u32x2 *q = gpw<u32x2>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = u32x2{pack_f16x2(o[4 * j], o[4 * j + 1]), pack_f16x2(o[4 * j + 2], o[4 * j + 3])};
+        } else if constexpr (PPU == 2) {
+            DC_GLOBAL unsigned *q = gpw<unsigned>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = pack_f16x2(o[2 * j], o[2 * j + 1]);
+        } else {
+            DC_GLOBAL _Float16 *q = gpw<_Float16>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = (_Float16)o[j];
+        }
+    } else {
+        uint8_t *p = base + 12 * lp;
+        unsigned b[3 * PPU];
+#pragma unroll
+        for (int i = 0; i < 3 * PPU; ++i)
+            b[i] = __builtin_bit_cast(unsigned, o[i]);
+        if constexpr (PPU == 4) {
+            DC_GLOBAL u32x4 *q = gpw<u32x4>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = u32x4{b[4 * j], b[4 * j + 1], b[4 * j + 2], b[4 * j + 3]};
+        } else if constexpr (PPU == 2) {
+            DC_GLOBAL u32x2 *q = gpw<u32x2>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = u32x2{b[2 * j], b[2 * j + 1]};
+        } else {
+            DC_GLOBAL unsigned *q = gpw<unsigned>(p);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                q[j] = b[j];
+        }
+    }
+}
+
+// Curve pass with colour output over one statistics tile: the same units,
+// tiles and T as tm_pass2_tile, and 3 output channels per pixel.
+template <int SRC, int MODE>
+__device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile, TmArgs tm,
+                                               Curve cv)
+{
+    constexpr int PPU = unit_px(SRC);
+    constexpr int U = kStatsPxPerThread / PPU;
+    constexpr int ES = elem_size(SRC);
+    const TileRef t = tile_ref<3>(im, tile, kStatsChunkPx);
+    const Enc e{1.0f, 255.0f};
+    const bool vec = im.walk != kWalkScalar;
+    if (vec && t.rem >= kStatsChunkPx) {
+        unsigned w[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float o[3 * PPU];
+#pragma unroll
+            for (int j = 0; j < PPU; ++j) {
+                const float R = chan<SRC>(w[u], 3 * j), G = chan<SRC>(w[u], 3 * j + 1),
+                            B = chan<SRC>(w[u], 3 * j + 2);
+                const float l = lum<SRC>(R, G, B, im.k);
+                const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
+                colour_px<SRC, MODE>(R, G, B, l, E, tm.saturation, &o[3 * j]);
+            }
+            store_rgb_unit<PPU>(t.dst, im.dst_dtype, slot_lp<PPU>(true, u, 0), o);
+        }
+        return;
+    }
+    const uint32_t rem = (uint32_t)(t.rem < kStatsChunkPx ? t.rem : kStatsChunkPx);
+#pragma unroll 1
+    for (int i = 0; i < kStatsPxPerThread; ++i) {
+        const uint32_t p = slot_lp<PPU>(vec, i / PPU, i % PPU);
+        if (p < rem) {
+            float R, G, B;
+            load_px<SRC>(t.src + p * (3 * ES), R, G, B);
+            const float l = lum<SRC>(R, G, B, im.k);
+            const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
+            float o[3];
+            colour_px<SRC, MODE>(R, G, B, l, E, tm.saturation, o);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                store_px<false, true>(t.dst, im.dst_dtype, 3 * p + c, o[c], e);
+        }
+    }
+}
+
+template <int SRC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_tm_colour(const DevImage *__restrict__ table,
+                                                      const int64_t *__restrict__ tile_end,
+                                                      int img0, int nimg, int64_t t0, int64_t t1,
+                                                      TmArgs tm, const Curve *__restrict__ curves)
+{
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
+        const DevImage im = table[i];
+        tm_colour_tile<SRC, MODE>(im, tile - im.tile_begin, tm, curves[i]);
+    });
+}
+
 // ------------------------------------------------------------ launchers
 
 static unsigned grid_of(int64_t ntiles, int64_t grid)
@@ -951,6 +1135,30 @@ hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs 
 {
     hipLaunchKernelGGL(k_tm_finalize, dim3(nimg), dim3(kBlock), 0, s, table, img0, tm, parts2,
                        curves, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                            int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
+                            const Curve *curves, int64_t grid, hipStream_t s)
+{
+    const dim3 g(grid_of(t1 - t0, grid));
+#define DC_LAUNCH_COL(S, M)                                                                       \
+    hipLaunchKernelGGL((k_tm_colour<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,    \
+                       t0, t1, tm, curves)
+    switch (src_dtype * 4 + mode) {
+    case 0 * 4 + kColourGrey: DC_LAUNCH_COL(0, kColourGrey); break;
+    case 0 * 4 + kColourRatio: DC_LAUNCH_COL(0, kColourRatio); break;
+    case 0 * 4 + kColourPow: DC_LAUNCH_COL(0, kColourPow); break;
+    case 1 * 4 + kColourGrey: DC_LAUNCH_COL(1, kColourGrey); break;
+    case 1 * 4 + kColourRatio: DC_LAUNCH_COL(1, kColourRatio); break;
+    case 1 * 4 + kColourPow: DC_LAUNCH_COL(1, kColourPow); break;
+    case 2 * 4 + kColourGrey: DC_LAUNCH_COL(2, kColourGrey); break;
+    case 2 * 4 + kColourRatio: DC_LAUNCH_COL(2, kColourRatio); break;
+    case 2 * 4 + kColourPow: DC_LAUNCH_COL(2, kColourPow); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DC_LAUNCH_COL
     return hipGetLastError();
 }
 

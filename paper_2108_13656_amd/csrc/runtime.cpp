@@ -68,6 +68,8 @@ int validate_tm(const dc_tm_params *tm)
     for (float x : v)
         if (!std::isfinite(x) || !(x > 0.0f))
             return fail(DC_ERR_INVALID_ARG, "eps, contrast and sigma_floor must be finite and > 0");
+    if (!(tm->saturation >= 0.0f && tm->saturation <= 2.0f))
+        return fail(DC_ERR_INVALID_ARG, "saturation must be in [0, 2]");
     return DC_OK;
 }
 
@@ -91,7 +93,8 @@ int check_src(const dc_image &m, const std::string &at, Range &r)
     return DC_OK;
 }
 
-int validate_images(const dc_image *imgs, int32_t n)
+// rgb_ok: the call is a tone map, so DC_IMG_RGB_OUT (3-channel dst) is allowed.
+int validate_images(const dc_image *imgs, int32_t n, bool rgb_ok)
 {
     if (n < 0)
         return fail(DC_ERR_INVALID_ARG, "n must be >= 0");
@@ -107,8 +110,10 @@ int validate_images(const dc_image *imgs, int32_t n)
             return fail(DC_ERR_INVALID_ARG, "src and dst must not be NULL" + at);
         if (m.width < 1 || m.height < 1)
             return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + at);
-        if (m.flags != 0)
-            return fail(DC_ERR_INVALID_ARG, "flags must be 0" + at);
+        if (m.flags & ~DC_IMG_RGB_OUT)
+            return fail(DC_ERR_INVALID_ARG, "unknown flags" + at);
+        if ((m.flags & DC_IMG_RGB_OUT) && !rgb_ok)
+            return fail(DC_ERR_UNSUPPORTED, "DC_IMG_RGB_OUT applies to the tone map only" + at);
         if (!dtype_ok(m.src_dtype) || !dtype_ok(m.dst_dtype))
             return fail(DC_ERR_INVALID_ARG, "src_dtype and dst_dtype must be DC_U8, DC_F16 or DC_F32" + at);
         if (m.dst2_dtype == DC_NONE) {
@@ -134,10 +139,11 @@ int validate_images(const dc_image *imgs, int32_t n)
             if (!op[o])
                 continue;
             const int64_t eo = dc::elem_size(dt[o]);
-            const int64_t row = eo * (int64_t)m.width;
+            const int64_t ch = (o == 0 && (m.flags & DC_IMG_RGB_OUT)) ? 3 : 1;
+            const int64_t row = ch * eo * (int64_t)m.width;
             if (pitch[o] < row)
                 return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) +
-                                                    "_pitch is smaller than width * element size" + at);
+                                                    "_pitch is smaller than its row bytes" + at);
             if ((uintptr_t)op[o] % eo || pitch[o] % eo)
                 return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) +
                                                     " and its pitch must be multiples of the element size" + at);
@@ -186,7 +192,8 @@ dc::Coef coef_of(const dc_params *p, int src_dtype)
 
 dc::TmArgs tm_of(const dc_tm_params *tm)
 {
-    return tm ? dc::TmArgs{tm->eps, tm->contrast, tm->sigma_floor} : dc::TmArgs{1e-4f, 2.0f, 1e-3f};
+    return tm ? dc::TmArgs{tm->eps, tm->contrast, tm->sigma_floor, tm->saturation}
+              : dc::TmArgs{1e-4f, 2.0f, 1e-3f, 1.0f};
 }
 
 // Walk classification and tile count of one image for tiles of tile_px pixels.
@@ -201,13 +208,14 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
     d.dst_dtype = m.dst_dtype;
     d.dst2_dtype = m.dst2 ? m.dst2_dtype : DC_NONE;
     d.image = index;
+    d.rgb_out = (m.flags & DC_IMG_RGB_OUT) ? 1 : 0;
     d.unit = m.src_dtype == DC_U8 ? (float)(1.0 / 255.0) : 1.0f;
     d.npx = (int64_t)m.width * m.height;
     d.k = coef_of(params, m.src_dtype);
 
     const int64_t W = m.width, H = m.height;
     const int64_t es = dc::elem_size(m.src_dtype);
-    const int64_t e1 = dc::elem_size(m.dst_dtype);
+    const int64_t e1 = dc::elem_size(m.dst_dtype) * (d.rgb_out ? 3 : 1); // dst bytes per pixel
     const int64_t e2 = m.dst2 ? dc::elem_size(m.dst2_dtype) : 0;
     const bool aligned = ((uintptr_t)m.src % 16 == 0) && ((uintptr_t)m.dst % 16 == 0) &&
                          (!m.dst2 || (uintptr_t)m.dst2 % 16 == 0);
@@ -323,11 +331,12 @@ struct HostTable {
     int src0 = 0;
     int groups = 2;  // decolorization only
     bool tonemap = false;
-    // Tone map: the table is stably sorted by input type; runs[k] = {first
-    // image, end image, type} of each run, so each pass launches its
-    // per-type kernel once per run.
+    // Tone map and channels: the table is stably sorted by input type (then
+    // gray before colour output); runs[k] = {first image, end image, type,
+    // colour output} of each run, so each pass launches its per-type kernel
+    // once per run.
     struct Run {
-        int img0, img1, src;
+        int img0, img1, src, rgb;
     };
     std::vector<Run> runs;
 };
@@ -355,7 +364,9 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
         order[i] = i;
     if (kind != kTabDecolor)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            return imgs[a].src_dtype < imgs[b].src_dtype;
+            const int ra = imgs[a].flags & DC_IMG_RGB_OUT, rb = imgs[b].flags & DC_IMG_RGB_OUT;
+            return imgs[a].src_dtype != imgs[b].src_dtype ? imgs[a].src_dtype < imgs[b].src_dtype
+                                                          : ra < rb;
         });
     h.runs.clear();
     int64_t total = 0;
@@ -366,8 +377,9 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
                     : (int64_t)dc::kBlock * (kind == kTabChannel ? 1 : h.groups) *
                           dc::group_px(m.src_dtype);
         h.d[i] = describe(m, order[i], tile_px, params);
-        if (h.runs.empty() || h.runs.back().src != m.src_dtype)
-            h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype});
+        const int rgb = h.d[i].rgb_out;
+        if (h.runs.empty() || h.runs.back().src != m.src_dtype || h.runs.back().rgb != rgb)
+            h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype, rgb});
         else
             h.runs.back().img1 = i + 1;
         h.d[i].tile_begin = total;
@@ -466,6 +478,21 @@ int ensure_fork(dc_ctx *ctx, size_t n)
     return DC_OK;
 }
 
+// Curve pass over tiles [t0, t1) of images img0 .. img0 + nimg - 1, all of
+// input type src and all with (rgb) or without colour output.
+hipError_t launch_curve(const DevBufs &b, int img0, int nimg, int64_t t0, int64_t t1, int src,
+                        int rgb, dc::TmArgs a, int64_t grid, hipStream_t st)
+{
+    if (!rgb)
+        return dc::launch_tm_pass2(b.table, b.tile_end, img0, nimg, t0, t1, 0, src, a, b.curves,
+                                   grid, st);
+    const int mode = a.saturation == 0.0f   ? dc::kColourGrey
+                     : a.saturation == 1.0f ? dc::kColourRatio
+                                            : dc::kColourPow;
+    return dc::launch_tm_colour(b.table, b.tile_end, img0, nimg, t0, t1, src, mode, a, b.curves,
+                                grid, st);
+}
+
 // Kernel sequence of a tone map over a staged table. Mode 0: the statistics
 // pass over every image, the two-level combine, then the curve pass over every
 // image. Mode 1 (t.tm_pipeline): image by image, the statistics pass runs on
@@ -497,8 +524,7 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
         for (const auto &r : h.runs) {
             const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
             if (e == hipSuccess)
-                e = dc::launch_tm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, 0,
-                                        r.src, a, b.curves, g2, st);
+                e = launch_curve(b, r.img0, r.img1 - r.img0, t0, t1, r.src, r.rgb, a, g2, st);
         }
         mark(ctx, marks, 3, st);
         if (e != hipSuccess)
@@ -523,8 +549,7 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
         if (e == hipSuccess)
             e = dc::launch_tm_finalize(b.table, i, 1, a, b.parts2, b.curves, stats, ctx->side);
         if (e == hipSuccess)
-            e = dc::launch_tm_pass2(b.table, b.tile_end, i, 1, t0, t1, 0, src, a, b.curves, g2,
-                                    ctx->side);
+            e = launch_curve(b, i, 1, t0, t1, src, h.d[i].rgb_out, a, g2, ctx->side);
     }
     if (e == hipSuccess)
         e = hipEventRecord(ctx->fork[n], ctx->side);
@@ -780,7 +805,7 @@ int dc_validate(const dc_image *imgs, int32_t n, const dc_params *params, const 
     if (rc == DC_OK)
         rc = validate_tm(tm);
     if (rc == DC_OK)
-        rc = validate_images(imgs, n);
+        rc = validate_images(imgs, n, tm != nullptr);
     return rc;
 }
 
@@ -1252,7 +1277,8 @@ void arena_free(dc_server *sv, size_t off, size_t bytes)
 // packed input keeps the packed vector walk; blocks start on 256-byte granules.
 size_t out_bytes(const dc_image &m, int64_t *pitch)
 {
-    *pitch = (int64_t)dc::elem_size(m.dst_dtype) * m.width;
+    const int64_t ch = (m.flags & DC_IMG_RGB_OUT) ? 3 : 1;
+    *pitch = ch * dc::elem_size(m.dst_dtype) * m.width;
     const size_t b = (size_t)*pitch * (size_t)m.height;
     return (b + kGranule - 1) / kGranule * kGranule;
 }
@@ -1433,10 +1459,12 @@ int dc_server_submit(dc_server *sv, const dc_request *reqs, int32_t n, double t_
         int rc = check_src(m, at, r);
         if (rc != DC_OK)
             return rc;
-        if (!dtype_ok(m.dst_dtype) || m.dst2 || m.dst2_dtype != DC_NONE || m.flags != 0)
-            return fail(DC_ERR_INVALID_ARG, "dst_dtype must be set; dst2 must be absent; flags 0" + at);
+        if (!dtype_ok(m.dst_dtype) || m.dst2 || m.dst2_dtype != DC_NONE ||
+            (m.flags & ~DC_IMG_RGB_OUT))
+            return fail(DC_ERR_INVALID_ARG,
+                        "dst_dtype must be set; dst2 must be absent; flags 0 or DC_IMG_RGB_OUT" + at);
         if (m.dst) {
-            rc = validate_images(&m, 1);
+            rc = validate_images(&m, 1, true);
             if (rc != DC_OK)
                 return rc;
         }

@@ -54,7 +54,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(P.DcImage) == 72
     assert ctypes.sizeof(P.DcStats) == 24
     assert ctypes.sizeof(P.DcParams) == 8
-    assert ctypes.sizeof(P.DcTmParams) == 12
+    assert ctypes.sizeof(P.DcTmParams) == 16
 
 
 def _img(**kw):
@@ -75,7 +75,7 @@ def test_validate_accepts_good_images(lib):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(src=None), dict(dst=None), dict(width=0), dict(height=-1), dict(flags=1),
+    dict(src=None), dict(dst=None), dict(width=0), dict(height=-1), dict(flags=2),
     dict(src_dtype=3), dict(dst_dtype=-1), dict(dst2_dtype=7, dst2=0x30000000, dst2_pitch=40),
     dict(dst2=0x30000000), dict(dst2_dtype=P.DC_F32), dict(src_pitch=29), dict(dst_pitch=39),
     dict(src_dtype=P.DC_F16, src_pitch=59), dict(src_dtype=P.DC_F32, src=0x10000002, src_pitch=120),
@@ -96,6 +96,31 @@ def test_validate_rejects_bad_params(lib, beta_r, beta_k):
                                 (float("nan"), 2.0, 1e-3)])
 def test_validate_rejects_bad_tm(lib, tm):
     assert P.validate([_img()], tm=tm) == P.DC_ERR_INVALID_ARG
+
+
+TM = (1e-4, 2.0, 1e-3, 1.0)
+
+
+def test_colour_output_flag(lib):
+    """DC_IMG_RGB_OUT: tone map only; dst rows hold 3 channels."""
+    rgb = dict(flags=P.DC_IMG_RGB_OUT, dst_pitch=120)
+    assert P.validate([_img(**rgb)], tm=TM) == P.DC_OK
+    assert P.validate([_img(**rgb)]) == P.DC_ERR_UNSUPPORTED  # not a tone map
+    assert P.validate([_img(flags=P.DC_IMG_RGB_OUT, dst_pitch=119)], tm=TM) == \
+        P.DC_ERR_INVALID_ARG
+    assert P.validate([_img(flags=P.DC_IMG_RGB_OUT | 4, dst_pitch=120)], tm=TM) == \
+        P.DC_ERR_INVALID_ARG
+    # the 3-channel extent (3 * 120 + 120 = 480 bytes) counts for aliasing
+    assert P.validate([_img(**rgb), _img(src=0x40000000, dst=0x20000000 + 480)], tm=TM) == P.DC_OK
+    assert P.validate([_img(**rgb), _img(src=0x40000000, dst=0x20000000 + 476)], tm=TM) == \
+        P.DC_ERR_ALIAS
+
+
+@pytest.mark.parametrize("s,ok", [(0.0, True), (0.6, True), (2.0, True), (-0.01, False),
+                                  (2.01, False), (float("nan"), False), (float("inf"), False)])
+def test_saturation_range(lib, s, ok):
+    rc = P.validate([_img(flags=P.DC_IMG_RGB_OUT, dst_pitch=120)], tm=(1e-4, 2.0, 1e-3, s))
+    assert rc == (P.DC_OK if ok else P.DC_ERR_INVALID_ARG)
 
 
 def test_validate_rejects_negative_count_and_null_list(lib):
@@ -157,7 +182,7 @@ def test_binding_refuses_cpu_tensors():
 
 
 def test_server_calls_reject_bad_arguments(lib):
-    cfg = P.DcServerConfig(1 << 20, 8, 2, 0, P.DcParams(0.55, 0.8), P.DcTmParams(1e-4, 2.0, 1e-3))
+    cfg = P.DcServerConfig(1 << 20, 8, 2, 0, P.DcParams(0.55, 0.8), P.DcTmParams(1e-4, 2.0, 1e-3, 1.0))
     h = ctypes.c_void_p()
     assert lib.dc_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_create(None, ctypes.byref(cfg), None) == P.DC_ERR_INVALID_ARG

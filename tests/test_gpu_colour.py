@@ -1,0 +1,164 @@
+"""GPU parity of the colour output of the global tone map (images flagged
+DC_IMG_RGB_OUT: every channel min(1, T (C / Lhat)^s), grey T where Lhat == 0)
+against the FP64 oracle, through ``dc_tonemap_global``.
+
+Tolerances. FP32 outputs: |d| <= 1e-5, as for T. The colour value is
+T (C / L)^s with C / L formed first (a few ulp) and T carrying the error of the
+gray curve; where the output is below 1 its error is at most c |dz| with dz the
+error of the curve's argument, four times the bound that holds for T, and far
+inside 1e-5 for images whose sigma is not tiny. 8-bit outputs: at most one code
+apart; a value lands within 255 |d| of a rounding midpoint with probability
+about 2 * 255 * |d| <= 2e-3 for |d| <= 4e-6, which bounds the reported
+fraction of codes off by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2108_13656_amd as P
+import synth
+from gpuhelp import check_f16, check_f32, check_u8, need_gpu, report, to_dev
+
+pytestmark = pytest.mark.gpu
+TM = dict(eps=1e-4, contrast=2.0, sigma_floor=1e-3)
+U8_COLOUR_FRACTION = 2e-3
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def _image(kind, h, w, seed):
+    if kind == "u8":
+        return synth.gradient_rects() if (h, w) == (512, 512) else synth.sdr_pixels(
+            np.random.default_rng(seed), h, w)
+    if kind == "f16":
+        return synth.hdr_pixels(np.random.default_rng(seed), h, w)
+    return synth.random_image(seed, h, w, np.float32, scale=4.0)
+
+
+@pytest.mark.parametrize("s", [1.0, 0.6, 1.6])
+@pytest.mark.parametrize("kind,shape", [("u8", (512, 512)), ("u8", (37, 91)), ("f16", (256, 256)),
+                                        ("f16", (5, 4099)), ("f32", (70, 33)), ("u8", (1, 1))])
+def test_colour_vs_oracle(dev, kind, shape, s):
+    h, w = shape
+    img = _image(kind, h, w, h * w)
+    rgb_ref, t_ref, _, _ = oracle.tonemap_colour(img, saturation=s, **TM)
+    outs, _, _ = P.tonemap_global([to_dev(img, dev)], torch.float32, colour=True, saturation=s,
+                                  **TM)
+    got = outs[0].cpu().numpy()
+    assert got.shape == (h, w, 3)
+    check_f32(got, rgb_ref, "colour %s %dx%d s=%g" % (kind, h, w, s))
+
+
+@pytest.mark.parametrize("s", [0.0, 1.0, 0.6])
+@pytest.mark.parametrize("kind", ["u8", "f16", "f32"])
+def test_colour_encodings(dev, kind, s):
+    img = _image(kind, 96, 130, 5)
+    rgb_ref, _, _, _ = oracle.tonemap_colour(img, saturation=s, **TM)
+    x = to_dev(img, dev)
+    o8 = P.tonemap_global([x], torch.uint8, colour=True, saturation=s, **TM)[0][0]
+    o16 = P.tonemap_global([x], torch.float16, colour=True, saturation=s, **TM)[0][0]
+    name = "colour %s s=%g" % (kind, s)
+    check_u8(o8.cpu().numpy(), oracle.encode_u8(rgb_ref), name + " u8",
+             max_fraction=U8_COLOUR_FRACTION)
+    check_f16(o16.cpu().numpy(), oracle.encode_f16(rgb_ref), name + " f16")
+
+
+def test_zero_saturation_equals_gray_t(dev):
+    img = _image("f16", 64, 200, 6)
+    x = to_dev(img, dev)
+    t = P.tonemap_global([x], torch.float32, **TM)[0][0]
+    c = P.tonemap_global([x], torch.float32, colour=True, saturation=0.0, **TM)[0][0]
+    for ch in range(3):
+        assert torch.equal(c[..., ch], t)
+
+
+def test_unit_saturation_output_luminance_is_t(dev):
+    """s = 1: decolorizing the FP32 colour output gives T back wherever no
+    channel was clamped (degree-1 homogeneity of Eqs. (1)-(6))."""
+    img = _image("f16", 128, 256, 7)
+    x = to_dev(img, dev)
+    rgb = P.tonemap_global([x], torch.float32, colour=True, saturation=1.0, **TM)[0][0]
+    t = P.tonemap_global([x], torch.float32, **TM)[0][0]
+    lum = P.decolorize(rgb.contiguous())
+    free = rgb.amax(dim=2) < 1.0
+    err = (lum - t).abs()[free]
+    report("s=1 luminance of the colour output vs T: %d unclamped px, max |d| %.3e" %
+           (int(free.sum()), float(err.max())))
+    assert int(free.sum()) > 1000 and float(err.max()) <= 2e-6
+
+
+@pytest.mark.parametrize("kind", ["u8", "f16"])
+def test_pitched_views(dev, kind):
+    """Input and colour-output row pitches: 16-byte multiples (row walk) and odd
+    ones (per-pixel walk) give the values of packed buffers."""
+    img = _image(kind, 40, 150, 8)
+    x = to_dev(img, dev)
+    ref = P.tonemap_global([x], torch.float32, colour=True, saturation=0.7, **TM)[0][0]
+    big = torch.zeros((40, 176, 3), dtype=x.dtype, device=dev)  # rows of 528 or 1056 bytes
+    # (first input column, output row padding): column 16 starts 16-byte aligned
+    # and output rows of (150 + 2) * 12 bytes are a 16-byte multiple, so the first
+    # case takes the row walk and the others the per-pixel walk.
+    for c0, pad in ((16, 2), (16, 5), (3, 2)):
+        big.zero_()
+        big[:, c0:c0 + 150] = x
+        o = torch.full((40, 150 + pad, 3), -1.0, device=dev)
+        P.tonemap_global([big[:, c0:c0 + 150]], outs=[o[:, :150]], want_stats=False, colour=True,
+                         saturation=0.7, **TM)
+        assert torch.equal(o[:, :150], ref), (c0, pad)
+        assert bool((o[:, 150:] == -1.0).all()), (c0, pad)
+
+
+def test_mixed_batch_matches_single_calls(dev):
+    """Gray and colour outputs and all input types in one call: each image's
+    result equals that of a call on it alone."""
+    imgs = [_image("u8", 33, 47, 9), _image("f16", 64, 300, 10), _image("f32", 9, 1000, 11),
+            _image("u8", 128, 128, 12), _image("f16", 1, 5, 13)]
+    xs = [to_dev(a, dev) for a in imgs]
+    shapes = [(33, 47, 3), (64, 300), (9, 1000, 3), (128, 128), (1, 5, 3)]
+    dts = [torch.uint8, torch.float32, torch.float16, torch.float32, torch.float32]
+    outs = [torch.empty(sh, dtype=dt, device=dev) for sh, dt in zip(shapes, dts)]
+    lh = [torch.empty(a.shape[:2], dtype=torch.float32, device=dev) for a in imgs]
+    P.tonemap_global(xs, outs=outs, lhats=lh, saturation=0.8, **TM)
+    for i, x in enumerate(xs):
+        colour = len(shapes[i]) == 3
+        one, l1, _ = P.tonemap_global([x], dts[i], torch.float32, colour=colour, saturation=0.8,
+                                      **TM)
+        assert torch.equal(outs[i], one[0]), i
+        assert torch.equal(lh[i], l1[0]), i
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_plan_graph_replays(dev, pipeline):
+    imgs = [_image("f16", 256, 256, 14), _image("u8", 200, 300, 15)]
+    xs = [to_dev(a, dev) for a in imgs]
+    want = [P.tonemap_global([x], torch.uint8, colour=True, saturation=0.5, **TM)[0][0]
+            for x in xs]
+    outs = [torch.zeros_like(w) for w in want]
+    t0 = P.get_tuning()
+    try:
+        P.set_tuning(dict(t0, tonemap_pipeline=pipeline))
+        s = torch.cuda.Stream()
+        plan = P.Plan(P.PLAN_TONEMAP, xs, outs, graph=True, saturation=0.5, **TM)
+        for rep in range(3):
+            for o in outs:
+                o.zero_()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                plan.run(s)
+            s.synchronize()
+            for o, w in zip(outs, want):
+                assert torch.equal(o, w), rep
+        plan.close()
+    finally:
+        P.set_tuning(t0)
+
+
+def test_flag_rejected_outside_tone_map(dev):
+    x = to_dev(_image("u8", 8, 8, 16), dev)
+    with pytest.raises(P.DecolorError) as e:
+        P.decolorize(x, out=torch.empty((8, 8, 3), device=dev))
+    assert e.value.status == P.DC_ERR_UNSUPPORTED

@@ -6,7 +6,9 @@ times: autotuned launch shapes and a HIP-graph plan over resident buffers.
   oracle's table of all 2^24 colours, computed by the FP64 oracle).
 - 16 x 4096^2 binary16 tone map: every image's statistics against the FP64
   oracle over all its pixels, and T at 65536 sampled pixels per image against
-  the oracle's curve evaluated with the oracle's own statistics.
+  the oracle's curve evaluated with the oracle's own statistics; the same for
+  the re-coloured 8-bit RGB output (s = 1 and s = 0.6) at 16384 sampled pixels
+  per image.
 - uneven batch of 256 images (half 8-bit, half binary16, 64..4096 per side),
   one persistent launch: every pixel against the oracle.
 """
@@ -39,7 +41,8 @@ def lut():
 def _run_plan(kind, xs, outs, outs2=None, **kw):
     t0 = P.get_tuning()
     try:
-        chosen = P.autotune(kind, xs, outs, outs2, **{k: v for k, v in kw.items() if k in TM})
+        chosen = P.autotune(kind, xs, outs, outs2,
+                             **{k: v for k, v in kw.items() if k in TM or k == "saturation"})
         report("autotuned: %s" % chosen)
         for o in outs:
             o.zero_()
@@ -106,6 +109,33 @@ def test_hdr_tonemap_full(dev):
     report("hdr tone map 16x4096^2: max |d mu| %.2e, max |d sigma|/sigma %.2e, max |dT| %.2e "
            "(65536 sampled px per image)" % (worst_mu, worst_sig, worst_t))
     assert worst_mu <= 2e-5 and worst_sig <= 2e-5 and worst_t <= 1e-5
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("s", [1.0, 0.6])
+def test_hdr_colour_tonemap_full(dev, s):
+    imgs = synth.hdr_images(workers=WORKERS)
+    xs = [to_dev(a, dev) for a in imgs]
+    outs = [torch.empty(a.shape, dtype=torch.uint8, device=dev) for a in imgs]
+    _run_plan(P.PLAN_TONEMAP, xs, outs, saturation=s, **TM)
+    rng = np.random.default_rng(98)
+    off, total = 0, 0
+    for i, img in enumerate(imgs):
+        lhat = oracle.decolorize(img, nthreads=WORKERS).ravel()
+        ref = oracle.tonemap_stats(lhat, TM["eps"])
+        idx = rng.integers(0, lhat.size, 16384)
+        t_ref = oracle.tonemap_curve(lhat[idx], ref["mu"], ref["sigma"], **TM)
+        rgb = oracle.decode_f16(img.reshape(-1, 3)[idx])
+        want = np.array([[oracle.colour_channel(c, lh, t, s) for c in px]
+                         for px, lh, t in zip(rgb, lhat[idx], t_ref)])
+        got = outs[i].view(-1, 3)[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.int32)
+        d = np.abs(got - oracle.encode_u8(want).astype(np.int32))
+        assert d.max() <= 1, i
+        off += int(np.count_nonzero(d))
+        total += d.size
+    report("hdr colour tone map 16x4096^2 -> u8 RGB, s=%g: %d sampled codes, %d off by one "
+           "(fraction %.3e)" % (s, total, off, off / total))
+    assert off / total <= 2e-3
 
 
 @pytest.mark.timeout(900)

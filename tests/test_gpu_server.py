@@ -97,3 +97,25 @@ def test_replay_trace_completes(dev):
     for i, (x, o) in enumerate(zip(xs, outs)):
         alone, _, _ = P.tonemap_global([x], o.dtype)
         assert torch.equal(alone[0], o), i
+
+
+def test_colour_requests_in_mix(dev):
+    """Requests with re-coloured RGB outputs (DC_IMG_RGB_OUT) batched with gray
+    ones: each equals the direct colour tone map of its image alone."""
+    xs, outs = _mixed_requests(dev, 24, 5)
+    for i in range(1, len(xs), 2):
+        h, w = xs[i].shape[:2]
+        outs[i] = torch.zeros((h, w, 3), dtype=torch.uint8 if i % 4 == 1 else torch.float16,
+                              device=dev)
+    srv = P.Server(budget_bytes=64 << 20, max_batch=16, max_inflight=3, saturation=0.7)
+    srv.submit([P.request_for(i, x, o) for i, (x, o) in enumerate(zip(xs, outs))])
+    done = []
+    while len(done) < len(xs):
+        srv.step()
+        done += srv.poll()
+    srv.close()
+    torch.cuda.synchronize()
+    assert all(c.status == P.DC_OK for c in done)
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        alone, _, _ = P.tonemap_global([x], o.dtype, colour=o.dim() == 3, saturation=0.7)
+        assert torch.equal(alone[0], o), i
