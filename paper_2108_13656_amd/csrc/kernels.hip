@@ -835,47 +835,57 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
 // Colour output of the tone map for one pixel: every channel C becomes
 // T (C / L)^s, clamped to at most 1, with C and L in the input's units (their
 // ratio is unit-free); E is the curve's exponential, T = 1 / (1 + E). A pixel
-// with no colour to carry (all channels 0, or L at most 1e-6 S, which only
-// the degenerate weights 0 produce) becomes grey T. The ratio is formed
-// first, so its logarithm stays small for ordinary colours and the power is
-// accurate: MODE kColourRatio (s = 1) is C (T / L); kColourPow is
-// exp2(min(s log2(C / L) + log2 T, 0)) with log2 T = -log2(1 + E), which
-// stays finite where T underflows; kColourGrey (s = 0) is T everywhere.
-template <int SRC, int MODE>
+// with no colour to carry (L at most 1e-6 S: black, or the degenerate weights
+// 0) becomes grey T; the 8-bit form's L of a black pixel is about 1e-7 (its
+// tiny addends), hence the extra 1e-6 there. The ratio is formed first, so its
+// logarithm stays small for ordinary colours and the power is accurate:
+//   kColourGrey  (s = 0): T everywhere;
+//   kColourRatio (s = 1): C k with k = 1 / ((1 + E) L), one reciprocal for T
+//                         and 1/L together (grey T = k L);
+//   kColourPow   (other s): exp2(min(s log2(C / L) + log2 T, 0)) with
+//                         log2 T = -log2(1 + E), finite where T underflows.
+// U8: the values are wanted as 8-bit codes, so they come out times 255 (for the
+// saturating 8-bit conversion, which also does the clamp at 255).
+template <int SRC, int MODE, bool U8>
 __device__ __forceinline__ void colour_px(float R, float G, float B, float l, float E, float s,
                                           float *o)
 {
+    constexpr float kOut = U8 ? 255.0f : 1.0f;
     if constexpr (SRC != 0) {
         R = fmaxf(R, 0.0f);
         G = fmaxf(G, 0.0f);
         B = fmaxf(B, 0.0f);
     }
-    const float T = hw_rcp(1.0f + E);
     if constexpr (MODE == kColourGrey) {
-        o[0] = o[1] = o[2] = T;
+        o[0] = o[1] = o[2] = hw_rcp(1.0f + E) * kOut;
         return;
     }
     const float S = (R + G) + B;
-    const bool grey = !(S > 0.0f) || !(l > S * 1e-6f);
+    const bool grey = !(l > fmaf(S, 1e-6f, SRC == 0 ? 1e-6f : 0.0f));
     const float C[3] = {R, G, B};
     if constexpr (MODE == kColourRatio) {
-        const float k = T * hw_rcp(l);
+        const float lc = fmaxf(l, 1e-30f);
+        const float k = hw_rcp((1.0f + E) * lc);
+        const float tg = k * lc * kOut;
+        const float ko = k * kOut;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            o[c] = grey ? T : fminf(C[c] * k, 1.0f);
+            o[c] = grey ? tg : (U8 ? C[c] * ko : fminf(C[c] * ko, 1.0f));
     } else {
         const float lT = -hw_log2(1.0f + E);
         const float il = hw_rcp(l);
+        const float tg = hw_exp2(lT) * kOut;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            o[c] = grey ? T : hw_exp2(fminf(fmaf(s, hw_log2(C[c] * il), lT), 0.0f));
+            o[c] = grey ? tg : hw_exp2(fminf(fmaf(s, hw_log2(C[c] * il), lT), 0.0f)) * kOut;
     }
 }
 
 // Stores the 3 * PPU channel values of one unit (PPU pixels) at pixel lp of
 // an interleaved RGB row whose pixel 0 is at base (16-byte aligned on the
 // vector walks, so every unit is aligned to its own size's largest power of
-// two up to 16). 8-bit values are v * 255 by v_cvt_pk_u8_f32.
+// two up to 16). 8-bit values arrive times 255 and are converted by the
+// saturating v_cvt_pk_u8_f32.
 template <int PPU>
 __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_t lp,
                                                const float (&o)[3 * PPU])
@@ -889,7 +899,7 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
                 w[j] = 0u;
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    w[j] = u8_of<true>(o[4 * j + i], 255.0f, i, w[j]);
+                    w[j] = u8_of<false>(o[4 * j + i], 1.0f, i, w[j]);
             }
             DC_GLOBAL unsigned *q = gpw<unsigned>(p);
             q[0] = w[0];
@@ -899,13 +909,13 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
             DC_GLOBAL unsigned short *q = gpw<unsigned short>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                q[j] = (unsigned short)u8_of<true>(o[2 * j + 1], 255.0f, 1,
-                                                   u8_of<true>(o[2 * j], 255.0f, 0, 0u));
+                q[j] = (unsigned short)u8_of<false>(o[2 * j + 1], 1.0f, 1,
+                                                    u8_of<false>(o[2 * j], 1.0f, 0, 0u));
         } else {
             DC_GLOBAL uint8_t *q = gpw<uint8_t>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                q[j] = (uint8_t)u8_of<true>(o[j], 255.0f, 0, 0u);
+                q[j] = (uint8_t)u8_of<false>(o[j], 1.0f, 0, 0u);
         }
     } else if (dtype == 1) {
         uint8_t *p = base + 6 * lp;
@@ -951,8 +961,9 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
 }
 
 // Curve pass with colour output over one statistics tile: the same units,
-// tiles and T as tm_pass2_tile, and 3 output channels per pixel.
-template <int SRC, int MODE>
+// tiles and curve as tm_pass2_tile, and 3 output channels per pixel. U8 =
+// the image's dst is 8-bit (a uniform choice per image).
+template <int SRC, int MODE, bool U8>
 __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                                Curve cv)
 {
@@ -960,7 +971,7 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
     constexpr int U = kStatsPxPerThread / PPU;
     constexpr int ES = elem_size(SRC);
     const TileRef t = tile_ref<3>(im, tile, kStatsChunkPx);
-    const Enc e{1.0f, 255.0f};
+    const Enc e{1.0f, 1.0f};
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= kStatsChunkPx) {
         unsigned w[U][3];
@@ -976,9 +987,9 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
                             B = chan<SRC>(w[u], 3 * j + 2);
                 const float l = lum<SRC>(R, G, B, im.k);
                 const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
-                colour_px<SRC, MODE>(R, G, B, l, E, tm.saturation, &o[3 * j]);
+                colour_px<SRC, MODE, U8>(R, G, B, l, E, tm.saturation, &o[3 * j]);
             }
-            store_rgb_unit<PPU>(t.dst, im.dst_dtype, slot_lp<PPU>(true, u, 0), o);
+            store_rgb_unit<PPU>(t.dst, U8 ? 0 : im.dst_dtype, slot_lp<PPU>(true, u, 0), o);
         }
         return;
     }
@@ -992,10 +1003,10 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
             const float l = lum<SRC>(R, G, B, im.k);
             const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
             float o[3];
-            colour_px<SRC, MODE>(R, G, B, l, E, tm.saturation, o);
+            colour_px<SRC, MODE, U8>(R, G, B, l, E, tm.saturation, o);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                store_px<false, true>(t.dst, im.dst_dtype, 3 * p + c, o[c], e);
+                store_px<false, false>(t.dst, U8 ? 0 : im.dst_dtype, 3 * p + c, o[c], e);
         }
     }
 }
@@ -1008,7 +1019,10 @@ __global__ __launch_bounds__(kBlock) void k_tm_colour(const DevImage *__restrict
 {
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
-        tm_colour_tile<SRC, MODE>(im, tile - im.tile_begin, tm, curves[i]);
+        if (im.dst_dtype == 0)
+            tm_colour_tile<SRC, MODE, true>(im, tile - im.tile_begin, tm, curves[i]);
+        else
+            tm_colour_tile<SRC, MODE, false>(im, tile - im.tile_begin, tm, curves[i]);
     });
 }
 

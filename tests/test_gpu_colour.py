@@ -94,10 +94,12 @@ def test_unit_saturation_output_luminance_is_t(dev):
 @pytest.mark.parametrize("kind", ["u8", "f16"])
 def test_pitched_views(dev, kind):
     """Input and colour-output row pitches: 16-byte multiples (row walk) and odd
-    ones (per-pixel walk) give the values of packed buffers."""
+    ones (per-pixel walk) match the oracle and leave the row padding alone. (The
+    walks split an image into different statistics chunks, so their results
+    agree within the tolerance, not bit for bit.)"""
     img = _image(kind, 40, 150, 8)
     x = to_dev(img, dev)
-    ref = P.tonemap_global([x], torch.float32, colour=True, saturation=0.7, **TM)[0][0]
+    ref = oracle.tonemap_colour(img, saturation=0.7, **TM)[0]
     big = torch.zeros((40, 176, 3), dtype=x.dtype, device=dev)  # rows of 528 or 1056 bytes
     # (first input column, output row padding): column 16 starts 16-byte aligned
     # and output rows of (150 + 2) * 12 bytes are a 16-byte multiple, so the first
@@ -108,7 +110,7 @@ def test_pitched_views(dev, kind):
         o = torch.full((40, 150 + pad, 3), -1.0, device=dev)
         P.tonemap_global([big[:, c0:c0 + 150]], outs=[o[:, :150]], want_stats=False, colour=True,
                          saturation=0.7, **TM)
-        assert torch.equal(o[:, :150], ref), (c0, pad)
+        check_f32(o[:, :150].cpu().numpy(), ref, "colour %s view c0=%d pad=%d" % (kind, c0, pad))
         assert bool((o[:, 150:] == -1.0).all()), (c0, pad)
 
 
