@@ -241,7 +241,9 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *tuning);
  * 0/1/2/4/8/16 for kind DC_PLAN_DECOLORIZE; grids per CU for each tone-map
  * pass, then the two schedules, for DC_PLAN_TONEMAP) on the given images with
  * HIP events on `stream` (fastest of 10 runs after a warm-up), keeps the best
- * in the context (the fields of the given batch's class only) and
+ * in the context (the fields of the given batch's class only; the shapes in
+ * place are measured first and a candidate replaces them only when it is more
+ * than 2 % faster, so timing noise does not flip between equal shapes) and
  * writes it to *chosen (if not NULL). The candidate runs write the images'
  * outputs. Synchronises `stream`. */
 int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,

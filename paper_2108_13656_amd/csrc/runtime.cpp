@@ -256,7 +256,7 @@ struct Tune {
     int decolor_gpc = 0;
     int mixed_gpc = 4;
     int pass1_gpc = 16;
-    int pass2_gpc = 16;
+    int pass2_gpc = 0;
     int tm_pipeline = 0; // 1 = per-image tone map on two streams
 };
 
@@ -1119,6 +1119,10 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
     const hipStream_t st = (hipStream_t)stream;
     const int gpcs[] = {0, 1, 2, 4, 8, 16};
     const int reps = 10;
+    // A candidate replaces the current choice only when it is faster by more
+    // than this factor, so run-to-run noise does not flip between shapes whose
+    // times are within it; the current shapes are measured first.
+    const float margin = 0.98f;
     Tune best = ctx->tune;
     std::vector<float> ms;
     auto run = [&](const Tune &t, std::vector<float> *out) -> int {
@@ -1136,7 +1140,10 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
         bool mixed = false;
         for (int32_t i = 1; i < n; ++i)
             mixed |= imgs[i].src_dtype != imgs[0].src_dtype;
-        float best_ms = 1e30f;
+        rc = run(ctx->tune, &ms);
+        if (rc != DC_OK)
+            return rc;
+        float best_ms = ms[0];
         for (int g : {1, 2, 4}) {
             for (int c : gpcs) {
                 Tune t = ctx->tune;
@@ -1150,14 +1157,19 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 rc = run(t, &ms);
                 if (rc != DC_OK)
                     return rc;
-                if (ms[0] < best_ms) {
+                if (ms[0] < margin * best_ms) {
                     best_ms = ms[0];
                     best = t;
                 }
             }
         }
     } else {
-        float b1 = 1e30f, b2 = 1e30f;
+        Tune cur = ctx->tune;
+        cur.tm_pipeline = 0;
+        rc = run(cur, &ms);
+        if (rc != DC_OK)
+            return rc;
+        float b1 = ms[0], b2 = ms[2];
         for (int c : gpcs) {
             Tune t = ctx->tune;
             t.tm_pipeline = 0;
@@ -1166,11 +1178,11 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
             rc = run(t, &ms);
             if (rc != DC_OK)
                 return rc;
-            if (ms[0] < b1) {
+            if (ms[0] < margin * b1) {
                 b1 = ms[0];
                 best.pass1_gpc = c;
             }
-            if (ms[2] < b2) {
+            if (ms[2] < margin * b2) {
                 b2 = ms[2];
                 best.pass2_gpc = c;
             }
@@ -1187,7 +1199,7 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
             for (float m : ms)
                 whole[pl] += m;
         }
-        best.tm_pipeline = whole[1] < whole[0] ? 1 : 0;
+        best.tm_pipeline = whole[1] < margin * whole[0] ? 1 : 0;
     }
     ctx->tune = best;
     if (chosen)
