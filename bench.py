@@ -34,13 +34,14 @@ def profiled_traffic():
     import glob
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2108_13656_amd", "csrc", "kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     found = {}
     for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         text = open(fn).read()
-        m = re.search(r"source sha256 \(paper_2108_13656_amd/csrc/kernels.hip\): ([0-9a-f]+)", text)
-        if not m or m.group(1) != digest:
+        m = re.search(r"source sha256 \((\S+)\): ([0-9a-f]+)", text)
+        src = os.path.join(ROOT, m.group(1)) if m else None
+        if not src or not os.path.exists(src):
+            continue
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(2):
             continue
         for key, val in re.findall(r"^traffic_bytes (\S+) (\d+)$", text, re.M):
             found[key] = int(val)
@@ -63,7 +64,7 @@ def parse():
     ap.add_argument("--skip-video", action="store_true")
     ap.add_argument("--skip-uneven", action="store_true")
     ap.add_argument("--no-per-image", action="store_true",
-                    help="skip the per-image-launch comparison (profiler runs)")
+                    help="skip the per-image-launch and gray-channel comparisons (profiler runs)")
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--requests", type=int, default=10000, help="serving trace length")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serving memory budget")
@@ -398,19 +399,22 @@ def main():
             vplan_ev.close()
             for sp in singles:
                 sp.close()
-            # Same-GPU comparison with the gray channels the paper compares its
-            # L against (u8 in, f32 out, kernel time from the library's events).
-            comp = {}
-            cplan = P.Plan(P.PLAN_DECOLORIZE, frames, o32)
-            comp["decolor_L"] = vpx / (kernel_times(lambda: cplan.run(stream), 10, P, dev)[0]
-                                       * 1e-3) / 1e9
-            cplan.close()
-            for ch in ("y601", "hsv_v", "cielab_l"):
-                t = kernel_times(lambda: P.channel_batch(frames, ch, outs=o32, stream=stream), 10,
-                                 P, dev)[0]
-                comp[ch] = vpx / (t * 1e-3) / 1e9
-            comp = {k: round(v, 1) for k, v in comp.items()}
-            log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
+            comp = None
+            if not args.no_per_image:
+                # Same-GPU comparison with the gray channels the paper compares
+                # its L against (u8 in, f32 out, kernel time from the library's
+                # events).
+                comp = {}
+                cplan = P.Plan(P.PLAN_DECOLORIZE, frames, o32)
+                comp["decolor_L"] = vpx / (kernel_times(lambda: cplan.run(stream), 10, P, dev)[0]
+                                           * 1e-3) / 1e9
+                cplan.close()
+                for ch in ("y601", "hsv_v", "cielab_l"):
+                    t = kernel_times(lambda: P.channel_batch(frames, ch, outs=o32, stream=stream),
+                                     10, P, dev)[0]
+                    comp[ch] = vpx / (t * 1e-3) / 1e9
+                comp = {k: round(v, 1) for k, v in comp.items()}
+                log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
         vbytes = vpx * 8
         vach = vbytes / (vk * 1e-3) / 1e9
         video = {"workload": "video_decolorize", "frames": "32x1920x1080 + 32x3840x2160",
