@@ -399,7 +399,7 @@ def main():
             vplan_ev.close()
             for sp in singles:
                 sp.close()
-            comp = None
+            comp = sweep = None
             if not args.no_per_image:
                 # Same-GPU comparison with the gray channels the paper compares
                 # its L against (u8 in, f32 out, kernel time from the library's
@@ -415,6 +415,23 @@ def main():
                     comp[ch] = vpx / (t * 1e-3) / 1e9
                 comp = {k: round(v, 1) for k, v in comp.items()}
                 log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
+                # Weight sweep (Fig. 4's explorer): one 3840x2160 frame under 20
+                # (beta_R, beta_k) pairs, 20 FP32 outputs from one launch.
+                betas = [(br, bk) for br in (0.0, 0.3, 0.55, 0.8, 1.0)
+                         for bk in (0.2, 0.5, 0.8, 1.0)]
+                f4k = frames[-1]
+                sw = torch.empty((len(betas),) + tuple(f4k.shape[:2]), dtype=torch.float32,
+                                 device=dev)
+                swt = kernel_times(lambda: P.beta_sweep(f4k, betas, out=sw, stream=stream), 10,
+                                   P, dev)[0]
+                spx = len(betas) * f4k.shape[0] * f4k.shape[1]
+                sweep = {"workload": "beta_sweep_3840x2160_u8_x20", "pairs": len(betas),
+                         "kernel_ms": round(swt, 4),
+                         "output_gpx_s": round(spx / (swt * 1e-3) / 1e9, 1),
+                         "output_write_gbs": round(spx * 4 / (swt * 1e-3) / 1e9, 1)}
+                log("beta sweep: %d pairs on one 4K frame in %.3f ms (%.0f Gpx/s of outputs)" %
+                    (len(betas), swt, sweep["output_gpx_s"]))
+                del sw
         vbytes = vpx * 8
         vach = vbytes / (vk * 1e-3) / 1e9
         video = {"workload": "video_decolorize", "frames": "32x1920x1080 + 32x3840x2160",
@@ -425,6 +442,7 @@ def main():
                  "tuning": {"groups_u8": vtune["groups"][0],
                             "grid_per_cu": vtune["decolor_grid_per_cu"]},
                  "gray_channels_u8_to_f32_gpx": comp,
+                 "beta_sweep": sweep,
                  "roofline": {"bound": "hbm", "kernel": "decolor_table", "achieved": round(vach, 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(vach / HBM_PEAK_GBS, 4),

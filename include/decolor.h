@@ -162,6 +162,16 @@ int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, voi
 int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                         void *stream);
 
+/* As dc_decolorize_batch, but image i uses its own weights betas[i] (a HOST
+ * array of n dc_params; NULL means the defaults for all). This is the
+ * weight-sweep explorer of Fig. 4, which plots how beta_R and beta_k bias L
+ * along colour ramps: a sweep of one image over many (beta_R, beta_k) pairs is
+ * n descriptors sharing one src with n outputs, all in one persistent launch.
+ * Every weight must be finite and in [0, 1]. Results are bit-identical to
+ * dc_decolorize of each image with its weights. */
+int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
+                              const dc_params *betas, void *stream);
+
 /* Global tone map (Sec. III-B.1 reading above) of n images: per image, one
  * statistics pass fused with the decolorization (Eqs. (1)-(6)), a fixed-order
  * combine of per-chunk partials, and a curve pass that recomputes L and writes

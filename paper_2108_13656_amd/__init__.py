@@ -156,6 +156,7 @@ def lib():
     L.dc_server_clock.restype = ctypes.c_double
     L.dc_server_replay.argtypes = [vp, req_p, ctypes.POINTER(ctypes.c_double), i32, comp_p]
     L.dc_channel_batch.argtypes = [vp, img_p, i32, i32, vp]
+    L.dc_decolorize_batch_betas.argtypes = [vp, img_p, i32, par_p, vp]
     L.dc_set_profiling.argtypes = [vp, ctypes.c_int]
     L.dc_last_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     for name in ("dc_create", "dc_destroy", "dc_validate", "dc_decolorize", "dc_decolorize_batch",
@@ -163,7 +164,7 @@ def lib():
                  "dc_plan_create", "dc_plan_run", "dc_plan_destroy", "dc_get_tuning",
                  "dc_set_tuning", "dc_autotune", "dc_server_create", "dc_server_destroy",
                  "dc_server_submit", "dc_server_step", "dc_server_poll", "dc_server_replay",
-                 "dc_channel_batch"):
+                 "dc_channel_batch", "dc_decolorize_batch_betas"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -337,6 +338,35 @@ def decolorize_batch(xs, out_dtype=torch.float32, out2_dtype=None, beta_r=BETA_R
     _check(lib().dc_decolorize_batch(context(dev).handle, arr, len(xs), ctypes.byref(p),
                                      _stream_ptr(stream, dev)))
     return outs if outs2 is None else list(zip(outs, outs2))
+
+
+def decolorize_betas(xs, betas, out_dtype=torch.float32, outs=None, stream=None):
+    """Decolorization of a list of images, image i with its own weights
+    betas[i] = (beta_r, beta_k), in one persistent launch."""
+    xs = list(xs)
+    if len(betas) != len(xs):
+        raise ValueError("one (beta_r, beta_k) pair per image")
+    if not xs:
+        return []
+    dev = xs[0].device
+    if outs is None:
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+    arr = _image_array(xs, outs, None)
+    pa = (DcParams * len(xs))(*[DcParams(float(a), float(b)) for a, b in betas])
+    _check(lib().dc_decolorize_batch_betas(context(dev).handle, arr, len(xs), pa,
+                                           _stream_ptr(stream, dev)))
+    return outs
+
+
+def beta_sweep(x, betas, out_dtype=torch.float32, out=None, stream=None):
+    """L of one HxWx3 image for every (beta_r, beta_k) pair (the weight sweep of
+    Fig. 4): an (n, H, W) tensor, one launch reading the shared input."""
+    _check_rgb(x)
+    h, w = x.shape[0], x.shape[1]
+    if out is None:
+        out = torch.empty((len(betas), h, w), dtype=out_dtype, device=x.device)
+    decolorize_betas([x] * len(betas), betas, outs=list(out.unbind(0)), stream=stream)
+    return out
 
 
 CHANNELS = {"y601": 1, "hsv_v": 2, "cielab_l": 3}

@@ -346,8 +346,10 @@ struct HostTable {
 // 48-byte group per thread, sorted by input type).
 enum TableKind { kTabDecolor = 0, kTabTonemap = 1, kTabChannel = 2 };
 
+// per_image, when not NULL, holds one dc_params per image (in the caller's
+// order) and overrides params.
 void build_table(const dc_image *imgs, int32_t n, const dc_params *params, TableKind kind,
-                 const Tune &tune, HostTable &h)
+                 const Tune &tune, HostTable &h, const dc_params *per_image = nullptr)
 {
     const bool tonemap = kind == kTabTonemap;
     h.d.resize((size_t)n);
@@ -376,7 +378,7 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
             tonemap ? dc::kStatsChunkPx
                     : (int64_t)dc::kBlock * (kind == kTabChannel ? 1 : h.groups) *
                           dc::group_px(m.src_dtype);
-        h.d[i] = describe(m, order[i], tile_px, params);
+        h.d[i] = describe(m, order[i], tile_px, per_image ? &per_image[order[i]] : params);
         const int rgb = h.d[i].rgb_out;
         if (h.runs.empty() || h.runs.back().src != m.src_dtype || h.runs.back().rgb != rgb)
             h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype, rgb});
@@ -959,6 +961,34 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
     const hipStream_t st = (hipStream_t)stream;
     HostTable h;
     build_table(imgs, n, params, kTabDecolor, ctx->tune, h);
+    dc_ctx::Slot *slot = nullptr;
+    DevBufs b;
+    rc = stage(ctx, h, st, &slot, &b);
+    if (rc != DC_OK)
+        return rc;
+    rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
+    if (rc != DC_OK)
+        return rc;
+    return release_slot(slot, st);
+}
+
+int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
+                              const dc_params *betas, void *stream)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    if (betas)
+        for (int32_t i = 0; i < n && rc == DC_OK; ++i)
+            rc = validate_params(&betas[i]);
+    if (rc == DC_OK)
+        rc = dc_validate(imgs, n, nullptr, nullptr);
+    if (rc != DC_OK || n == 0)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    HostTable h;
+    build_table(imgs, n, nullptr, kTabDecolor, ctx->tune, h, betas);
     dc_ctx::Slot *slot = nullptr;
     DevBufs b;
     rc = stage(ctx, h, st, &slot, &b);

@@ -200,3 +200,16 @@ def random_image(seed, h, w, dtype, scale=1.0):
     if np.dtype(dtype) == np.uint8:
         return rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
     return (rng.random((h, w, 3)) * scale).astype(dtype)
+
+
+def colour_ramps(n=256):
+    """The three colour ramps of the weight-sweep figure (Fig. 4), as 1 x n
+    8-bit images: pure green to pure red, pure blue to pure red, pure blue to
+    pure green, each a straight line in code values (round half up)."""
+    t = np.arange(n, dtype=np.float64) / max(1, n - 1)
+    g, r, b = np.eye(3)[[1, 0, 2]] * 255.0
+    out = {}
+    for name, a, z in (("g_to_r", g, r), ("b_to_r", b, r), ("b_to_g", b, g)):
+        px = np.floor((1.0 - t)[:, None] * a + t[:, None] * z + 0.5)
+        out[name] = px.astype(np.uint8).reshape(1, n, 3)
+    return out

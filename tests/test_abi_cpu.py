@@ -172,6 +172,8 @@ def test_compute_calls_reject_null_context(lib):
         P.DC_ERR_INVALID_ARG
     assert lib.dc_tonemap_global(None, ctypes.byref(d), 1, ctypes.byref(p), None, None, None) == \
         P.DC_ERR_INVALID_ARG
+    assert lib.dc_decolorize_batch_betas(None, ctypes.byref(d), 1, ctypes.byref(p), None) == \
+        P.DC_ERR_INVALID_ARG
 
 
 def test_binding_refuses_cpu_tensors():
