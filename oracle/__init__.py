@@ -6,7 +6,8 @@ library and its Python binding) never does, and the two share no code.
 
 Every function here marshals arguments and calls the C oracle, whose header
 comment cites the passages of arXiv 2108.13656 it follows (Sec. II-B, Eqs.
-(1)-(6); Sec. III-B.1 for the tone curve and its colour output).
+(1)-(6); Sec. III-B.1 for the tone curve and its colour output; Sec. III-B.2
+for the local tone map).
 """
 import ctypes
 import os
@@ -70,6 +71,8 @@ def _load():
     lib.ref_tonemap_curve_array.argtypes = [vp, i64, d, d, d, d, d, vp]
     lib.ref_tonemap_image.restype = i32
     lib.ref_tonemap_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, vp, vp, vp, i32]
+    lib.ref_tonemap_local_image.restype = i32
+    lib.ref_tonemap_local_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, d, vp, vp, i32]
     lib.ref_colour_channel.restype = d
     lib.ref_colour_channel.argtypes = [d, d, d, d]
     lib.ref_tonemap_colour_image.restype = i32
@@ -223,3 +226,21 @@ def tonemap_colour(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_f
         raise ValueError("oracle rejected the image or the saturation")
     stats = {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": w * h}
     return rgb, t, lhat, stats
+
+
+LTM_TILE, LTM_BINS = 64, 64
+
+
+def tonemap_local(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_floor=1e-3,
+                  strength=0.5, nthreads=1):
+    """Local tone map of one image (smoothed local histogram equalisation on a
+    64-pixel tile grid, blended with the global curve): (T float64 HxW, stats)."""
+    img, code, w, h, pitch = _image_args(img)
+    t = np.empty((h, w), np.float64)
+    st = np.zeros(4, np.float64)
+    rc = _load().ref_tonemap_local_image(_ptr(img), code, w, h, pitch, beta_r, beta_k, eps,
+                                         contrast, sigma_floor, strength, _ptr(t), _ptr(st),
+                                         int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the image or the strength")
+    return t, {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": w * h}

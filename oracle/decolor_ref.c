@@ -490,3 +490,152 @@ int ref_tonemap_colour_image(const void *src, int dtype, int W, int H, int64_t p
         free(lhat);
     return rc;
 }
+
+/* ------------------------------------------------------ local tone mapping */
+
+/* Local tone map on the luminance, Sec. III-B.2. The paper builds it on
+ * smoothed local histogram equalisation (tone curves from local cumulative
+ * histograms, as in its cited O(1) design) and gives no equations; the
+ * reading used here, step by step:
+ *   1. Lhat, the global statistics and the global curve T_g of every pixel,
+ *      exactly as ref_tonemap_image.
+ *   2. The pixel's position on a fixed log2 scale of 64 bins, 2 per stop,
+ *      starting at eps: u = clamp(2 log2((Lhat + eps) / eps) - 0.5, 0, 63),
+ *      so bin centres are the integers 0..63.
+ *   3. Histograms on a grid of 64 x 64-pixel tiles (edge tiles may be
+ *      smaller): each pixel puts mass 1 - f on bin k and f on bin k + 1,
+ *      k = min(floor(u), 62), f = u - k (linear soft binning).
+ *   4. Spatial smoothing: H_t = sum over the 3 x 3 neighbouring tiles t' of
+ *      w(dx) w(dy) h_t', w(0) = 2, w(+-1) = 1, tiles outside the grid absent.
+ *   5. The tile's tone curve is the cumulative distribution of its smoothed
+ *      histogram with every bin's mass spread by the unit triangle kernel:
+ *      F_t(u) = sum_b H_t(b) R(u - b) / sum_b H_t(b), R the integral of the
+ *      triangle max(0, 1 - |x|).
+ *   6. The pixel's local value interpolates the curves of the four tile
+ *      centres around it bilinearly (tile t's centre at 64 t + 32 pixels,
+ *      clamped at the grid's edges): T_l.
+ *   7. Output T = (1 - strength) T_g + strength T_l.
+ * Returns 0, or -1 on a bad argument or allocation failure. */
+
+#define REF_LTM_TILE 64
+#define REF_LTM_BINS 64
+
+static double ltm_u(double lhat, double eps)
+{
+    double u = 2.0 * log2((lhat + eps) / eps) - 0.5;
+    if (!(u > 0.0))
+        return 0.0;
+    return u < REF_LTM_BINS - 1 ? u : (double)(REF_LTM_BINS - 1);
+}
+
+/* Integral of the unit triangle kernel, from -inf to x. */
+static double ltm_tri_cdf(double x)
+{
+    if (x <= -1.0)
+        return 0.0;
+    if (x <= 0.0)
+        return 0.5 * (1.0 + x) * (1.0 + x);
+    if (x <= 1.0)
+        return 1.0 - 0.5 * (1.0 - x) * (1.0 - x);
+    return 1.0;
+}
+
+int ref_tonemap_local_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes,
+                            double beta_r, double beta_k, double eps, double contrast,
+                            double sigma_floor, double strength, double *t_out, double *stats,
+                            int nthreads)
+{
+    if (!t_out || !stats || W < 1 || H < 1 || !(strength >= 0.0 && strength <= 1.0))
+        return -1;
+    const int64_t n = (int64_t)W * H;
+    const int nx = (W + REF_LTM_TILE - 1) / REF_LTM_TILE, ny = (H + REF_LTM_TILE - 1) / REF_LTM_TILE;
+    double *lhat = (double *)malloc((size_t)n * sizeof(double));
+    double *tg = (double *)malloc((size_t)n * sizeof(double));
+    double *hist = (double *)calloc((size_t)nx * ny * REF_LTM_BINS, sizeof(double));
+    double *smooth = (double *)calloc((size_t)nx * ny * REF_LTM_BINS, sizeof(double));
+    int rc = -1;
+    if (!lhat || !tg || !hist || !smooth)
+        goto done;
+    /* step 1 */
+    rc = ref_tonemap_image(src, dtype, W, H, pitch_bytes, beta_r, beta_k, eps, contrast,
+                           sigma_floor, lhat, tg, stats, nthreads);
+    if (rc != 0)
+        goto done;
+    /* steps 2 and 3 */
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double u = ltm_u(lhat[(int64_t)y * W + x], eps);
+            int k = (int)floor(u);
+            if (k > REF_LTM_BINS - 2)
+                k = REF_LTM_BINS - 2;
+            double f = u - k;
+            double *h = hist + ((int64_t)(y / REF_LTM_TILE) * nx + x / REF_LTM_TILE) * REF_LTM_BINS;
+            h[k] += 1.0 - f;
+            h[k + 1] += f;
+        }
+    /* step 4 */
+    for (int ty = 0; ty < ny; ++ty)
+        for (int tx = 0; tx < nx; ++tx) {
+            double *s = smooth + ((int64_t)ty * nx + tx) * REF_LTM_BINS;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int sx = tx + dx, sy = ty + dy;
+                    if (sx < 0 || sx >= nx || sy < 0 || sy >= ny)
+                        continue;
+                    double w = (dx == 0 ? 2.0 : 1.0) * (dy == 0 ? 2.0 : 1.0);
+                    const double *h = hist + ((int64_t)sy * nx + sx) * REF_LTM_BINS;
+                    for (int b = 0; b < REF_LTM_BINS; ++b)
+                        s[b] += w * h[b];
+                }
+        }
+    /* steps 5 to 7 */
+    for (int y = 0; y < H; ++y) {
+        double gy = (y + 0.5) / REF_LTM_TILE - 0.5;
+        int ty0 = (int)floor(gy);
+        double fy = gy - ty0;
+        if (ty0 < 0) {
+            ty0 = 0;
+            fy = 0.0;
+        }
+        if (ty0 >= ny - 1) {
+            ty0 = ny - 1;
+            fy = 0.0;
+        }
+        int ty1 = ty0 + 1 < ny ? ty0 + 1 : ny - 1;
+        for (int x = 0; x < W; ++x) {
+            double gx = (x + 0.5) / REF_LTM_TILE - 0.5;
+            int tx0 = (int)floor(gx);
+            double fx = gx - tx0;
+            if (tx0 < 0) {
+                tx0 = 0;
+                fx = 0.0;
+            }
+            if (tx0 >= nx - 1) {
+                tx0 = nx - 1;
+                fx = 0.0;
+            }
+            int tx1 = tx0 + 1 < nx ? tx0 + 1 : nx - 1;
+            int64_t i = (int64_t)y * W + x;
+            double u = ltm_u(lhat[i], eps);
+            const int tyy[4] = {ty0, ty0, ty1, ty1}, txx[4] = {tx0, tx1, tx0, tx1};
+            const double wt[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+            double tl = 0.0;
+            for (int c = 0; c < 4; ++c) {
+                const double *s = smooth + ((int64_t)tyy[c] * nx + txx[c]) * REF_LTM_BINS;
+                double num = 0.0, den = 0.0;
+                for (int b = 0; b < REF_LTM_BINS; ++b) {
+                    num += s[b] * ltm_tri_cdf(u - b);
+                    den += s[b];
+                }
+                tl += wt[c] * (num / den);
+            }
+            t_out[i] = (1.0 - strength) * tg[i] + strength * tl;
+        }
+    }
+done:
+    free(lhat);
+    free(tg);
+    free(hist);
+    free(smooth);
+    return rc;
+}

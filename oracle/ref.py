@@ -152,3 +152,78 @@ def tonemap_colour(pixels, dtype, eps, contrast, sigma_floor, saturation,
         rgb.append(out_row)
         t_rows.append(t_row)
     return rgb, t_rows
+
+
+def tonemap_local(pixels, dtype, eps, contrast, sigma_floor, strength,
+                  beta_r=BETA_R, beta_k=BETA_K, tile=64, bins=64):
+    """Local tone map of a nested-list image: smoothed local histogram
+    equalisation on a tile grid blended with the global curve (same reading as
+    the C oracle, written independently; for tiny images only)."""
+    lhat = decolorize_image(pixels, dtype, beta_r, beta_k)
+    h, w = len(lhat), len(lhat[0])
+    flat = [v for row in lhat for v in row]
+    mu, sigma, _, _ = tonemap_stats(flat, eps)
+    nx, ny = -(-w // tile), -(-h // tile)
+
+    def pos(v):
+        u = 2.0 * math.log((v + eps) / eps, 2) - 0.5
+        return min(max(u, 0.0), bins - 1.0)
+
+    hist = {(tx, ty): [0.0] * bins for tx in range(nx) for ty in range(ny)}
+    for y in range(h):
+        for x in range(w):
+            u = pos(lhat[y][x])
+            k = min(int(math.floor(u)), bins - 2)
+            f = u - k
+            hb = hist[(x // tile, y // tile)]
+            hb[k] += 1.0 - f
+            hb[k + 1] += f
+    smooth = {}
+    for (tx, ty) in hist:
+        acc = [0.0] * bins
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nb = hist.get((tx + dx, ty + dy))
+                if nb is None:
+                    continue
+                wgt = (2.0 if dx == 0 else 1.0) * (2.0 if dy == 0 else 1.0)
+                for b in range(bins):
+                    acc[b] += wgt * nb[b]
+        smooth[(tx, ty)] = acc
+
+    def ramp(x):  # integral of the unit triangle
+        if x <= -1.0:
+            return 0.0
+        if x <= 0.0:
+            return 0.5 * (1.0 + x) ** 2
+        if x <= 1.0:
+            return 1.0 - 0.5 * (1.0 - x) ** 2
+        return 1.0
+
+    def curve(t, u):
+        s = smooth[t]
+        return math.fsum(s[b] * ramp(u - b) for b in range(bins)) / math.fsum(s)
+
+    def corners(p, n):
+        g = (p + 0.5) / tile - 0.5
+        a = math.floor(g)
+        fr = g - a
+        if a < 0:
+            a, fr = 0, 0.0
+        if a >= n - 1:
+            a, fr = n - 1, 0.0
+        return a, min(a + 1, n - 1), fr
+
+    out = []
+    for y in range(h):
+        y0, y1, fy = corners(y, ny)
+        row = []
+        for x in range(w):
+            x0, x1, fx = corners(x, nx)
+            u = pos(lhat[y][x])
+            tl = ((1 - fx) * (1 - fy) * curve((x0, y0), u) + fx * (1 - fy) * curve((x1, y0), u) +
+                  (1 - fx) * fy * curve((x0, y1), u) + fx * fy * curve((x1, y1), u))
+            tg = tonemap_curve(lhat[y][x], eps, contrast, mu, sigma, sigma_floor)
+            row.append((1.0 - strength) * tg + strength * tl)
+        out.append(row)
+    return out
