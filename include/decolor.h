@@ -88,17 +88,19 @@ typedef struct dc_params {
     float beta_k; /* default 0.80 */
 } dc_params;
 
-/* Global tone-curve parameters (Sec. III-B.1 reading above). eps > 0 keeps the
+/* Tone-curve parameters (Sec. III-B.1 reading above). eps > 0 keeps the
  * logarithm finite on black pixels; contrast > 0 is the slope in units of the
  * image's standard deviation; sigma_floor > 0 bounds the slope on flat images;
  * saturation in [0, 2] is the exponent s of the colour output (used only by
- * images flagged DC_IMG_RGB_OUT; note that a zero-filled struct asks for s = 0,
- * a grey result). */
+ * images flagged DC_IMG_RGB_OUT); local_strength in [0, 1] is the weight of the
+ * local curve in dc_tonemap_local (0 gives the global tone map). Note that a
+ * zero-filled struct asks for s = 0 (grey) and strength 0. */
 typedef struct dc_tm_params {
-    float eps;         /* default 1e-4 */
-    float contrast;    /* default 2.0  */
-    float sigma_floor; /* default 1e-3 */
-    float saturation;  /* default 1.0  */
+    float eps;            /* default 1e-4 */
+    float contrast;       /* default 2.0  */
+    float sigma_floor;    /* default 1e-3 */
+    float saturation;     /* default 1.0  */
+    float local_strength; /* default 0.5  */
 } dc_tm_params;
 
 /* One image. width, height >= 1. src_pitch >= 3 * width * sizeof(src element);
@@ -183,6 +185,27 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
 int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                       const dc_tm_params *tm, dc_stats *stats, void *stream);
 
+/* Local tone map (Sec. III-B.2: tone curves from smoothed local cumulative
+ * histograms, the paper's choice for its local operator; it defers the
+ * algorithm to its cited O(1) design). Reading, per image:
+ *   u = clamp(2 log2((Lhat + eps) / eps) - 0.5, 0, 63): position on 64 bins of
+ *       log2 luminance, 2 per stop, bin centres at integers;
+ *   each 64 x 64-pixel tile (edge tiles smaller) collects a soft histogram
+ *       (mass 1 - f on bin floor(u), f on the next; f the fraction);
+ *   each tile's histogram is smoothed over its 3 x 3 tile neighbourhood with
+ *       weights (1, 2, 1) x (1, 2, 1), and its curve F_t is the cumulative
+ *       distribution of those masses spread by the unit triangle kernel;
+ *   T_l bilinearly interpolates, at the pixel's u, the curves of the four
+ *       tile centres around the pixel (centres at 64 t + 32, clamped at the
+ *       grid's edges);
+ *   T = (1 - local_strength) T_g + local_strength T_l, with T_g the global
+ *       curve above (statistics as dc_tonemap_global, written to stats).
+ * Gray output only: images flagged DC_IMG_RGB_OUT give DC_ERR_UNSUPPORTED.
+ * Histograms hold integer masses (2^-19 per pixel), so results do not depend
+ * on the order of the additions. Otherwise as dc_tonemap_global. */
+int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                     const dc_tm_params *tm, dc_stats *stats, void *stream);
+
 /* Comparator gray channels on the same data path, for side-by-side
  * comparison with Eqs. (1)-(6) on the same GPU (the paper's run-time table
  * compares its method with CIELAB L on one CPU; Sec. I quotes the rgb2gray
@@ -201,8 +224,9 @@ int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t chann
  * A plan freezes one call's images, parameters and launch shape: the
  * descriptor table is built, validated and copied to the device once, and
  * every dc_plan_run enqueues only the kernels. This is the batched launch of
- * dc_decolorize_batch (kind DC_PLAN_DECOLORIZE) or the three-kernel tone map
- * of dc_tonemap_global (kind DC_PLAN_TONEMAP) for callers that process the
+ * dc_decolorize_batch (kind DC_PLAN_DECOLORIZE), the three-kernel tone map
+ * of dc_tonemap_global (kind DC_PLAN_TONEMAP) or the local tone map of
+ * dc_tonemap_local (kind DC_PLAN_LOCAL) for callers that process the
  * same buffers repeatedly (video pipelines, serving slots). The buffers named
  * by the plan must outlive it. With DC_PLAN_GRAPH the first run captures the
  * kernels into a HIP graph on `stream` (which must not be NULL) and every run
@@ -212,10 +236,11 @@ int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t chann
 typedef struct dc_plan dc_plan;
 #define DC_PLAN_DECOLORIZE 0
 #define DC_PLAN_TONEMAP 1
+#define DC_PLAN_LOCAL 2
 #define DC_PLAN_GRAPH 1 /* flag */
 
 /* imgs: HOST array of n >= 1 descriptors; tm and stats (DEVICE, n entries)
- * only for DC_PLAN_TONEMAP; flags 0 or DC_PLAN_GRAPH. Allocates the plan's
+ * only for the tone-map kinds; flags 0 or DC_PLAN_GRAPH. Allocates the plan's
  * device workspace and waits for its upload. Errors as dc_tonemap_global. */
 int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                    const dc_params *params, const dc_tm_params *tm, dc_stats *stats,

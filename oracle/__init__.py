@@ -72,7 +72,8 @@ def _load():
     lib.ref_tonemap_image.restype = i32
     lib.ref_tonemap_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, vp, vp, vp, i32]
     lib.ref_tonemap_local_image.restype = i32
-    lib.ref_tonemap_local_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, d, vp, vp, i32]
+    lib.ref_tonemap_local_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, d, vp, vp, i32,
+                                            vp, i64]
     lib.ref_colour_channel.restype = d
     lib.ref_colour_channel.argtypes = [d, d, d, d]
     lib.ref_tonemap_colour_image.restype = i32
@@ -232,15 +233,18 @@ LTM_TILE, LTM_BINS = 64, 64
 
 
 def tonemap_local(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_floor=1e-3,
-                  strength=0.5, nthreads=1):
+                  strength=0.5, nthreads=1, sample=None):
     """Local tone map of one image (smoothed local histogram equalisation on a
-    64-pixel tile grid, blended with the global curve): (T float64 HxW, stats)."""
+    64-pixel tile grid, blended with the global curve): (T float64 HxW, stats),
+    or T at the flat pixel indices ``sample`` only."""
     img, code, w, h, pitch = _image_args(img)
-    t = np.empty((h, w), np.float64)
+    idx = None if sample is None else np.ascontiguousarray(sample, np.int64)
+    t = np.empty((h, w) if idx is None else idx.shape, np.float64)
     st = np.zeros(4, np.float64)
     rc = _load().ref_tonemap_local_image(_ptr(img), code, w, h, pitch, beta_r, beta_k, eps,
                                          contrast, sigma_floor, strength, _ptr(t), _ptr(st),
-                                         int(nthreads))
+                                         int(nthreads), None if idx is None else _ptr(idx),
+                                         0 if idx is None else idx.size)
     if rc != 0:
         raise ValueError("oracle rejected the image or the strength")
     return t, {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": w * h}

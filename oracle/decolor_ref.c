@@ -540,10 +540,12 @@ static double ltm_tri_cdf(double x)
     return 1.0;
 }
 
+/* sample: NULL, or nsample pixel indices (y * W + x) at which alone T is
+ * evaluated into t_out[0 .. nsample) (steps 1 to 4 still cover every pixel). */
 int ref_tonemap_local_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes,
                             double beta_r, double beta_k, double eps, double contrast,
                             double sigma_floor, double strength, double *t_out, double *stats,
-                            int nthreads)
+                            int nthreads, const int64_t *sample, int64_t nsample)
 {
     if (!t_out || !stats || W < 1 || H < 1 || !(strength >= 0.0 && strength <= 1.0))
         return -1;
@@ -589,7 +591,13 @@ int ref_tonemap_local_image(const void *src, int dtype, int W, int H, int64_t pi
                 }
         }
     /* steps 5 to 7 */
-    for (int y = 0; y < H; ++y) {
+    for (int64_t j = 0; j < (sample ? nsample : n); ++j) {
+        const int64_t pix = sample ? sample[j] : j;
+        if (pix < 0 || pix >= n) {
+            rc = -1;
+            goto done;
+        }
+        const int y = (int)(pix / W), x = (int)(pix % W);
         double gy = (y + 0.5) / REF_LTM_TILE - 0.5;
         int ty0 = (int)floor(gy);
         double fy = gy - ty0;
@@ -602,7 +610,7 @@ int ref_tonemap_local_image(const void *src, int dtype, int W, int H, int64_t pi
             fy = 0.0;
         }
         int ty1 = ty0 + 1 < ny ? ty0 + 1 : ny - 1;
-        for (int x = 0; x < W; ++x) {
+        {
             double gx = (x + 0.5) / REF_LTM_TILE - 0.5;
             int tx0 = (int)floor(gx);
             double fx = gx - tx0;
@@ -629,7 +637,7 @@ int ref_tonemap_local_image(const void *src, int dtype, int W, int H, int64_t pi
                 }
                 tl += wt[c] * (num / den);
             }
-            t_out[i] = (1.0 - strength) * tg[i] + strength * tl;
+            t_out[j] = (1.0 - strength) * tg[i] + strength * tl;
         }
     }
 done:

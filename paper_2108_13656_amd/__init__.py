@@ -30,6 +30,7 @@ _TORCH_TO_DC = {torch.uint8: DC_U8, torch.float16: DC_F16, torch.float32: DC_F32
 BETA_R = 0.55  # Eq. (3) weight chosen after Eq. (6)
 BETA_K = 0.80  # Eq. (6) weight
 TM_EPS, TM_CONTRAST, TM_SIGMA_FLOOR, TM_SATURATION = 1e-4, 2.0, 1e-3, 1.0
+TM_LOCAL_STRENGTH = 0.5
 DC_IMG_RGB_OUT = 1  # dc_image.flags: tone-map dst holds re-coloured RGB
 
 
@@ -48,7 +49,8 @@ class DcParams(ctypes.Structure):
 
 class DcTmParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("contrast", ctypes.c_float),
-                ("sigma_floor", ctypes.c_float), ("saturation", ctypes.c_float)]
+                ("sigma_floor", ctypes.c_float), ("saturation", ctypes.c_float),
+                ("local_strength", ctypes.c_float)]
 
 
 class DcStats(ctypes.Structure):
@@ -87,7 +89,7 @@ class DcTuning(ctypes.Structure):
         return t
 
 
-PLAN_DECOLORIZE, PLAN_TONEMAP, PLAN_GRAPH = 0, 1, 1
+PLAN_DECOLORIZE, PLAN_TONEMAP, PLAN_LOCAL, PLAN_GRAPH = 0, 1, 2, 1
 
 
 class DcServerConfig(ctypes.Structure):
@@ -133,6 +135,7 @@ def lib():
     L.dc_decolorize.argtypes = [vp, img_p, par_p, vp]
     L.dc_decolorize_batch.argtypes = [vp, img_p, i32, par_p, vp]
     L.dc_tonemap_global.argtypes = [vp, img_p, i32, par_p, tm_p, vp, vp]
+    L.dc_tonemap_local.argtypes = [vp, img_p, i32, par_p, tm_p, vp, vp]
     L.dc_status_string.argtypes = [ctypes.c_int]
     L.dc_status_string.restype = ctypes.c_char_p
     L.dc_last_error_message.argtypes = []
@@ -164,7 +167,7 @@ def lib():
                  "dc_plan_create", "dc_plan_run", "dc_plan_destroy", "dc_get_tuning",
                  "dc_set_tuning", "dc_autotune", "dc_server_create", "dc_server_destroy",
                  "dc_server_submit", "dc_server_step", "dc_server_poll", "dc_server_replay",
-                 "dc_channel_batch", "dc_decolorize_batch_betas"):
+                 "dc_channel_batch", "dc_decolorize_batch_betas", "dc_tonemap_local"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -411,11 +414,39 @@ def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, 
         stats = torch.empty((len(xs), STATS_BYTES), dtype=torch.uint8, device=dev)
     arr = _image_array(xs, outs, lhats)
     p = _params(beta_r, beta_k)
-    tm = DcTmParams(eps, contrast, sigma_floor, saturation)
+    tm = DcTmParams(eps, contrast, sigma_floor, saturation, TM_LOCAL_STRENGTH)
     _check(lib().dc_tonemap_global(context(dev).handle, arr, len(xs), ctypes.byref(p),
                                    ctypes.byref(tm),
                                    ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
                                    _stream_ptr(stream, dev)))
+    return outs, lhats, stats
+
+
+def tonemap_local(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
+                  eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR,
+                  strength=TM_LOCAL_STRENGTH, outs=None, lhats=None, stats=None, want_stats=True,
+                  stream=None):
+    """Local tone map (Sec. III-B.2: smoothed local histogram equalisation on
+    64-pixel tiles, blended with the global curve by ``strength``) of a list of
+    images. Returns (T outputs, Lhat outputs or None, stats) as
+    ``tonemap_global``."""
+    xs = list(xs)
+    if not xs:
+        return [], None, None
+    dev = xs[0].device
+    if outs is None:
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+    if lhats is None and lhat_dtype is not None:
+        lhats = [_alloc(x, lhat_dtype, x.shape[0], x.shape[1]) for x in xs]
+    if stats is None and want_stats:
+        stats = torch.empty((len(xs), STATS_BYTES), dtype=torch.uint8, device=dev)
+    arr = _image_array(xs, outs, lhats)
+    p = _params(beta_r, beta_k)
+    tm = DcTmParams(eps, contrast, sigma_floor, TM_SATURATION, strength)
+    _check(lib().dc_tonemap_local(context(dev).handle, arr, len(xs), ctypes.byref(p),
+                                  ctypes.byref(tm),
+                                  ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                                  _stream_ptr(stream, dev)))
     return outs, lhats, stats
 
 
@@ -433,8 +464,8 @@ def validate(images, beta_r=BETA_R, beta_k=BETA_K, tm=None):
     """Host-only check of DcImage descriptors (no GPU needed). Returns the status."""
     arr = (DcImage * len(images))(*images) if images else None
     p = _params(beta_r, beta_k)
-    if tm is not None and len(tm) == 3:
-        tm = tuple(tm) + (TM_SATURATION,)
+    if tm is not None:
+        tm = tuple(tm) + (TM_SATURATION, TM_LOCAL_STRENGTH)[len(tm) - 3:]
     tmp = DcTmParams(*tm) if tm is not None else None
     return lib().dc_validate(arr, len(images), ctypes.byref(p),
                              ctypes.byref(tmp) if tmp is not None else None)
@@ -447,13 +478,14 @@ class Plan:
 
     def __init__(self, kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
                  contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stats=None, graph=False,
-                 saturation=TM_SATURATION):
+                 saturation=TM_SATURATION, local_strength=TM_LOCAL_STRENGTH):
         xs = list(xs)
         self.device = xs[0].device
         self._keep = (xs, list(outs), None if outs2 is None else list(outs2), stats)
         arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
         p = _params(beta_r, beta_k)
-        tm = DcTmParams(eps, contrast, sigma_floor, saturation) if kind == PLAN_TONEMAP else None
+        tm = (DcTmParams(eps, contrast, sigma_floor, saturation, local_strength)
+              if kind in (PLAN_TONEMAP, PLAN_LOCAL) else None)
         self._h = ctypes.c_void_p()
         _check(lib().dc_plan_create(context(self.device).handle, kind, arr, len(xs),
                                     ctypes.byref(p), ctypes.byref(tm) if tm is not None else None,
@@ -517,7 +549,8 @@ class Server:
             device = torch.cuda.current_device()
         self.device = device if isinstance(device, torch.device) else torch.device("cuda", device)
         cfg = DcServerConfig(budget_bytes, max_batch, max_inflight, 0, DcParams(beta_r, beta_k),
-                             DcTmParams(eps, contrast, sigma_floor, saturation))
+                             DcTmParams(eps, contrast, sigma_floor, saturation,
+                                        TM_LOCAL_STRENGTH))
         self._h = ctypes.c_void_p()
         _check(lib().dc_server_create(context(self.device).handle, ctypes.byref(cfg),
                                       ctypes.byref(self._h)))
@@ -583,7 +616,7 @@ def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EP
     dev = xs[0].device
     arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
     p = _params(beta_r, beta_k)
-    tm = DcTmParams(eps, contrast, sigma_floor, saturation)
+    tm = DcTmParams(eps, contrast, sigma_floor, saturation, TM_LOCAL_STRENGTH)
     t = DcTuning()
     _check(lib().dc_autotune(context(dev).handle, kind, arr, len(xs), ctypes.byref(p),
                              ctypes.byref(tm), _stream_ptr(stream, dev), ctypes.byref(t)))

@@ -13,6 +13,13 @@ constexpr int kStatsPxPerThread = 16; // pixels per thread in a statistics chunk
 constexpr int64_t kStatsChunkPx = (int64_t)kBlock * kStatsPxPerThread; // 4096 px per tile
 constexpr int kWavesPerBlock = kBlock / 64; // statistics partials per tone-map tile
 
+// Local tone map: square tiles of kLtmTile pixels (one workgroup's 4096-pixel
+// statistics chunk each), kLtmBins soft bins of log2 luminance, 2 per stop
+// from log2(eps), histogram masses in fixed point (kLtmOne per pixel).
+constexpr int kLtmTile = 64;
+constexpr int kLtmBins = 64;
+constexpr unsigned kLtmOne = 1u << 19;
+
 // Pixels per vector group for each input element type (48 B of RGB).
 __host__ __device__ constexpr int group_px(int src_dtype)
 {
@@ -62,6 +69,8 @@ struct DevImage {
     int32_t walk;
     int32_t image;          // index within the call
     int32_t rgb_out;        // tone map: dst holds 3 channels (re-coloured RGB)
+    int32_t width;          // pixels per row (local tone map's 2-D tile walk)
+    int32_t height;         // rows
     float unit;             // Lhat = L * unit (1/255 for 8-bit input)
     Coef k;                 // per-pixel constants for this image's input type
 };
@@ -83,6 +92,13 @@ struct TmArgs {
     float contrast;
     float sigma_floor;
     float saturation; // exponent s of the colour output
+    float strength;   // local tone map: weight of the local curve
+};
+
+// Local tone map: one tile's curve as a quadratic per bin interval k:
+// F(k + f) = a + f (b + f c), f in [0, 1].
+struct LtmCoef {
+    float a, b, c, pad;
 };
 
 // Colour output modes: s = 0 (grey T), s = 1 (ratio kept), any other s.
@@ -113,6 +129,15 @@ hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs 
 hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                             int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
                             const Curve *curves, int64_t grid, hipStream_t s);
+hipError_t launch_ltm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, Part *parts,
+                            unsigned *hist, int64_t grid, hipStream_t s);
+hipError_t launch_ltm_tables(const DevImage *table, const int64_t *tile_end, int nimg,
+                             int64_t total_tiles, const unsigned *hist, LtmCoef *coef,
+                             hipStream_t s);
+hipError_t launch_ltm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, const Curve *curves,
+                            const LtmCoef *coef, int64_t grid, hipStream_t s);
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                            int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            const Curve *curves, int64_t grid, hipStream_t s);

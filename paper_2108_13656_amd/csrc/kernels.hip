@@ -342,6 +342,15 @@ __device__ __forceinline__ float lum_at(const TileRef &t, uint32_t p, Coef k)
     return lum<SRC>(R, G_, B, k);
 }
 
+// L (input units) of the pixel at p, loaded channel by channel.
+template <int SRC>
+__device__ __forceinline__ void lum_at_px(const uint8_t *p, Coef k, float &l)
+{
+    float R, G_, B;
+    load_px<SRC>(p, R, G_, B);
+    l = lum<SRC>(R, G_, B, k);
+}
+
 // Visits global tiles t0 + blockIdx.x, t0 + blockIdx.x + gridDim.x, ... below
 // t1 with the index of the image that owns each, searching images img0 ..
 // img0 + nimg - 1. tile_end is the inclusive prefix sum of the images' tile
@@ -1026,6 +1035,352 @@ __global__ __launch_bounds__(kBlock) void k_tm_colour(const DevImage *__restrict
     });
 }
 
+// ----------------------------------------------------- local tone map
+
+// The local tone map (Sec. III-B.2, smoothed local histogram equalisation)
+// walks each image in square tiles of kLtmTile x kLtmTile pixels, one tile per
+// workgroup visit: 64 rows of 64 / PPU work units. Thread t, pass i takes row
+// i * (kBlock / UPR) + t / UPR and unit t % UPR of it (UPR = units per tile
+// row), so a wave's lanes cover whole row segments and slot 0 of lane 0 is
+// the wave's first pixel in the tile; each row segment of a pass is contiguous
+// in memory.
+struct LtmRef {
+    const uint8_t *src; // tile's pixel (0, 0)
+    uint8_t *dst;
+    uint8_t *dst2;
+    int64_t sp, dp, d2p; // row pitches
+    int bw, bh;          // tile width and height inside the image
+    int tx, ty, nx, ny;  // tile coordinates and grid size
+    bool vec;            // full-width tile on a 16-byte aligned walk
+};
+
+__device__ __forceinline__ LtmRef ltm_ref(const DevImage &im, int64_t tile)
+{
+    LtmRef r;
+    r.nx = (int)im.tiles_per_seg;
+    r.ny = (int)(im.ntiles / im.tiles_per_seg);
+    r.ty = (int)(tile / r.nx);
+    r.tx = (int)(tile - (int64_t)r.ty * r.nx);
+    const int64_t x0 = (int64_t)r.tx * kLtmTile, y0 = (int64_t)r.ty * kLtmTile;
+    r.bw = (int)min((int64_t)kLtmTile, (int64_t)im.width - x0);
+    r.bh = (int)min((int64_t)kLtmTile, (int64_t)im.height - y0);
+    r.sp = im.src_seg_stride;
+    r.dp = im.dst_seg_stride;
+    r.d2p = im.dst2_seg_stride;
+    r.src = im.src + y0 * r.sp + x0 * 3 * elem_size(im.src_dtype);
+    r.dst = im.dst + y0 * r.dp + x0 * elem_size(im.dst_dtype);
+    r.dst2 = im.dst2 ? im.dst2 + y0 * r.d2p + x0 * elem_size(im.dst2_dtype) : nullptr;
+    r.vec = im.walk != kWalkScalar && r.bw == kLtmTile;
+    return r;
+}
+
+// Row and first column (within the tile) of slot (pass i, unit pixel q).
+template <int PPU>
+__device__ __forceinline__ void ltm_slot(int i, int q, int &row, int &col)
+{
+    constexpr int UPR = kLtmTile / PPU;
+    constexpr int RPP = kBlock / UPR;
+    const int t = threadIdx.x;
+    row = i * RPP + t / UPR;
+    col = (t % UPR) * PPU + q;
+}
+
+// Bin position u in [0, kLtmBins - 1] of x2 = log2(Lhat + eps): 2 bins per
+// stop, bin centres at integers, bin 0 centred half a bin above log2(eps).
+__device__ __forceinline__ float ltm_u(float x2, float lo2)
+{
+    const float u = fmaf(2.0f, x2 - lo2, -0.5f);
+    return fminf(fmaxf(u, 0.0f), (float)(kLtmBins - 1));
+}
+
+// Statistics pass of the local tone map over one tile: the global statistics
+// partial of each wave (as tm_pass1_tile) and the tile's soft histogram of u
+// (mass 1 - f to bin k, f to bin k + 1, in units of 2^-19, integer LDS atomics,
+// so the histogram does not depend on the order of the adds).
+template <int SRC>
+__device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
+                                               Part *__restrict__ parts,
+                                               unsigned *__restrict__ hist, unsigned *lds_hist)
+{
+    constexpr int PPU = unit_px(SRC);
+    constexpr int U = kStatsPxPerThread / PPU;
+    constexpr int ES = elem_size(SRC);
+    constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
+    const LtmRef r = ltm_ref(im, tile);
+    const Enc e{im.unit, 255.0f};
+    const float lo2 = hw_log2(tm.eps);
+    if (threadIdx.x < kLtmBins)
+        lds_hist[threadIdx.x] = 0u;
+    __syncthreads();
+    float K = 0.0f, s = 0.0f, q = 0.0f, cnt = 0.0f, lo = __builtin_inff(), hi = -__builtin_inff();
+    {
+        int row0, col0;
+        ltm_slot<PPU>(0, 0, row0, col0);
+        float l0 = 0.0f;
+        if (row0 < r.bh && col0 < r.bw)
+            lum_at_px<SRC>(r.src + row0 * r.sp + col0 * 3 * ES, im.k, l0);
+        K = __builtin_bit_cast(
+            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, xlog2(l0, im.unit, tm.eps))));
+    }
+    auto add = [&](float l) {
+        const float x2 = xlog2(l, im.unit, tm.eps);
+        const float d = x2 - K;
+        s += d;
+        q = fmaf(d, d, q);
+        lo = fminf(lo, l);
+        hi = fmaxf(hi, l);
+        cnt += 1.0f;
+        const float u = ltm_u(x2, lo2);
+        const int k = min((int)u, kLtmBins - 2);
+        const unsigned whi = (unsigned)fmaf(u - (float)k, (float)kLtmOne, 0.5f);
+        atomicAdd(&lds_hist[k], kLtmOne - whi);
+        atomicAdd(&lds_hist[k + 1], whi);
+    };
+    if (r.vec) {
+        // all of the thread's unit loads first, then the arithmetic
+        unsigned w[U][3];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            if (row < r.bh)
+                load_unit(r.src + row * r.sp + col * 3 * ES, w[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            if (row < r.bh) {
+                float v[PPU];
+#pragma unroll
+                for (int j = 0; j < PPU; ++j) {
+                    v[j] = lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
+                                    chan<SRC>(w[i], 3 * j + 2), im.k);
+                    add(v[j]);
+                }
+                if (r.dst2)
+                    store_unit<PPU, SF, SU>(r.dst2 + row * r.d2p, im.dst2_dtype, col, v, e);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int sl = 0; sl < kStatsPxPerThread; ++sl) {
+            int row, col;
+            ltm_slot<PPU>(sl / PPU, sl % PPU, row, col);
+            if (row < r.bh && col < r.bw) {
+                float l;
+                lum_at_px<SRC>(r.src + row * r.sp + col * 3 * ES, im.k, l);
+                add(l);
+                if (r.dst2)
+                    store_px<SF, SU>(r.dst2 + row * r.d2p, im.dst2_dtype, col, l, e);
+            }
+        }
+    }
+    s = wave_sum(s);
+    q = wave_sum(q);
+    const float n = wave_sum(cnt);
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & 63) == 0) {
+        Part p = part_empty();
+        if (n > 0.0f) {
+            const float m = s / n;
+            p = Part{n, K + m, fmaxf(fmaf(-s, m, q), 0.0f), lo * im.unit, hi * im.unit};
+        }
+        parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x < kLtmBins)
+        hist[(im.tile_begin + tile) * kLtmBins + threadIdx.x] = lds_hist[threadIdx.x];
+    __syncthreads();
+}
+
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_ltm_pass1(const DevImage *__restrict__ table,
+                                                      const int64_t *__restrict__ tile_end,
+                                                      int img0, int nimg, int64_t t0, int64_t t1,
+                                                      TmArgs tm, Part *__restrict__ parts,
+                                                      unsigned *__restrict__ hist)
+{
+    __shared__ unsigned lds_hist[kLtmBins];
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
+        const DevImage im = table[i];
+        ltm_pass1_tile<SRC>(im, tile - im.tile_begin, tm, parts, hist, lds_hist);
+    });
+}
+
+// Per tile: the 3 x 3 smoothing of the neighbouring tiles' histograms with
+// weights (1, 2, 1) x (1, 2, 1) (tiles outside the grid left out), the prefix
+// sums over the bins, and the quadratic of each bin interval,
+//   F(k + f) = [P(k) + H(k)/2 + H(k) f + (H(k+1) - H(k)) f^2 / 2] / M,
+// which is the triangle-smoothed cumulative distribution exactly. One wave per
+// tile, lane b = bin b; integer sums in double (exact below 2^53).
+__global__ __launch_bounds__(64) void k_ltm_tables(const DevImage *__restrict__ table,
+                                                   const int64_t *__restrict__ tile_end, int nimg,
+                                                   const unsigned *__restrict__ hist,
+                                                   LtmCoef *__restrict__ coef)
+{
+    const int64_t g = blockIdx.x;
+    int lo = 0, hi = nimg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_end[mid] > g)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const DevImage im = table[lo];
+    const int nx = (int)im.tiles_per_seg, ny = (int)(im.ntiles / im.tiles_per_seg);
+    const int64_t lt = g - im.tile_begin;
+    const int ty = (int)(lt / nx), tx = (int)(lt - (int64_t)ty * nx);
+    const int b = threadIdx.x;
+    double h = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int sy = ty + dy;
+        if (sy < 0 || sy >= ny)
+            continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int sx = tx + dx;
+            if (sx < 0 || sx >= nx)
+                continue;
+            const double w = (dx == 0 ? 2.0 : 1.0) * (dy == 0 ? 2.0 : 1.0);
+            h += w * (double)hist[(im.tile_begin + (int64_t)sy * nx + sx) * kLtmBins + b];
+        }
+    }
+    // inclusive scan over the 64 lanes, then the exclusive prefix and total
+    double incl = h;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double v = __shfl_up(incl, off, 64);
+        if (b >= off)
+            incl += v;
+    }
+    const double total = __shfl(incl, 63, 64);
+    const double prefix = incl - h;
+    const double next = __shfl_down(h, 1, 64);
+    const double inv = 1.0 / total;
+    LtmCoef c;
+    c.a = (float)((prefix + 0.5 * h) * inv);
+    c.b = (float)(h * inv);
+    c.c = b < kLtmBins - 1 ? (float)(0.5 * (next - h) * inv) : 0.0f;
+    c.pad = 0.0f;
+    coef[g * kLtmBins + b] = c;
+}
+
+// Curve pass of the local tone map over one tile: the 3 x 3 neighbourhood's
+// curve tables are staged in LDS, then every pixel gets
+//   T = T_g + strength (T_l - T_g),
+// T_g the global curve and T_l the bilinear interpolation, between the four
+// tile centres around the pixel, of those tiles' curves at the pixel's u.
+// Tile centres sit at 64 t + 32 pixels; the interpolation weights are exact
+// multiples of 1/64.
+template <int SRC>
+__device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile, TmArgs tm,
+                                               Curve cv, const LtmCoef *__restrict__ coef,
+                                               LtmCoef *lds)
+{
+    constexpr int PPU = unit_px(SRC);
+    constexpr int U = kStatsPxPerThread / PPU;
+    constexpr int ES = elem_size(SRC);
+    const LtmRef r = ltm_ref(im, tile);
+    const Enc e{1.0f, 255.0f};
+    const float lo2 = hw_log2(tm.eps);
+    for (int idx = threadIdx.x; idx < 9 * kLtmBins; idx += kBlock) {
+        const int nb = idx / kLtmBins, bin = idx - nb * kLtmBins;
+        const int sx = r.tx + nb % 3 - 1, sy = r.ty + nb / 3 - 1;
+        if (sx >= 0 && sx < r.nx && sy >= 0 && sy < r.ny)
+            lds[idx] = coef[(im.tile_begin + (int64_t)sy * r.nx + sx) * kLtmBins + bin];
+    }
+    __syncthreads();
+    // Interpolation corner (neighbourhood index 0..2) and weight along one axis
+    // for the pixel at tile-local position p of tile t in a grid of n tiles.
+    auto axis = [](int p, int t, int n, int &c0, int &c1, float &w) {
+        const float g = ((float)(t * kLtmTile + p) + 0.5f) * (1.0f / kLtmTile) - 0.5f;
+        int a = (int)floorf(g);
+        w = g - (float)a;
+        if (a < 0) {
+            a = 0;
+            w = 0.0f;
+        }
+        if (a >= n - 1) {
+            a = n - 1;
+            w = 0.0f;
+        }
+        const int b = min(a + 1, n - 1);
+        c0 = a - t + 1;
+        c1 = b - t + 1;
+    };
+    auto value = [&](float l, int row, int col) {
+        const float x2 = xlog2(l, im.unit, tm.eps);
+        const float tg = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
+        const float u = ltm_u(x2, lo2);
+        const int k = min((int)u, kLtmBins - 2);
+        const float f = u - (float)k;
+        int cx0, cx1, cy0, cy1;
+        float wx, wy;
+        axis(col, r.tx, r.nx, cx0, cx1, wx);
+        axis(row, r.ty, r.ny, cy0, cy1, wy);
+        auto F = [&](int cx, int cy) {
+            const LtmCoef c = lds[(cy * 3 + cx) * kLtmBins + k];
+            return fmaf(f, fmaf(f, c.c, c.b), c.a);
+        };
+        const float top = fmaf(wx, F(cx1, cy0) - F(cx0, cy0), F(cx0, cy0));
+        const float bot = fmaf(wx, F(cx1, cy1) - F(cx0, cy1), F(cx0, cy1));
+        const float tl = fmaf(wy, bot - top, top);
+        return fmaf(tm.strength, tl - tg, tg);
+    };
+    if (r.vec) {
+        unsigned w[U][3];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            if (row < r.bh)
+                load_unit(r.src + row * r.sp + col * 3 * ES, w[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            if (row < r.bh) {
+                float v[PPU];
+#pragma unroll
+                for (int j = 0; j < PPU; ++j)
+                    v[j] = value(lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
+                                          chan<SRC>(w[i], 3 * j + 2), im.k),
+                                 row, col + j);
+                store_unit<PPU, false, true>(r.dst + row * r.dp, im.dst_dtype, col, v, e);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int sl = 0; sl < kStatsPxPerThread; ++sl) {
+            int row, col;
+            ltm_slot<PPU>(sl / PPU, sl % PPU, row, col);
+            if (row < r.bh && col < r.bw) {
+                float l;
+                lum_at_px<SRC>(r.src + row * r.sp + col * 3 * ES, im.k, l);
+                store_px<false, true>(r.dst + row * r.dp, im.dst_dtype, col, value(l, row, col), e);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict__ table,
+                                                      const int64_t *__restrict__ tile_end,
+                                                      int img0, int nimg, int64_t t0, int64_t t1,
+                                                      TmArgs tm, const Curve *__restrict__ curves,
+                                                      const LtmCoef *__restrict__ coef)
+{
+    __shared__ LtmCoef lds[9 * kLtmBins];
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
+        const DevImage im = table[i];
+        ltm_pass2_tile<SRC>(im, tile - im.tile_begin, tm, curves[i], coef, lds);
+    });
+}
+
 // ------------------------------------------------------------ launchers
 
 static unsigned grid_of(int64_t ntiles, int64_t grid)
@@ -1173,6 +1528,53 @@ hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int 
     default: return hipErrorInvalidValue;
     }
 #undef DC_LAUNCH_COL
+    return hipGetLastError();
+}
+
+hipError_t launch_ltm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, Part *parts,
+                            unsigned *hist, int64_t grid, hipStream_t s)
+{
+    const dim3 g(grid_of(t1 - t0, grid));
+#define DC_LAUNCH_L1(S)                                                                           \
+    hipLaunchKernelGGL((k_ltm_pass1<S>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg, t0,  \
+                       t1, tm, parts, hist)
+    if (src_dtype == 0)
+        DC_LAUNCH_L1(0);
+    else if (src_dtype == 1)
+        DC_LAUNCH_L1(1);
+    else
+        DC_LAUNCH_L1(2);
+#undef DC_LAUNCH_L1
+    return hipGetLastError();
+}
+
+hipError_t launch_ltm_tables(const DevImage *table, const int64_t *tile_end, int nimg,
+                             int64_t total_tiles, const unsigned *hist, LtmCoef *coef,
+                             hipStream_t s)
+{
+    if (total_tiles <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_ltm_tables, dim3((unsigned)total_tiles), dim3(64), 0, s, table, tile_end,
+                       nimg, hist, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_ltm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, const Curve *curves,
+                            const LtmCoef *coef, int64_t grid, hipStream_t s)
+{
+    const dim3 g(grid_of(t1 - t0, grid));
+#define DC_LAUNCH_L2(S)                                                                           \
+    hipLaunchKernelGGL((k_ltm_pass2<S>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg, t0,  \
+                       t1, tm, curves, coef)
+    if (src_dtype == 0)
+        DC_LAUNCH_L2(0);
+    else if (src_dtype == 1)
+        DC_LAUNCH_L2(1);
+    else
+        DC_LAUNCH_L2(2);
+#undef DC_LAUNCH_L2
     return hipGetLastError();
 }
 

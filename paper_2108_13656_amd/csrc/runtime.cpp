@@ -70,6 +70,8 @@ int validate_tm(const dc_tm_params *tm)
             return fail(DC_ERR_INVALID_ARG, "eps, contrast and sigma_floor must be finite and > 0");
     if (!(tm->saturation >= 0.0f && tm->saturation <= 2.0f))
         return fail(DC_ERR_INVALID_ARG, "saturation must be in [0, 2]");
+    if (!(tm->local_strength >= 0.0f && tm->local_strength <= 1.0f))
+        return fail(DC_ERR_INVALID_ARG, "local_strength must be in [0, 1]");
     return DC_OK;
 }
 
@@ -192,8 +194,9 @@ dc::Coef coef_of(const dc_params *p, int src_dtype)
 
 dc::TmArgs tm_of(const dc_tm_params *tm)
 {
-    return tm ? dc::TmArgs{tm->eps, tm->contrast, tm->sigma_floor, tm->saturation}
-              : dc::TmArgs{1e-4f, 2.0f, 1e-3f, 1.0f};
+    return tm ? dc::TmArgs{tm->eps, tm->contrast, tm->sigma_floor, tm->saturation,
+                           tm->local_strength}
+              : dc::TmArgs{1e-4f, 2.0f, 1e-3f, 1.0f, 0.5f};
 }
 
 // Walk classification and tile count of one image for tiles of tile_px pixels.
@@ -211,6 +214,8 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
     d.rgb_out = (m.flags & DC_IMG_RGB_OUT) ? 1 : 0;
     d.unit = m.src_dtype == DC_U8 ? (float)(1.0 / 255.0) : 1.0f;
     d.npx = (int64_t)m.width * m.height;
+    d.width = m.width;
+    d.height = m.height;
     d.k = coef_of(params, m.src_dtype);
 
     const int64_t W = m.width, H = m.height;
@@ -238,6 +243,30 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
     }
     d.tiles_per_seg = (d.seg_len + tile_px - 1) / tile_px;
     d.ntiles = d.tiles_per_seg * nseg;
+    return d;
+}
+
+// Local tone map: a grid of kLtmTile-square tiles per image, walked row by
+// row inside a tile. Unit loads need 4-byte aligned rows; unit stores of the
+// outputs the same 16-byte alignment as the other walks, else per pixel.
+dc::DevImage describe_local(const dc_image &m, int index, const dc_params *params)
+{
+    dc::DevImage d = describe(m, index, dc::kStatsChunkPx, params);
+    const int64_t W = m.width, H = m.height;
+    const int64_t nx = (W + dc::kLtmTile - 1) / dc::kLtmTile;
+    const int64_t ny = (H + dc::kLtmTile - 1) / dc::kLtmTile;
+    d.width = m.width;
+    d.height = m.height;
+    d.seg_len = W;
+    d.tiles_per_seg = nx;
+    d.ntiles = nx * ny;
+    d.src_seg_stride = m.src_pitch;
+    d.dst_seg_stride = m.dst_pitch;
+    d.dst2_seg_stride = m.dst2 ? m.dst2_pitch : 0;
+    const bool src4 = (uintptr_t)m.src % 4 == 0 && m.src_pitch % 4 == 0;
+    const bool out16 = (uintptr_t)m.dst % 16 == 0 && m.dst_pitch % 16 == 0 &&
+                       (!m.dst2 || ((uintptr_t)m.dst2 % 16 == 0 && m.dst2_pitch % 16 == 0));
+    d.walk = (src4 && out16) ? dc::kWalkRows : dc::kWalkScalar;
     return d;
 }
 
@@ -330,7 +359,8 @@ struct HostTable {
     bool mixed = false;
     int src0 = 0;
     int groups = 2;  // decolorization only
-    bool tonemap = false;
+    bool tonemap = false; // statistics workspace (global and local tone map)
+    bool local = false;   // local tone map: histograms and curve tables too
     // Tone map and channels: the table is stably sorted by input type (then
     // gray before colour output); runs[k] = {first image, end image, type,
     // colour output} of each run, so each pass launches its per-type kernel
@@ -344,18 +374,19 @@ struct HostTable {
 // kind of table: decolorization (tiles of the tuned group count), tone map
 // (fixed 4096-pixel tiles, sorted by input type) or comparator channel (one
 // 48-byte group per thread, sorted by input type).
-enum TableKind { kTabDecolor = 0, kTabTonemap = 1, kTabChannel = 2 };
+enum TableKind { kTabDecolor = 0, kTabTonemap = 1, kTabChannel = 2, kTabLocal = 3 };
 
 // per_image, when not NULL, holds one dc_params per image (in the caller's
 // order) and overrides params.
 void build_table(const dc_image *imgs, int32_t n, const dc_params *params, TableKind kind,
                  const Tune &tune, HostTable &h, const dc_params *per_image = nullptr)
 {
-    const bool tonemap = kind == kTabTonemap;
+    const bool tonemap = kind == kTabTonemap || kind == kTabLocal;
     h.d.resize((size_t)n);
     h.tile_end.resize((size_t)n);
     h.grp_end.resize((size_t)n);
     h.tonemap = tonemap;
+    h.local = kind == kTabLocal;
     h.src0 = n > 0 ? imgs[0].src_dtype : 0;
     h.mixed = false;
     for (int32_t i = 0; i < n; ++i)
@@ -378,7 +409,9 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
             tonemap ? dc::kStatsChunkPx
                     : (int64_t)dc::kBlock * (kind == kTabChannel ? 1 : h.groups) *
                           dc::group_px(m.src_dtype);
-        h.d[i] = describe(m, order[i], tile_px, per_image ? &per_image[order[i]] : params);
+        const dc_params *pp = per_image ? &per_image[order[i]] : params;
+        h.d[i] = kind == kTabLocal ? describe_local(m, order[i], pp)
+                                   : describe(m, order[i], tile_px, pp);
         const int rgb = h.d[i].rgb_out;
         if (h.runs.empty() || h.runs.back().src != m.src_dtype || h.runs.back().rgb != rgb)
             h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype, rgb});
@@ -401,9 +434,10 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
 }
 
 // Byte layout of the device copy: table | tile ends | group ends (uploaded)
-// then the workspace: wave partials | group partials | curves.
+// then the workspace: wave partials | group partials | curves, and for the
+// local tone map tile histograms | tile curve tables.
 struct Layout {
-    size_t table, ends, gends, parts, parts2, curves, upload, total;
+    size_t table, ends, gends, parts, parts2, curves, hist, coef, upload, total;
 };
 
 Layout layout_of(const HostTable &h)
@@ -418,7 +452,10 @@ Layout layout_of(const HostTable &h)
     l.parts2 = l.parts + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_tiles *
                                                    dc::kWavesPerBlock, 256) : 0);
     l.curves = l.parts2 + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_grps, 256) : 0);
-    l.total = l.curves + (h.tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0);
+    l.hist = l.curves + (h.tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0);
+    const size_t nt = h.local ? (size_t)h.total_tiles : 0;
+    l.coef = l.hist + align_up(sizeof(unsigned) * dc::kLtmBins * nt, 256);
+    l.total = l.coef + align_up(sizeof(dc::LtmCoef) * dc::kLtmBins * nt, 256);
     return l;
 }
 
@@ -436,6 +473,8 @@ struct DevBufs {
     dc::Part *parts;
     dc::Part *parts2;
     dc::Curve *curves;
+    unsigned *hist;
+    dc::LtmCoef *coef;
 };
 
 DevBufs bufs_of(void *dev, const Layout &l)
@@ -443,7 +482,8 @@ DevBufs bufs_of(void *dev, const Layout &l)
     char *p = (char *)dev;
     return DevBufs{(const dc::DevImage *)(p + l.table), (const int64_t *)(p + l.ends),
                    (const int64_t *)(p + l.gends), (dc::Part *)(p + l.parts),
-                   (dc::Part *)(p + l.parts2), (dc::Curve *)(p + l.curves)};
+                   (dc::Part *)(p + l.parts2), (dc::Curve *)(p + l.curves),
+                   (unsigned *)(p + l.hist), (dc::LtmCoef *)(p + l.coef)};
 }
 
 // Kernel sequence of a decolorization launch over a staged table.
@@ -560,6 +600,42 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
     mark(ctx, marks, 1, st);
     if (e != hipSuccess)
         return hip_fail(e, "tonemap pipeline launch");
+    return DC_OK;
+}
+
+// Kernel sequence of the local tone map over a staged table: per input-type
+// run the statistics-and-histogram pass over 64 x 64 tiles, the two-level
+// statistics combine, the per-tile curve tables, then per run the curve pass.
+// One workgroup per tile in both passes.
+int enqueue_local(dc_ctx *ctx, const HostTable &h, const DevBufs &b, dc::TmArgs a,
+                  dc::StatsOut *stats, hipStream_t st, bool marks)
+{
+    const int n = (int)h.d.size();
+    hipError_t e = hipSuccess;
+    mark(ctx, marks, 0, st);
+    for (const auto &r : h.runs) {
+        const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
+        if (e == hipSuccess)
+            e = dc::launch_ltm_pass1(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, r.src, a,
+                                     b.parts, b.hist, 0, st);
+    }
+    mark(ctx, marks, 1, st);
+    if (e == hipSuccess)
+        e = dc::launch_tm_combine(b.table, b.grp_end, 0, n, 0, h.total_grps, b.parts, b.parts2, st);
+    if (e == hipSuccess)
+        e = dc::launch_tm_finalize(b.table, 0, n, a, b.parts2, b.curves, stats, st);
+    if (e == hipSuccess)
+        e = dc::launch_ltm_tables(b.table, b.tile_end, n, h.total_tiles, b.hist, b.coef, st);
+    mark(ctx, marks, 2, st);
+    for (const auto &r : h.runs) {
+        const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
+        if (e == hipSuccess)
+            e = dc::launch_ltm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, r.src, a,
+                                     b.curves, b.coef, 0, st);
+    }
+    mark(ctx, marks, 3, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "local tone map launch");
     return DC_OK;
 }
 
@@ -692,6 +768,8 @@ int plan_enqueue(dc_plan *p, hipStream_t st, bool marks)
 {
     if (p->kind == DC_PLAN_TONEMAP)
         return enqueue_tonemap(p->ctx, p->h, p->b, p->tune, p->tm, p->stats, st, marks);
+    if (p->kind == DC_PLAN_LOCAL)
+        return enqueue_local(p->ctx, p->h, p->b, p->tm, p->stats, st, marks);
     return enqueue_decolor(p->ctx, p->h, p->b, p->tune, st, marks);
 }
 
@@ -720,7 +798,10 @@ int plan_build(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n, const
     p->tm = tm_of(tm);
     p->stats = (dc::StatsOut *)stats;
     p->graph = (flags & DC_PLAN_GRAPH) != 0;
-    build_table(imgs, n, params, kind == DC_PLAN_TONEMAP ? kTabTonemap : kTabDecolor, tune, p->h);
+    build_table(imgs, n, params,
+                kind == DC_PLAN_TONEMAP ? kTabTonemap
+                                        : (kind == DC_PLAN_LOCAL ? kTabLocal : kTabDecolor),
+                tune, p->h);
     const Layout l = layout_of(p->h);
     std::vector<char> up(l.upload);
     write_upload(p->h, l, up.data());
@@ -748,7 +829,9 @@ int time_plan(dc_plan *p, hipStream_t st, int reps, std::vector<float> *per_inte
         return ev;
     const bool was = ctx->profiling;
     ctx->profiling = true;
-    const int nint = p->kind == DC_PLAN_TONEMAP && !p->tune.tm_pipeline ? 3 : 1;
+    const int nint = (p->kind == DC_PLAN_TONEMAP && !p->tune.tm_pipeline) || p->kind == DC_PLAN_LOCAL
+                         ? 3
+                         : 1;
     std::vector<std::vector<float>> samples(nint);
     for (int r = 0; r < reps + 1; ++r) {
         int rc = plan_enqueue(p, st, true);
@@ -1024,6 +1107,44 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
     return release_slot(slot, st);
 }
 
+namespace {
+// The local tone map writes gray T only.
+int reject_rgb(const dc_image *imgs, int32_t n)
+{
+    for (int32_t i = 0; i < n; ++i)
+        if (imgs[i].flags & DC_IMG_RGB_OUT)
+            return fail(DC_ERR_UNSUPPORTED, "the local tone map has no colour output (image " +
+                                                std::to_string(i) + ")");
+    return DC_OK;
+}
+} // namespace
+
+int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
+                     const dc_tm_params *tm, dc_stats *stats, void *stream)
+{
+    g_last_error.clear();
+    int rc = check_ctx(ctx);
+    if (rc != DC_OK)
+        return rc;
+    rc = dc_validate(imgs, n, params, tm);
+    if (rc == DC_OK)
+        rc = reject_rgb(imgs, n);
+    if (rc != DC_OK || n == 0)
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    HostTable h;
+    build_table(imgs, n, params, kTabLocal, ctx->tune, h);
+    dc_ctx::Slot *slot = nullptr;
+    DevBufs b;
+    rc = stage(ctx, h, st, &slot, &b);
+    if (rc != DC_OK)
+        return rc;
+    rc = enqueue_local(ctx, h, b, tm_of(tm), (dc::StatsOut *)stats, st, true);
+    if (rc != DC_OK)
+        return rc;
+    return release_slot(slot, st);
+}
+
 int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t channel, void *stream)
 {
     g_last_error.clear();
@@ -1068,15 +1189,18 @@ int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
     int rc = check_ctx(ctx);
     if (rc != DC_OK)
         return rc;
-    if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP)
-        return fail(DC_ERR_INVALID_ARG, "kind must be DC_PLAN_DECOLORIZE or DC_PLAN_TONEMAP");
+    if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP && kind != DC_PLAN_LOCAL)
+        return fail(DC_ERR_INVALID_ARG,
+                    "kind must be DC_PLAN_DECOLORIZE, DC_PLAN_TONEMAP or DC_PLAN_LOCAL");
     if (flags & ~DC_PLAN_GRAPH)
         return fail(DC_ERR_INVALID_ARG, "unknown plan flags");
     if (n < 1)
         return fail(DC_ERR_INVALID_ARG, "a plan needs at least one image");
     if (kind == DC_PLAN_DECOLORIZE && (tm || stats))
         return fail(DC_ERR_INVALID_ARG, "tm and stats apply to tone-map plans only");
-    rc = dc_validate(imgs, n, params, tm);
+    rc = dc_validate(imgs, n, params, kind == DC_PLAN_DECOLORIZE ? nullptr : tm);
+    if (rc == DC_OK && kind == DC_PLAN_LOCAL)
+        rc = reject_rgb(imgs, n);
     if (rc != DC_OK)
         return rc;
     return plan_build(ctx, kind, imgs, n, params, tm, stats, flags, ctx->tune, plan);

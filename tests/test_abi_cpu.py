@@ -54,7 +54,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(P.DcImage) == 72
     assert ctypes.sizeof(P.DcStats) == 24
     assert ctypes.sizeof(P.DcParams) == 8
-    assert ctypes.sizeof(P.DcTmParams) == 16
+    assert ctypes.sizeof(P.DcTmParams) == 20
 
 
 def _img(**kw):
@@ -123,6 +123,13 @@ def test_saturation_range(lib, s, ok):
     assert rc == (P.DC_OK if ok else P.DC_ERR_INVALID_ARG)
 
 
+@pytest.mark.parametrize("strength,ok", [(0.0, True), (0.5, True), (1.0, True), (-0.01, False),
+                                         (1.01, False), (float("nan"), False)])
+def test_local_strength_range(lib, strength, ok):
+    rc = P.validate([_img()], tm=(1e-4, 2.0, 1e-3, 1.0, strength))
+    assert rc == (P.DC_OK if ok else P.DC_ERR_INVALID_ARG)
+
+
 def test_validate_rejects_negative_count_and_null_list(lib):
     p = P.DcParams(0.55, 0.8)
     assert lib.dc_validate(None, 1, ctypes.byref(p), None) == P.DC_ERR_INVALID_ARG
@@ -174,6 +181,8 @@ def test_compute_calls_reject_null_context(lib):
         P.DC_ERR_INVALID_ARG
     assert lib.dc_decolorize_batch_betas(None, ctypes.byref(d), 1, ctypes.byref(p), None) == \
         P.DC_ERR_INVALID_ARG
+    assert lib.dc_tonemap_local(None, ctypes.byref(d), 1, ctypes.byref(p), None, None, None) == \
+        P.DC_ERR_INVALID_ARG
 
 
 def test_binding_refuses_cpu_tensors():
@@ -184,7 +193,7 @@ def test_binding_refuses_cpu_tensors():
 
 
 def test_server_calls_reject_bad_arguments(lib):
-    cfg = P.DcServerConfig(1 << 20, 8, 2, 0, P.DcParams(0.55, 0.8), P.DcTmParams(1e-4, 2.0, 1e-3, 1.0))
+    cfg = P.DcServerConfig(1 << 20, 8, 2, 0, P.DcParams(0.55, 0.8), P.DcTmParams(1e-4, 2.0, 1e-3, 1.0, 0.5))
     h = ctypes.c_void_p()
     assert lib.dc_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_create(None, ctypes.byref(cfg), None) == P.DC_ERR_INVALID_ARG

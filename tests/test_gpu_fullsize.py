@@ -9,6 +9,8 @@ times: autotuned launch shapes and a HIP-graph plan over resident buffers.
   the oracle's curve evaluated with the oracle's own statistics; the same for
   the re-coloured 8-bit RGB output (s = 1 and s = 0.6) at 16384 sampled pixels
   per image.
+- the same images through the local tone map: T at 8192 sampled pixels per
+  image against the oracle (which still builds every tile's histogram).
 - uneven batch of 256 images (half 8-bit, half binary16, 64..4096 per side),
   one persistent launch: every pixel against the oracle.
 """
@@ -136,6 +138,28 @@ def test_hdr_colour_tonemap_full(dev, s):
     report("hdr colour tone map 16x4096^2 -> u8 RGB, s=%g: %d sampled codes, %d off by one "
            "(fraction %.3e)" % (s, total, off, off / total))
     assert off / total <= 2e-3
+
+
+@pytest.mark.timeout(900)
+def test_hdr_local_tonemap_full(dev):
+    imgs = synth.hdr_images(workers=WORKERS)
+    xs = [to_dev(a, dev) for a in imgs]
+    outs = [torch.empty(a.shape[:2], dtype=torch.float32, device=dev) for a in imgs]
+    s = torch.cuda.Stream()
+    plan = P.Plan(P.PLAN_LOCAL, xs, outs, graph=True, local_strength=0.5, **TM)
+    with torch.cuda.stream(s):
+        plan.run(s)
+    s.synchronize()
+    plan.close()
+    rng = np.random.default_rng(97)
+    worst = 0.0
+    for i, img in enumerate(imgs):
+        idx = rng.integers(0, img.shape[0] * img.shape[1], 8192)
+        want, _ = oracle.tonemap_local(img, strength=0.5, nthreads=WORKERS, sample=idx, **TM)
+        got = outs[i].view(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - want))))
+    report("hdr local tone map 16x4096^2: max |dT| %.2e (8192 sampled px per image)" % worst)
+    assert worst <= 1e-5
 
 
 @pytest.mark.timeout(900)

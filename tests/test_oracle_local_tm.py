@@ -122,3 +122,12 @@ def test_twin_agrees(oracle_mod, dtype):
 def test_rejects_bad_strength(oracle_mod):
     with pytest.raises(ValueError):
         oracle_mod.tonemap_local(synth.random_image(46, 2, 2, np.uint8), strength=1.5)
+
+
+def test_sampled_evaluation_matches_full(oracle_mod):
+    img = synth.hdr_pixels(np.random.default_rng(47), 150, 230)
+    full, st = oracle_mod.tonemap_local(img, strength=0.6, nthreads=3, **TM)
+    idx = np.random.default_rng(48).integers(0, full.size, 500)
+    part, st2 = oracle_mod.tonemap_local(img, strength=0.6, sample=idx, **TM)
+    np.testing.assert_array_equal(part, full.ravel()[idx])
+    assert st == st2
