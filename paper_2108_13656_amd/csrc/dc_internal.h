@@ -71,6 +71,7 @@ struct DevImage {
     int32_t rgb_out;        // tone map: dst holds 3 channels (re-coloured RGB)
     int32_t width;          // pixels per row (local tone map's 2-D tile walk)
     int32_t height;         // rows
+    int32_t staged;         // local tone map: the FP32 dst carries x2 between passes
     float unit;             // Lhat = L * unit (1/255 for 8-bit input)
     Coef k;                 // per-pixel constants for this image's input type
 };
@@ -135,6 +136,7 @@ hipError_t launch_ltm_pass1(const DevImage *table, const int64_t *tile_end, int 
 hipError_t launch_ltm_tables(const DevImage *table, const int64_t *tile_end, int nimg,
                              int64_t total_tiles, const unsigned *hist, LtmCoef *coef,
                              hipStream_t s);
+// src_dtype 3 selects the staged curve pass (FP32 dst holding x2).
 hipError_t launch_ltm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                             int64_t t0, int64_t t1, int src_dtype, TmArgs tm, const Curve *curves,
                             const LtmCoef *coef, int64_t grid, hipStream_t s);

@@ -1096,7 +1096,9 @@ __device__ __forceinline__ float ltm_u(float x2, float lo2)
 // Statistics pass of the local tone map over one tile: the global statistics
 // partial of each wave (as tm_pass1_tile) and the tile's soft histogram of u
 // (mass 1 - f to bin k, f to bin k + 1, in units of 2^-19, integer LDS atomics,
-// so the histogram does not depend on the order of the adds).
+// so the histogram does not depend on the order of the adds). When the image's
+// output is FP32 the pass also parks x2 = log2(Lhat + eps) there, for the
+// curve pass to read instead of the input (im.staged).
 template <int SRC>
 __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                                Part *__restrict__ parts,
@@ -1122,6 +1124,7 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
         K = __builtin_bit_cast(
             float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, xlog2(l0, im.unit, tm.eps))));
     }
+    const bool staged = im.staged != 0;
     auto add = [&](float l) {
         const float x2 = xlog2(l, im.unit, tm.eps);
         const float d = x2 - K;
@@ -1135,31 +1138,35 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
         const unsigned whi = (unsigned)fmaf(u - (float)k, (float)kLtmOne, 0.5f);
         atomicAdd(&lds_hist[k], kLtmOne - whi);
         atomicAdd(&lds_hist[k + 1], whi);
+        return x2;
     };
     if (r.vec) {
         // all of the thread's unit loads first, then the arithmetic
+        // rows past the image's end (bottom tiles) load the last row again, so
+        // every load is unconditional and all of them are in flight together
         unsigned w[U][3];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
-            if (row < r.bh)
-                load_unit(r.src + row * r.sp + col * 3 * ES, w[i]);
+            load_unit(r.src + min(row, r.bh - 1) * r.sp + col * 3 * ES, w[i]);
         }
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
             if (row < r.bh) {
-                float v[PPU];
+                float v[PPU], x[PPU];
 #pragma unroll
                 for (int j = 0; j < PPU; ++j) {
                     v[j] = lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
                                     chan<SRC>(w[i], 3 * j + 2), im.k);
-                    add(v[j]);
+                    x[j] = add(v[j]);
                 }
                 if (r.dst2)
                     store_unit<PPU, SF, SU>(r.dst2 + row * r.d2p, im.dst2_dtype, col, v, e);
+                if (staged)
+                    store_unit<PPU, false, false>(r.dst + row * r.dp, 2, col, x, e);
             }
         }
     } else {
@@ -1170,9 +1177,11 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
             if (row < r.bh && col < r.bw) {
                 float l;
                 lum_at_px<SRC>(r.src + row * r.sp + col * 3 * ES, im.k, l);
-                add(l);
+                const float x2 = add(l);
                 if (r.dst2)
                     store_px<SF, SU>(r.dst2 + row * r.d2p, im.dst2_dtype, col, l, e);
+                if (staged)
+                    store_px<false, false>(r.dst + row * r.dp, 2, col, x2, e);
             }
         }
     }
@@ -1267,13 +1276,60 @@ __global__ __launch_bounds__(64) void k_ltm_tables(const DevImage *__restrict__ 
     coef[g * kLtmBins + b] = c;
 }
 
-// Curve pass of the local tone map over one tile: the 3 x 3 neighbourhood's
-// curve tables are staged in LDS, then every pixel gets
-//   T = T_g + strength (T_l - T_g),
-// T_g the global curve and T_l the bilinear interpolation, between the four
-// tile centres around the pixel, of those tiles' curves at the pixel's u.
-// Tile centres sit at 64 t + 32 pixels; the interpolation weights are exact
-// multiples of 1/64.
+// Corner indices in the 3 x 3 tile neighbourhood and the weight of the second
+// corner along one axis, for tile-local coordinate p of tile t in a grid of n:
+// the pixel lies between the centres of tiles t - 1 and t (p < 32) or t and
+// t + 1, at distance (p + 1/2) / 64 -/+ 1/2 from the first (exact in FP32);
+// at the grid's edges it takes tile t alone.
+__device__ __forceinline__ void ltm_axis(int p, int t, int n, int &c0, int &c1, float &w)
+{
+    const bool lower = p < kLtmTile / 2;
+    const bool edge = lower ? t == 0 : t == n - 1;
+    c0 = (lower && !edge) ? 0 : 1;
+    c1 = edge ? 1 : c0 + 1;
+    w = edge ? 0.0f : fmaf((float)p + 0.5f, 1.0f / kLtmTile, lower ? 0.5f : -0.5f);
+}
+
+// Stages the curve tables of tile (tx, ty)'s 3 x 3 neighbourhood in LDS
+// (entries of tiles outside the grid are left unset and never read).
+__device__ __forceinline__ void ltm_stage(const DevImage &im, const LtmRef &r,
+                                          const LtmCoef *__restrict__ coef, LtmCoef *lds)
+{
+    for (int idx = threadIdx.x; idx < 9 * kLtmBins; idx += kBlock) {
+        const int nb = idx / kLtmBins, bin = idx - nb * kLtmBins;
+        const int sx = r.tx + nb % 3 - 1, sy = r.ty + nb / 3 - 1;
+        if (sx >= 0 && sx < r.nx && sy >= 0 && sy < r.ny)
+            lds[idx] = coef[(im.tile_begin + (int64_t)sy * r.nx + sx) * kLtmBins + bin];
+    }
+    __syncthreads();
+}
+
+// T of one pixel from its x2 = log2(Lhat + eps): the global curve T_g, the
+// bilinear blend T_l of the four corner tiles' curves at u, and
+// T = T_g + strength (T_l - T_g). cy0/cy1/wy: the row's axis; cx0/cx1/wx:
+// the column's.
+__device__ __forceinline__ float ltm_value(float x2, float lo2, TmArgs tm, Curve cv,
+                                           const LtmCoef *lds, int cx0, int cx1, float wx,
+                                           int cy0, int cy1, float wy)
+{
+    const float tg = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
+    const float u = ltm_u(x2, lo2);
+    const int k = min((int)u, kLtmBins - 2);
+    const float f = u - (float)k;
+    auto F = [&](int cx, int cy) {
+        const LtmCoef c = lds[(cy * 3 + cx) * kLtmBins + k];
+        return fmaf(f, fmaf(f, c.c, c.b), c.a);
+    };
+    const float f00 = F(cx0, cy0), f10 = F(cx1, cy0), f01 = F(cx0, cy1), f11 = F(cx1, cy1);
+    const float top = fmaf(wx, f10 - f00, f00);
+    const float bot = fmaf(wx, f11 - f01, f01);
+    const float tl = fmaf(wy, bot - top, top);
+    return fmaf(tm.strength, tl - tg, tg);
+}
+
+// Curve pass of the local tone map over one tile, recomputing L from the
+// input: the 3 x 3 neighbourhood's curve tables are staged in LDS, then every
+// pixel gets ltm_value. Tile centres sit at 64 t + 32 pixels.
 template <int SRC>
 __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                                Curve cv, const LtmCoef *__restrict__ coef,
@@ -1285,74 +1341,46 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
     const LtmRef r = ltm_ref(im, tile);
     const Enc e{1.0f, 255.0f};
     const float lo2 = hw_log2(tm.eps);
-    for (int idx = threadIdx.x; idx < 9 * kLtmBins; idx += kBlock) {
-        const int nb = idx / kLtmBins, bin = idx - nb * kLtmBins;
-        const int sx = r.tx + nb % 3 - 1, sy = r.ty + nb / 3 - 1;
-        if (sx >= 0 && sx < r.nx && sy >= 0 && sy < r.ny)
-            lds[idx] = coef[(im.tile_begin + (int64_t)sy * r.nx + sx) * kLtmBins + bin];
-    }
-    __syncthreads();
-    // Interpolation corner (neighbourhood index 0..2) and weight along one axis
-    // for the pixel at tile-local position p of tile t in a grid of n tiles.
-    auto axis = [](int p, int t, int n, int &c0, int &c1, float &w) {
-        const float g = ((float)(t * kLtmTile + p) + 0.5f) * (1.0f / kLtmTile) - 0.5f;
-        int a = (int)floorf(g);
-        w = g - (float)a;
-        if (a < 0) {
-            a = 0;
-            w = 0.0f;
-        }
-        if (a >= n - 1) {
-            a = n - 1;
-            w = 0.0f;
-        }
-        const int b = min(a + 1, n - 1);
-        c0 = a - t + 1;
-        c1 = b - t + 1;
-    };
-    auto value = [&](float l, int row, int col) {
-        const float x2 = xlog2(l, im.unit, tm.eps);
-        const float tg = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
-        const float u = ltm_u(x2, lo2);
-        const int k = min((int)u, kLtmBins - 2);
-        const float f = u - (float)k;
-        int cx0, cx1, cy0, cy1;
-        float wx, wy;
-        axis(col, r.tx, r.nx, cx0, cx1, wx);
-        axis(row, r.ty, r.ny, cy0, cy1, wy);
-        auto F = [&](int cx, int cy) {
-            const LtmCoef c = lds[(cy * 3 + cx) * kLtmBins + k];
-            return fmaf(f, fmaf(f, c.c, c.b), c.a);
-        };
-        const float top = fmaf(wx, F(cx1, cy0) - F(cx0, cy0), F(cx0, cy0));
-        const float bot = fmaf(wx, F(cx1, cy1) - F(cx0, cy1), F(cx0, cy1));
-        const float tl = fmaf(wy, bot - top, top);
-        return fmaf(tm.strength, tl - tg, tg);
-    };
     if (r.vec) {
+        // rows past the image's end (bottom tiles) load the last row again, so
+        // every load is unconditional and all of them are in flight together,
+        // also while the curve tables are being staged
         unsigned w[U][3];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
-            if (row < r.bh)
-                load_unit(r.src + row * r.sp + col * 3 * ES, w[i]);
+            load_unit(r.src + min(row, r.bh - 1) * r.sp + col * 3 * ES, w[i]);
         }
+        ltm_stage(im, r, coef, lds);
+        int col0, row0;
+        ltm_slot<PPU>(0, 0, row0, col0);
+        int cx0[PPU], cx1[PPU];
+        float wx[PPU];
+#pragma unroll
+        for (int j = 0; j < PPU; ++j)
+            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], cx1[j], wx[j]);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
             if (row < r.bh) {
+                int cy0, cy1;
+                float wy;
+                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
                 float v[PPU];
 #pragma unroll
-                for (int j = 0; j < PPU; ++j)
-                    v[j] = value(lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
-                                          chan<SRC>(w[i], 3 * j + 2), im.k),
-                                 row, col + j);
+                for (int j = 0; j < PPU; ++j) {
+                    const float l = lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
+                                             chan<SRC>(w[i], 3 * j + 2), im.k);
+                    v[j] = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j], cx1[j],
+                                     wx[j], cy0, cy1, wy);
+                }
                 store_unit<PPU, false, true>(r.dst + row * r.dp, im.dst_dtype, col, v, e);
             }
         }
     } else {
+        ltm_stage(im, r, coef, lds);
 #pragma unroll 1
         for (int sl = 0; sl < kStatsPxPerThread; ++sl) {
             int row, col;
@@ -1360,13 +1388,90 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
             if (row < r.bh && col < r.bw) {
                 float l;
                 lum_at_px<SRC>(r.src + row * r.sp + col * 3 * ES, im.k, l);
-                store_px<false, true>(r.dst + row * r.dp, im.dst_dtype, col, value(l, row, col), e);
+                int cx0, cx1, cy0, cy1;
+                float wx, wy;
+                ltm_axis(col, r.tx, r.nx, cx0, cx1, wx);
+                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                store_px<false, true>(r.dst + row * r.dp, im.dst_dtype, col,
+                                      ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0,
+                                                cx1, wx, cy0, cy1, wy),
+                                      e);
             }
         }
     }
     __syncthreads();
 }
 
+// Curve pass over one tile of an image whose FP32 output holds x2 from the
+// statistics pass: reads x2 (4 pixels per 16-byte unit) and overwrites it with
+// T; the input is not touched.
+__device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_t tile, TmArgs tm,
+                                                      Curve cv, const LtmCoef *__restrict__ coef,
+                                                      LtmCoef *lds)
+{
+    constexpr int PPU = 4;
+    constexpr int U = kStatsPxPerThread / PPU;
+    const LtmRef r = ltm_ref(im, tile);
+    const float lo2 = hw_log2(tm.eps);
+    if (r.vec) {
+        float w[U][PPU];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            const u32x4 t = *gp<u32x4>(r.dst + min(row, r.bh - 1) * r.dp + col * 4);
+            // Elements go through plain scalars first: hipcc's
+            // __builtin_bit_cast applied directly to a vector element (t.y)
+            // reads element 0.
+            const unsigned e[PPU] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int j = 0; j < PPU; ++j)
+                w[i][j] = __builtin_bit_cast(float, e[j]);
+        }
+        ltm_stage(im, r, coef, lds);
+        int col0, row0;
+        ltm_slot<PPU>(0, 0, row0, col0);
+        int cx0[PPU], cx1[PPU];
+        float wx[PPU];
+#pragma unroll
+        for (int j = 0; j < PPU; ++j)
+            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], cx1[j], wx[j]);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            if (row < r.bh) {
+                int cy0, cy1;
+                float wy;
+                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                unsigned o[PPU];
+#pragma unroll
+                for (int j = 0; j < PPU; ++j)
+                    o[j] = __builtin_bit_cast(unsigned, ltm_value(w[i][j], lo2, tm, cv, lds, cx0[j],
+                                                                  cx1[j], wx[j], cy0, cy1, wy));
+                *gpw<u32x4>(r.dst + row * r.dp + col * 4) = u32x4{o[0], o[1], o[2], o[3]};
+            }
+        }
+    } else {
+        ltm_stage(im, r, coef, lds);
+#pragma unroll 1
+        for (int sl = 0; sl < kStatsPxPerThread; ++sl) {
+            int row, col;
+            ltm_slot<PPU>(sl / PPU, sl % PPU, row, col);
+            if (row < r.bh && col < r.bw) {
+                DC_GLOBAL float *p = gpw<float>(r.dst + row * r.dp) + col;
+                int cx0, cx1, cy0, cy1;
+                float wx, wy;
+                ltm_axis(col, r.tx, r.nx, cx0, cx1, wx);
+                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                *p = ltm_value(*p, lo2, tm, cv, lds, cx0, cx1, wx, cy0, cy1, wy);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// SRC 3 = the staged form (FP32 output holding x2), whatever the input type.
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict__ table,
                                                       const int64_t *__restrict__ tile_end,
@@ -1377,7 +1482,10 @@ __global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict
     __shared__ LtmCoef lds[9 * kLtmBins];
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
-        ltm_pass2_tile<SRC>(im, tile - im.tile_begin, tm, curves[i], coef, lds);
+        if constexpr (SRC == 3)
+            ltm_pass2_staged_tile(im, tile - im.tile_begin, tm, curves[i], coef, lds);
+        else
+            ltm_pass2_tile<SRC>(im, tile - im.tile_begin, tm, curves[i], coef, lds);
     });
 }
 
@@ -1572,8 +1680,10 @@ hipError_t launch_ltm_pass2(const DevImage *table, const int64_t *tile_end, int 
         DC_LAUNCH_L2(0);
     else if (src_dtype == 1)
         DC_LAUNCH_L2(1);
-    else
+    else if (src_dtype == 2)
         DC_LAUNCH_L2(2);
+    else
+        DC_LAUNCH_L2(3);
 #undef DC_LAUNCH_L2
     return hipGetLastError();
 }

@@ -267,6 +267,7 @@ dc::DevImage describe_local(const dc_image &m, int index, const dc_params *param
     const bool out16 = (uintptr_t)m.dst % 16 == 0 && m.dst_pitch % 16 == 0 &&
                        (!m.dst2 || ((uintptr_t)m.dst2 % 16 == 0 && m.dst2_pitch % 16 == 0));
     d.walk = (src4 && out16) ? dc::kWalkRows : dc::kWalkScalar;
+    d.staged = m.dst_dtype == DC_F32 ? 1 : 0;
     return d;
 }
 
@@ -366,7 +367,7 @@ struct HostTable {
     // colour output} of each run, so each pass launches its per-type kernel
     // once per run.
     struct Run {
-        int img0, img1, src, rgb;
+        int img0, img1, src, rgb, staged;
     };
     std::vector<Run> runs;
 };
@@ -397,7 +398,11 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
         order[i] = i;
     if (kind != kTabDecolor)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            const int ra = imgs[a].flags & DC_IMG_RGB_OUT, rb = imgs[b].flags & DC_IMG_RGB_OUT;
+            // second key: colour output (tone map) or FP32 staging (local tone map)
+            const int ra = kind == kTabLocal ? imgs[a].dst_dtype == DC_F32
+                                             : imgs[a].flags & DC_IMG_RGB_OUT;
+            const int rb = kind == kTabLocal ? imgs[b].dst_dtype == DC_F32
+                                             : imgs[b].flags & DC_IMG_RGB_OUT;
             return imgs[a].src_dtype != imgs[b].src_dtype ? imgs[a].src_dtype < imgs[b].src_dtype
                                                           : ra < rb;
         });
@@ -412,9 +417,10 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
         const dc_params *pp = per_image ? &per_image[order[i]] : params;
         h.d[i] = kind == kTabLocal ? describe_local(m, order[i], pp)
                                    : describe(m, order[i], tile_px, pp);
-        const int rgb = h.d[i].rgb_out;
-        if (h.runs.empty() || h.runs.back().src != m.src_dtype || h.runs.back().rgb != rgb)
-            h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype, rgb});
+        const int rgb = h.d[i].rgb_out, staged = h.d[i].staged;
+        if (h.runs.empty() || h.runs.back().src != m.src_dtype || h.runs.back().rgb != rgb ||
+            h.runs.back().staged != staged)
+            h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype, rgb, staged});
         else
             h.runs.back().img1 = i + 1;
         h.d[i].tile_begin = total;
@@ -605,8 +611,9 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
 
 // Kernel sequence of the local tone map over a staged table: per input-type
 // run the statistics-and-histogram pass over 64 x 64 tiles, the two-level
-// statistics combine, the per-tile curve tables, then per run the curve pass.
-// One workgroup per tile in both passes.
+// statistics combine, the per-tile curve tables, then per run the curve pass
+// (for images with an FP32 output, the form that reads back the x2 the first
+// pass parked in that output instead of the input). One workgroup per tile.
 int enqueue_local(dc_ctx *ctx, const HostTable &h, const DevBufs &b, dc::TmArgs a,
                   dc::StatsOut *stats, hipStream_t st, bool marks)
 {
@@ -630,8 +637,8 @@ int enqueue_local(dc_ctx *ctx, const HostTable &h, const DevBufs &b, dc::TmArgs 
     for (const auto &r : h.runs) {
         const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
         if (e == hipSuccess)
-            e = dc::launch_ltm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, r.src, a,
-                                     b.curves, b.coef, 0, st);
+            e = dc::launch_ltm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1,
+                                     r.staged ? 3 : r.src, a, b.curves, b.coef, 0, st);
     }
     mark(ctx, marks, 3, st);
     if (e != hipSuccess)
