@@ -1290,16 +1290,24 @@ __device__ __forceinline__ void ltm_axis(int p, int t, int n, int &c0, int &c1, 
     w = edge ? 0.0f : fmaf((float)p + 0.5f, 1.0f / kLtmTile, lower ? 0.5f : -0.5f);
 }
 
+// A bin's quadratic as staged in LDS: 3 words, so consecutive bins are 3
+// banks apart and lanes looking up different bins rarely share a bank.
+struct LtmLds {
+    float a, b, c;
+};
+
 // Stages the curve tables of tile (tx, ty)'s 3 x 3 neighbourhood in LDS
 // (entries of tiles outside the grid are left unset and never read).
 __device__ __forceinline__ void ltm_stage(const DevImage &im, const LtmRef &r,
-                                          const LtmCoef *__restrict__ coef, LtmCoef *lds)
+                                          const LtmCoef *__restrict__ coef, LtmLds *lds)
 {
     for (int idx = threadIdx.x; idx < 9 * kLtmBins; idx += kBlock) {
         const int nb = idx / kLtmBins, bin = idx - nb * kLtmBins;
         const int sx = r.tx + nb % 3 - 1, sy = r.ty + nb / 3 - 1;
-        if (sx >= 0 && sx < r.nx && sy >= 0 && sy < r.ny)
-            lds[idx] = coef[(im.tile_begin + (int64_t)sy * r.nx + sx) * kLtmBins + bin];
+        if (sx >= 0 && sx < r.nx && sy >= 0 && sy < r.ny) {
+            const LtmCoef c = coef[(im.tile_begin + (int64_t)sy * r.nx + sx) * kLtmBins + bin];
+            lds[idx] = LtmLds{c.a, c.b, c.c};
+        }
     }
     __syncthreads();
 }
@@ -1309,7 +1317,7 @@ __device__ __forceinline__ void ltm_stage(const DevImage &im, const LtmRef &r,
 // T = T_g + strength (T_l - T_g). cy0/cy1/wy: the row's axis; cx0/cx1/wx:
 // the column's.
 __device__ __forceinline__ float ltm_value(float x2, float lo2, TmArgs tm, Curve cv,
-                                           const LtmCoef *lds, int cx0, int cx1, float wx,
+                                           const LtmLds *lds, int cx0, int cx1, float wx,
                                            int cy0, int cy1, float wy)
 {
     const float tg = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
@@ -1317,7 +1325,7 @@ __device__ __forceinline__ float ltm_value(float x2, float lo2, TmArgs tm, Curve
     const int k = min((int)u, kLtmBins - 2);
     const float f = u - (float)k;
     auto F = [&](int cx, int cy) {
-        const LtmCoef c = lds[(cy * 3 + cx) * kLtmBins + k];
+        const LtmLds c = lds[(cy * 3 + cx) * kLtmBins + k];
         return fmaf(f, fmaf(f, c.c, c.b), c.a);
     };
     const float f00 = F(cx0, cy0), f10 = F(cx1, cy0), f01 = F(cx0, cy1), f11 = F(cx1, cy1);
@@ -1333,7 +1341,7 @@ __device__ __forceinline__ float ltm_value(float x2, float lo2, TmArgs tm, Curve
 template <int SRC>
 __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                                Curve cv, const LtmCoef *__restrict__ coef,
-                                               LtmCoef *lds)
+                                               LtmLds *lds)
 {
     constexpr int PPU = unit_px(SRC);
     constexpr int U = kStatsPxPerThread / PPU;
@@ -1407,7 +1415,7 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
 // T; the input is not touched.
 __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                                       Curve cv, const LtmCoef *__restrict__ coef,
-                                                      LtmCoef *lds)
+                                                      LtmLds *lds)
 {
     constexpr int PPU = 4;
     constexpr int U = kStatsPxPerThread / PPU;
@@ -1479,7 +1487,7 @@ __global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict
                                                       TmArgs tm, const Curve *__restrict__ curves,
                                                       const LtmCoef *__restrict__ coef)
 {
-    __shared__ LtmCoef lds[9 * kLtmBins];
+    __shared__ LtmLds lds[9 * kLtmBins];
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         if constexpr (SRC == 3)
