@@ -112,6 +112,10 @@ typedef struct dc_tm_params {
  * element)) instead of the gray T; dst2 keeps its meaning. Other calls reject
  * the flag with DC_ERR_UNSUPPORTED; unknown bits are DC_ERR_INVALID_ARG. */
 #define DC_IMG_RGB_OUT 1
+/* Server requests only: img.src is a HOST pointer (pinned memory, e.g. from
+ * hipHostMalloc, for an asynchronous copy). The server copies the image into
+ * its device budget on the launch lane's stream before the kernels. */
+#define DC_IMG_HOST_SRC 2
 typedef struct dc_image {
     const void *src; /* device, interleaved RGB, row y at src + y * src_pitch */
     void *dst;       /* device, 1 channel */
@@ -300,7 +304,7 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
 typedef struct dc_server dc_server;
 
 typedef struct dc_server_config {
-    int64_t budget_bytes;  /* device bytes for server-allocated outputs, > 0 */
+    int64_t budget_bytes;  /* device bytes for server-allocated outputs and input copies, > 0 */
     int32_t max_batch;     /* images per launch, >= 1 */
     int32_t max_inflight;  /* launch lanes, 1..8 */
     int32_t flags;         /* reserved, 0 */
@@ -308,12 +312,16 @@ typedef struct dc_server_config {
     dc_tm_params tm;       /* tone curve */
 } dc_server_config;
 
-/* One request. img.src (DEVICE), size, src_dtype and dst_dtype as in
- * dc_image; dst2 must be NULL (dst2_dtype DC_NONE). With img.dst NULL the
- * server allocates the output (rows padded to 16 bytes) from its budget and
- * frees it when the request completes (the output is not kept); with img.dst
- * set (caller memory, dst_pitch given) the output stays there and takes no
- * budget. */
+/* One request. img.src (DEVICE, or HOST with DC_IMG_HOST_SRC), size,
+ * src_dtype and dst_dtype as in dc_image; dst2 must be NULL (dst2_dtype
+ * DC_NONE); flags may hold DC_IMG_RGB_OUT and DC_IMG_HOST_SRC. With img.dst
+ * NULL the server allocates the output (rows packed) from its budget and frees
+ * it when the request completes (the output is not kept); with img.dst set
+ * (caller memory, dst_pitch given) the output stays there and takes no budget.
+ * A host input takes budget for its device copy (rows packed) until the
+ * request completes; the host memory must stay valid until then. Packed host
+ * rows (src_pitch = 3 * width * element size) go over in one linear copy;
+ * pitched ones take hipMemcpy2DAsync, which is much slower. */
 typedef struct dc_request {
     int64_t id;
     dc_image img;

@@ -32,6 +32,7 @@ BETA_K = 0.80  # Eq. (6) weight
 TM_EPS, TM_CONTRAST, TM_SIGMA_FLOOR, TM_SATURATION = 1e-4, 2.0, 1e-3, 1.0
 TM_LOCAL_STRENGTH = 0.5
 DC_IMG_RGB_OUT = 1  # dc_image.flags: tone-map dst holds re-coloured RGB
+DC_IMG_HOST_SRC = 2  # dc_image.flags, server requests: src is pinned host memory
 
 
 class DcImage(ctypes.Structure):
@@ -526,12 +527,21 @@ def make_request(rid, src, src_dtype, width, height, src_pitch, dst_dtype, dst=N
 
 
 def request_for(rid, x, out=None, out_dtype=torch.float32, colour=False):
-    """A DcRequest for an HxWx3 device tensor (and an optional HxW, or with
-    colour HxWx3, output)."""
-    _check_rgb(x)
-    flags = DC_IMG_RGB_OUT if colour else 0
+    """A DcRequest for an HxWx3 tensor (and an optional HxW, or with colour
+    HxWx3, device output). x is a device tensor, or a pinned host tensor that
+    the server copies to the device itself."""
+    host = isinstance(x, torch.Tensor) and not x.is_cuda
+    if host:
+        if not x.is_pinned():
+            raise ValueError("host inputs must be pinned (pin_memory=True)")
+        if x.dim() != 3 or x.shape[2] != 3 or x.stride(2) != 1 or x.stride(1) != 3:
+            raise ValueError("expected an HxWx3 interleaved RGB tensor")
+    else:
+        _check_rgb(x)
+    flags = (DC_IMG_RGB_OUT if colour else 0) | (DC_IMG_HOST_SRC if host else 0)
     if out is not None:
-        flags = _check_out(out, x.shape[0], x.shape[1], x.device)
+        flags = _check_out(out, x.shape[0], x.shape[1], out.device) | (
+            DC_IMG_HOST_SRC if host else 0)
     return make_request(rid, x.data_ptr(), _dc_dtype(x.dtype), x.shape[1], x.shape[0],
                         x.stride(0) * x.element_size(),
                         _dc_dtype(out.dtype if out is not None else out_dtype),

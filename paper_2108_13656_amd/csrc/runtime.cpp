@@ -95,8 +95,10 @@ int check_src(const dc_image &m, const std::string &at, Range &r)
     return DC_OK;
 }
 
-// rgb_ok: the call is a tone map, so DC_IMG_RGB_OUT (3-channel dst) is allowed.
-int validate_images(const dc_image *imgs, int32_t n, bool rgb_ok)
+// allowed: the dc_image flags this call accepts (DC_IMG_RGB_OUT for the tone
+// map, DC_IMG_HOST_SRC for server requests); other known flags are
+// DC_ERR_UNSUPPORTED, unknown bits DC_ERR_INVALID_ARG.
+int validate_images(const dc_image *imgs, int32_t n, int32_t allowed)
 {
     if (n < 0)
         return fail(DC_ERR_INVALID_ARG, "n must be >= 0");
@@ -112,10 +114,12 @@ int validate_images(const dc_image *imgs, int32_t n, bool rgb_ok)
             return fail(DC_ERR_INVALID_ARG, "src and dst must not be NULL" + at);
         if (m.width < 1 || m.height < 1)
             return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + at);
-        if (m.flags & ~DC_IMG_RGB_OUT)
+        if (m.flags & ~(DC_IMG_RGB_OUT | DC_IMG_HOST_SRC))
             return fail(DC_ERR_INVALID_ARG, "unknown flags" + at);
-        if ((m.flags & DC_IMG_RGB_OUT) && !rgb_ok)
+        if ((m.flags & DC_IMG_RGB_OUT) && !(allowed & DC_IMG_RGB_OUT))
             return fail(DC_ERR_UNSUPPORTED, "DC_IMG_RGB_OUT applies to the tone map only" + at);
+        if ((m.flags & DC_IMG_HOST_SRC) && !(allowed & DC_IMG_HOST_SRC))
+            return fail(DC_ERR_UNSUPPORTED, "DC_IMG_HOST_SRC applies to server requests only" + at);
         if (!dtype_ok(m.src_dtype) || !dtype_ok(m.dst_dtype))
             return fail(DC_ERR_INVALID_ARG, "src_dtype and dst_dtype must be DC_U8, DC_F16 or DC_F32" + at);
         if (m.dst2_dtype == DC_NONE) {
@@ -897,7 +901,7 @@ int dc_validate(const dc_image *imgs, int32_t n, const dc_params *params, const 
     if (rc == DC_OK)
         rc = validate_tm(tm);
     if (rc == DC_OK)
-        rc = validate_images(imgs, n, tm != nullptr);
+        rc = validate_images(imgs, n, tm != nullptr ? DC_IMG_RGB_OUT : 0);
     return rc;
 }
 
@@ -1383,7 +1387,8 @@ struct dc_server {
     struct Req {
         dc_request r;
         double t_submit = 0, t_admit = 0, t_launch = 0;
-        size_t off = 0, bytes = 0;
+        size_t off = 0, bytes = 0; // budget block: [input copy | output]
+        size_t in_bytes = 0;       // bytes of the input copy (host inputs)
         bool owned = false;
     };
     struct Lane {
@@ -1456,6 +1461,14 @@ size_t out_bytes(const dc_image &m, int64_t *pitch)
     return (b + kGranule - 1) / kGranule * kGranule;
 }
 
+// Bytes of the device copy of a host input (rows packed), granule-rounded.
+size_t in_bytes(const dc_image &m, int64_t *pitch)
+{
+    *pitch = 3 * dc::elem_size(m.src_dtype) * m.width;
+    const size_t b = (size_t)*pitch * (size_t)m.height;
+    return (b + kGranule - 1) / kGranule * kGranule;
+}
+
 void complete(dc_server *sv, const dc_server::Req &q, int status, int batch, double t_done)
 {
     dc_completion c;
@@ -1490,17 +1503,20 @@ int server_step(dc_server *sv)
         ln.batch.clear();
         ln.busy = false;
     }
-    // 2. admit in FIFO order while outputs fit
+    // 2. admit in FIFO order while inputs copies and outputs fit
     while (!sv->waiting.empty()) {
         dc_server::Req &q = sv->waiting.front();
-        if (q.r.img.dst) {
+        const bool host = (q.r.img.flags & DC_IMG_HOST_SRC) != 0;
+        if (q.r.img.dst && !host) {
             q.t_admit = server_now(sv);
             sv->admitted.push_back(q);
             sv->waiting.pop_front();
             continue;
         }
-        int64_t pitch = 0;
-        const size_t bytes = out_bytes(q.r.img, &pitch);
+        int64_t in_pitch = 0, out_pitch = 0;
+        const size_t ib = host ? in_bytes(q.r.img, &in_pitch) : 0;
+        const size_t ob = q.r.img.dst ? 0 : out_bytes(q.r.img, &out_pitch);
+        const size_t bytes = ib + ob;
         if (bytes > sv->arena_bytes) {
             complete(sv, q, DC_ERR_NO_MEMORY, 0, server_now(sv));
             sv->waiting.pop_front();
@@ -1511,9 +1527,12 @@ int server_step(dc_server *sv)
             break;
         q.off = off;
         q.bytes = bytes;
+        q.in_bytes = ib;
         q.owned = true;
-        q.r.img.dst = sv->arena + off;
-        q.r.img.dst_pitch = pitch;
+        if (!q.r.img.dst) {
+            q.r.img.dst = sv->arena + off + ib;
+            q.r.img.dst_pitch = out_pitch;
+        }
         q.t_admit = server_now(sv);
         sv->admitted.push_back(q);
         sv->waiting.pop_front();
@@ -1530,8 +1549,29 @@ int server_step(dc_server *sv)
         for (size_t i = 0; i < k; ++i) {
             ln.batch.push_back(sv->admitted.front());
             sv->admitted.pop_front();
-            ln.batch.back().t_launch = t;
-            imgs[i] = ln.batch.back().r.img;
+            dc_server::Req &q = ln.batch.back();
+            q.t_launch = t;
+            imgs[i] = q.r.img;
+            if (q.r.img.flags & DC_IMG_HOST_SRC) {
+                // the input's device copy, packed, at the start of its block
+                int64_t pitch = 0;
+                (void)in_bytes(q.r.img, &pitch);
+                char *d = sv->arena + q.off;
+                const size_t rows = (size_t)q.r.img.height;
+                // one linear copy when the host rows are packed too
+                const hipError_t ce =
+                    q.r.img.src_pitch == pitch
+                        ? hipMemcpyAsync(d, q.r.img.src, (size_t)pitch * rows,
+                                         hipMemcpyHostToDevice, ln.s)
+                        : hipMemcpy2DAsync(d, (size_t)pitch, q.r.img.src,
+                                           (size_t)q.r.img.src_pitch, (size_t)pitch, rows,
+                                           hipMemcpyHostToDevice, ln.s);
+                if (ce != hipSuccess)
+                    return hip_fail(ce, "host input copy");
+                imgs[i].src = d;
+                imgs[i].src_pitch = pitch;
+                imgs[i].flags &= ~DC_IMG_HOST_SRC;
+            }
         }
         HostTable h;
         build_table(imgs.data(), (int32_t)k, &sv->cfg.params, kTabTonemap, sv->ctx->tune, h);
@@ -1633,11 +1673,11 @@ int dc_server_submit(dc_server *sv, const dc_request *reqs, int32_t n, double t_
         if (rc != DC_OK)
             return rc;
         if (!dtype_ok(m.dst_dtype) || m.dst2 || m.dst2_dtype != DC_NONE ||
-            (m.flags & ~DC_IMG_RGB_OUT))
-            return fail(DC_ERR_INVALID_ARG,
-                        "dst_dtype must be set; dst2 must be absent; flags 0 or DC_IMG_RGB_OUT" + at);
+            (m.flags & ~(DC_IMG_RGB_OUT | DC_IMG_HOST_SRC)))
+            return fail(DC_ERR_INVALID_ARG, "dst_dtype must be set; dst2 must be absent; flags "
+                                            "DC_IMG_RGB_OUT and DC_IMG_HOST_SRC only" + at);
         if (m.dst) {
-            rc = validate_images(&m, 1, true);
+            rc = validate_images(&m, 1, DC_IMG_RGB_OUT | DC_IMG_HOST_SRC);
             if (rc != DC_OK)
                 return rc;
         }

@@ -75,7 +75,7 @@ def test_validate_accepts_good_images(lib):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(src=None), dict(dst=None), dict(width=0), dict(height=-1), dict(flags=2),
+    dict(src=None), dict(dst=None), dict(width=0), dict(height=-1), dict(flags=8),
     dict(src_dtype=3), dict(dst_dtype=-1), dict(dst2_dtype=7, dst2=0x30000000, dst2_pitch=40),
     dict(dst2=0x30000000), dict(dst2_dtype=P.DC_F32), dict(src_pitch=29), dict(dst_pitch=39),
     dict(src_dtype=P.DC_F16, src_pitch=59), dict(src_dtype=P.DC_F32, src=0x10000002, src_pitch=120),
@@ -110,6 +110,9 @@ def test_colour_output_flag(lib):
         P.DC_ERR_INVALID_ARG
     assert P.validate([_img(flags=P.DC_IMG_RGB_OUT | 4, dst_pitch=120)], tm=TM) == \
         P.DC_ERR_INVALID_ARG
+    # host inputs are for server requests only
+    assert P.validate([_img(flags=P.DC_IMG_HOST_SRC)], tm=TM) == P.DC_ERR_UNSUPPORTED
+    assert P.validate([_img(flags=P.DC_IMG_HOST_SRC)]) == P.DC_ERR_UNSUPPORTED
     # the 3-channel extent (3 * 120 + 120 = 480 bytes) counts for aliasing
     assert P.validate([_img(**rgb), _img(src=0x40000000, dst=0x20000000 + 480)], tm=TM) == P.DC_OK
     assert P.validate([_img(**rgb), _img(src=0x40000000, dst=0x20000000 + 476)], tm=TM) == \

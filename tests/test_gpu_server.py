@@ -119,3 +119,37 @@ def test_colour_requests_in_mix(dev):
     for i, (x, o) in enumerate(zip(xs, outs)):
         alone, _, _ = P.tonemap_global([x], o.dtype, colour=o.dim() == 3, saturation=0.7)
         assert torch.equal(alone[0], o), i
+
+
+def test_host_input_requests(dev):
+    """Requests whose inputs are pinned host tensors (DC_IMG_HOST_SRC): the
+    server copies each into its budget before the kernels; results equal the
+    device-input tone map bit for bit, alone and mixed with device inputs."""
+    xs, outs = _mixed_requests(dev, 20, 7)
+    hosts = [x.cpu().pin_memory() if i % 2 == 0 else x for i, x in enumerate(xs)]
+    srv = P.Server(budget_bytes=64 << 20, max_batch=8, max_inflight=3)
+    srv.submit([P.request_for(i, h, o) for i, (h, o) in enumerate(zip(hosts, outs))])
+    done = []
+    while len(done) < len(xs):
+        srv.step()
+        done += srv.poll()
+    srv.close()
+    torch.cuda.synchronize()
+    assert all(c.status == P.DC_OK for c in done)
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        alone, _, _ = P.tonemap_global([x], o.dtype)
+        assert torch.equal(alone[0], o), i
+
+
+def test_host_input_budget_counts_the_copy(dev):
+    """An input copy larger than the whole budget is rejected at once."""
+    x = torch.zeros((512, 512, 3), dtype=torch.float16).pin_memory()
+    out = torch.empty((512, 512), device=dev)
+    srv = P.Server(budget_bytes=1 << 20, max_batch=4, max_inflight=1)
+    srv.submit([P.request_for(0, x, out)])
+    done = []
+    while not done:
+        srv.step()
+        done += srv.poll()
+    srv.close()
+    assert done[0].status == P.DC_ERR_NO_MEMORY
