@@ -1,14 +1,17 @@
 // HIP kernels (gfx950) of the colour-temperature decolorization, Eqs. (1)-(6)
-// of Ambalathankandy et al. (arXiv 2108.13656, Sec. II-B), and of the global
-// tone map on its luminance (Sec. III-B.1, read as a centred sigmoid in the log
-// domain, slope normalised by the image's standard deviation).
+// of Ambalathankandy et al. (arXiv 2108.13656, Sec. II-B), and of the tone
+// mapping built on its luminance: the global map (Sec. III-B.1, read as a
+// centred sigmoid in the log domain, slope normalised by the image's standard
+// deviation) with gray or re-coloured output, and the local map (Sec. III-B.2,
+// smoothed local histogram equalisation on a tile grid). Also the comparator
+// gray channels (rgb2gray Y, V of HSV, CIE L*) on the same data path.
 //
 // The work is an elementwise stream bounded by HBM bandwidth, so there is no
-// MFMA here: each thread owns whole 48-byte groups of interleaved RGB (16 px
-// of u8, 8 of f16, 4 of f32), loads them with three 16-byte loads, decodes
-// them in registers, evaluates the luminance in FP32 with the hardware
-// square-root / reciprocal-square-root / reciprocal instructions, and writes
-// its outputs with 4-16 byte stores.
+// MFMA here: each lane owns 12-byte work units of interleaved RGB (4 px of u8,
+// 2 of f16, 1 of f32), loaded with one dwordx3 each so that a wave's lanes read
+// contiguous memory, decodes them in registers, evaluates the luminance in FP32
+// with the hardware square-root / reciprocal-square-root / reciprocal
+// instructions, and writes its outputs with 1-16 byte stores.
 #include "dc_internal.h"
 
 namespace dc {

@@ -1,6 +1,8 @@
 // Host runtime behind include/decolor.h: argument validation, the context and
-// its workspace ring, the per-image walk classification and tile tables, and
-// the launch sequences of the three compute entry points.
+// its workspace ring, the per-image walk classification and tile tables, the
+// launch sequences of the compute entry points (decolorization, weight sweep,
+// comparator channels, global and local tone map), plans with HIP-graph
+// capture, the autotuner and the continuous-batching server.
 #include "../../include/decolor.h"
 #include "dc_internal.h"
 
