@@ -39,12 +39,12 @@ enum Walk : int32_t {
 };
 
 // Per-pixel coefficients of Eqs. (3) and (6), in the scaling the input's
-// per-pixel form expects (see lum_code / lum_linear).
+// per-pixel form expects (see lum_code / lum_half / lum_linear).
 struct Coef {
-    float cr; // beta_R        (x3 for 8-bit input)
-    float cg; // 1 - beta_R    (x3 for 8-bit input)
-    float ck; // beta_k        (/3 for 8-bit input)
-    float cc; // 1 - beta_k    (/3 for 8-bit input)
+    float cr; // beta_R        (x3 for 8-bit and binary16 input)
+    float cg; // 1 - beta_R    (x3 for 8-bit and binary16 input)
+    float ck; // beta_k        (/3 for 8-bit and binary16 input)
+    float cc; // 1 - beta_k    (/3 for 8-bit and binary16 input)
 };
 
 // Device-side descriptor of one image, built by the host runtime.

@@ -53,6 +53,27 @@ __device__ __forceinline__ float lum_code(float R, float G, float B, Coef k)
     return Y * hw_rsq(Y * fmaf(S, S, 1e-6f));
 }
 
+// L for binary16 input: the division-free form of lum_code on the decoded
+// values (the same four constants), finished as sqrt(Y) / S. Binary16 spans
+// 6e-8 .. 65504, so Y stays between about 1e-30 and 5e20 and no intermediate
+// leaves the FP32 normal range; NaN and negative channels read as 0 (max
+// returns the non-NaN operand), and a black pixel gives 0 * (1 / 1e-30) = 0.
+__device__ __forceinline__ float lum_half(float R, float G, float B, Coef k)
+{
+    R = fmaxf(R, 0.0f);
+    G = fmaxf(G, 0.0f);
+    B = fmaxf(B, 0.0f);
+    const float rr = R * R, gg = G * G;
+    const float Q = hw_sqrt(fmaf(B, B, rr + gg));                 // sqrt(3) * Eq. (1)
+    const float Lgr3 = hw_sqrt(fmaf(k.cr, rr, k.cg * gg));        // sqrt(3) * Eq. (3)
+    const float rg = R + G;
+    const float S = rg + B;
+    const float A = fmaf(R, Lgr3, (G + B) * Q);                   // sqrt(3) S * Eq. (4)
+    const float C = B * fmaf(1.73205080756887729f, rg, Q);        // sqrt(3) S * Eq. (5)
+    const float Y = fmaf(k.ck * A, A, k.cc * (C * C));            // S^2 * Eq. (6)^2
+    return hw_sqrt(Y) * hw_rcp(fmaxf(S, 1e-30f));
+}
+
 // L for linear float input. The pixel is first normalised by S, so every
 // intermediate lies in [0, 1] whatever the radiance scale (binary16 spans
 // 6e-8 .. 65504), and L = S * L(r, g, b) by degree-1 homogeneity. NaN and
@@ -79,6 +100,8 @@ __device__ __forceinline__ float lum(float R, float G, float B, Coef k)
 {
     if constexpr (SRC == 0)
         return lum_code(R, G, B, k);
+    else if constexpr (SRC == 1)
+        return lum_half(R, G, B, k);
     else
         return lum_linear(R, G, B, k);
 }

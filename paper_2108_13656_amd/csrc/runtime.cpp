@@ -186,13 +186,14 @@ int validate_images(const dc_image *imgs, int32_t n, int32_t allowed)
     return DC_OK;
 }
 
-// Constants of the two per-pixel forms. The 8-bit form carries sqrt(3) S
-// scaling (cr, cg scaled by 3; ck, cc by 1/3); the linear form uses the plain
-// weights. Computed in double, rounded once.
+// Constants of the per-pixel forms. The division-free form (8-bit and
+// binary16 input) carries sqrt(3) S scaling (cr, cg scaled by 3; ck, cc by
+// 1/3); the normalised form (binary32 input) uses the plain weights. Computed
+// in double, rounded once.
 dc::Coef coef_of(const dc_params *p, int src_dtype)
 {
     const double br = p ? p->beta_r : 0.55, bk = p ? p->beta_k : 0.80;
-    if (src_dtype == DC_U8)
+    if (src_dtype != DC_F32)
         return dc::Coef{(float)(3.0 * br), (float)(3.0 * (1.0 - br)), (float)(bk / 3.0),
                         (float)((1.0 - bk) / 3.0)};
     return dc::Coef{(float)br, (float)(1.0 - br), (float)bk, (float)(1.0 - bk)};
