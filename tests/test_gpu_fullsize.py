@@ -179,3 +179,32 @@ def test_uneven_batch_every_pixel(dev, lut):
     report("uneven batch: %d px, max |dL| u8 %.3e, f16 scaled %.3e" %
            (sum(a.shape[0] * a.shape[1] for a in imgs), worst8, worst16))
     assert worst8 <= 1e-5 and worst16 <= 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_image_larger_than_2gib(dev):
+    """One binary32 image of 14000 x 14000 (2.35 GB of input, byte offsets past
+    2^31): decolorization at sampled pixels and at the last row against the
+    oracle's per-pixel value, and the global tone map's statistics against the
+    oracle over every pixel."""
+    h = w = 14000
+    rng = np.random.default_rng(96)
+    img = rng.random((h, w, 3), dtype=np.float32) * 4.0
+    x = to_dev(img, dev)
+    out = P.decolorize(x)
+    idx = np.concatenate([rng.integers(0, h * w, 4096), np.arange(h * w - w, h * w)])
+    got = out.view(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+    flat = img.reshape(-1, 3)[idx].astype(np.float64)
+    want = np.array([oracle.luminance(*p) for p in flat])
+    err = float(np.max(np.abs(got - want) / np.maximum(1.0, want)))
+    report("14000^2 binary32 decolorize: max scaled error %.3e over %d px" % (err, idx.size))
+    assert err <= 1e-5
+    del out
+    _, _, stats = P.tonemap_global([x], torch.float16, **TM)
+    st = P.stats_to_host(stats)[0]
+    ref = oracle.tonemap_stats(oracle.decolorize(img, nthreads=WORKERS), TM["eps"])
+    report("14000^2 tone map: mu %.7f / %.7f, sigma %.7f / %.7f" %
+           (st["mu"], ref["mu"], st["sigma"], ref["sigma"]))
+    assert st["count"] == h * w
+    assert abs(st["mu"] - ref["mu"]) <= 2e-5 * (1 + abs(ref["mu"]))
+    assert abs(st["sigma"] - ref["sigma"]) <= 2e-5 * ref["sigma"]
