@@ -351,6 +351,30 @@ def main():
                                                 "FP64, one thread" % (k, n_img, size, size)}
             result["parity_sample"] = {"images": k, "max_abs_err_T": worst}
             log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
+            # Eqs. (1)-(6) alone, as in the paper's run-time table: one thread,
+            # and the oracle's row split over the host cores this box gives one
+            # GPU (16).
+            ncores = min(WORKERS, 16)
+            t0 = time.time()
+            oracle.decolorize(imgs[0], nthreads=1)
+            one = size * size / (time.time() - t0) / 1e9
+            t0 = time.time()
+            for i in range(k):
+                oracle.decolorize(imgs[i], nthreads=ncores)
+            allc = k * size * size / (time.time() - t0) / 1e9
+            model = None
+            try:
+                with open("/proc/cpuinfo") as f:
+                    model = next((ln.split(":", 1)[1].strip() for ln in f
+                                  if ln.startswith("model name")), None)
+            except OSError:
+                pass
+            result["cpu_baseline"]["decolorize_only"] = {
+                "one_thread_gpx": round(one, 6), "all_cores_gpx": round(allc, 6),
+                "cores": ncores, "cpu_model": model,
+                "sample": "Eqs. (1)-(6) in FP64 on 1 and %d of the images" % k}
+            log("cpu oracle, decolorization only: %.4f Gpx/s on 1 thread, %.4f on %d (%s)" %
+                (one, allc, ncores, model))
         plan.close()
         plan_ev.close()
         del outs
