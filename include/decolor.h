@@ -262,7 +262,8 @@ int dc_plan_destroy(dc_plan *plan);
  * image by image with the curve pass of one image on a second stream beside the
  * statistics pass of the next. The tone map's statistics chunks are fixed
  * (1024 pixels per partial, merged in a fixed tree), so no setting changes any
- * result bit. */
+ * result bit. The local tone map always runs one workgroup per 64 x 64 tile and
+ * is not tuned. */
 typedef struct dc_tuning {
     int32_t groups[3];
     int32_t mixed_groups;
@@ -284,7 +285,8 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *tuning);
  * place are measured first and a candidate replaces them only when it is more
  * than 2 % faster, so timing noise does not flip between equal shapes) and
  * writes it to *chosen (if not NULL). The candidate runs write the images'
- * outputs. Synchronises `stream`. */
+ * outputs. Synchronises `stream`. kind DC_PLAN_LOCAL is not tuned
+ * (DC_ERR_INVALID_ARG). */
 int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 const dc_params *params, const dc_tm_params *tm, void *stream,
                 dc_tuning *chosen);
@@ -292,8 +294,9 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
 /* -------------------------------------------------------------- serving
  * Continuous-batching server for the global tone map of single-image requests
  * of any size and element type (each request: decolorization + statistics +
- * curve). Requests wait in FIFO order and are admitted when their output fits
- * the server's device-memory budget (a first-fit arena allocated once at
+ * curve). Requests wait in FIFO order and are admitted when their output (and,
+ * for host inputs, the input's device copy) fits the server's device-memory
+ * budget (a first-fit arena allocated once at
  * creation); whenever one of max_inflight launch lanes (each its own stream) is
  * idle, every admitted request, up to max_batch, goes into one launch on it;
  * when a launch's completion event fires its requests complete and their
