@@ -114,22 +114,25 @@ def video_frames(seed=VIDEO_SEED, count=64, workers=1):
 
 # --------------------------------------------------------------- workload 3
 
-def hdr_pixels(rng, h, w):
+def hdr_pixels(rng, h, w, exact=False):
     """h x w x 3 float16 linear radiance: log10 Y ~ N(0, 1.2) clipped to
-    [-3, 2]; each channel Y * U[0.7, 1.3]; rounded to nearest binary16."""
+    [-3, 2]; each channel Y * U[0.7, 1.3]; rounded to nearest binary16. With
+    exact=True the same draws are returned unrounded, as float64 (the radiance
+    the binary16 image stores)."""
     n = h * w
     log_y = np.clip(rng.normal(0.0, 1.2, n), -3.0, 2.0)
     y = np.power(10.0, log_y)
     jitter = 0.7 + 0.6 * rng.random((n, 3), dtype=np.float64)
-    return (y[:, None] * jitter).astype(np.float16).reshape(h, w, 3)
+    rad = (y[:, None] * jitter).reshape(h, w, 3)
+    return rad if exact else rad.astype(np.float16)
 
 
 HDR_SHAPE = (4096, 4096)
 
 
-def hdr_image(index, seed=HDR_SEED, shape=HDR_SHAPE):
+def hdr_image(index, seed=HDR_SEED, shape=HDR_SHAPE, exact=False):
     h, w = shape
-    return hdr_pixels(_rng(seed, index), h, w)
+    return hdr_pixels(_rng(seed, index), h, w, exact)
 
 
 def hdr_images(seed=HDR_SEED, count=16, shape=HDR_SHAPE, workers=1):

@@ -218,3 +218,29 @@ def test_low_variance_image_within_derived_bound(dev):
     report("low-variance image: sigma %.2e, |dT| %.2e, derived bound %.2e" % (st_ref["sigma"], err,
                                                                           bound))
     assert err <= bound
+
+
+def test_hdr_storage_error_against_exact_radiance(dev):
+    """The HDR error stated a second way: the GPU result from the binary16
+    image against the FP64 oracle on the radiance it stores before rounding
+    (passed as FP32, 2^-24 relative). Each binary16 channel is within 2^-11
+    relative of that radiance, and L is degree-1 homogeneous and monotone in
+    every channel, so L moves by at most 2^-11 relative (plus the kernel's
+    1e-5). Then x = ln(Lhat + eps) and mu move by at most 2^-11 and sigma by at
+    most 2 * 2^-11; with z = (x - mu) / sigma, dT = T (1 - T) c dz, and since
+    T (1 - T) <= 1/4 and T (1 - T) |c z| <= 0.224 (the logistic's largest
+    u sigma'(u)), |dT| <= (c / 4) (2 * 2^-11) / sigma + 0.224 (2 * 2^-11) / sigma,
+    plus the kernel's 1e-5."""
+    img = synth.hdr_pixels(np.random.default_rng(123), 256, 256)
+    exact = synth.hdr_pixels(np.random.default_rng(123), 256, 256, exact=True).astype(np.float32)
+    outs, lhats, _ = P.tonemap_global([to_dev(img, dev)], torch.float32, torch.float32, **TM)
+    lhat_ref = oracle.decolorize(exact)
+    rel = float(np.max(np.abs(lhats[0].cpu().numpy() - lhat_ref) / lhat_ref))
+    t_ref, _, st = oracle.tonemap(exact, **TM)
+    dt = float(np.max(np.abs(outs[0].cpu().numpy() - t_ref)))
+    half = 2.0 ** -11
+    bound_t = (TM["contrast"] / 4 + 0.224) * (2 * half) / st["sigma"] + 1e-5
+    report("binary16 storage: max rel |dL| %.3e (bound %.3e), max |dT| %.3e (bound %.3e)" %
+           (rel, half + 1e-5, dt, bound_t))
+    assert rel <= half + 1e-5
+    assert dt <= bound_t

@@ -267,3 +267,11 @@ def test_tonemap_twin_curve(oracle_mod):
     for v, tv in zip(lhat.ravel(), t.ravel()):
         assert twin.tonemap_curve(v, 1e-4, 2.0, st["mu"], st["sigma"], 1e-3) == pytest.approx(
             tv, abs=1e-15)
+
+
+def test_hdr_generator_exact_and_stored_agree():
+    """The binary16 image is the round-to-nearest of the exact radiance."""
+    a = synth.hdr_pixels(np.random.default_rng(5), 7, 9)
+    b = synth.hdr_pixels(np.random.default_rng(5), 7, 9, exact=True)
+    assert a.dtype == np.float16 and b.dtype == np.float64
+    np.testing.assert_array_equal(a, b.astype(np.float16))
