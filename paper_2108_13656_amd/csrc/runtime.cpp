@@ -291,7 +291,7 @@ struct Tune {
     int groups[3] = {1, 2, 2};
     int mixed_groups = 1;
     int decolor_gpc = 0;
-    int mixed_gpc = 4;
+    int mixed_gpc = 0;
     int pass1_gpc = 16;
     int pass2_gpc = 0;
     int tm_pipeline = 0; // 1 = per-image tone map on two streams
