@@ -74,6 +74,8 @@ def _load():
     lib.ref_tonemap_local_image.restype = i32
     lib.ref_tonemap_local_image.argtypes = [vp, i32, i32, i32, i64, d, d, d, d, d, d, vp, vp, i32,
                                             vp, i64]
+    lib.ref_recolour_image.restype = i32
+    lib.ref_recolour_image.argtypes = [vp, i32, i32, i32, i64, vp, vp, d, vp]
     lib.ref_colour_channel.restype = d
     lib.ref_colour_channel.argtypes = [d, d, d, d]
     lib.ref_tonemap_colour_image.restype = i32
@@ -248,3 +250,26 @@ def tonemap_local(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_fl
     if rc != 0:
         raise ValueError("oracle rejected the image or the strength")
     return t, {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": w * h}
+
+
+def recolour(img, lhat, t, saturation=1.0):
+    """Colour output (float64 HxWx3) of any tone map from the image, its Lhat
+    and its T: every channel min(1, T (C / Lhat)^s), grey T where Lhat == 0."""
+    img, code, w, h, pitch = _image_args(img)
+    lh = np.ascontiguousarray(lhat, np.float64)
+    tt = np.ascontiguousarray(t, np.float64)
+    if lh.shape != (h, w) or tt.shape != (h, w):
+        raise ValueError("lhat and t must be HxW")
+    rgb = np.empty((h, w, 3), np.float64)
+    if _load().ref_recolour_image(_ptr(img), code, w, h, pitch, _ptr(lh), _ptr(tt), saturation,
+                                  _ptr(rgb)):
+        raise ValueError("oracle rejected the arguments")
+    return rgb
+
+
+def tonemap_local_colour(img, beta_r=0.55, beta_k=0.8, eps=1e-4, contrast=2.0, sigma_floor=1e-3,
+                         strength=0.5, saturation=1.0, nthreads=1):
+    """Colour output of the local tone map: (rgb float64 HxWx3, T HxW)."""
+    t, _ = tonemap_local(img, beta_r, beta_k, eps, contrast, sigma_floor, strength, nthreads)
+    lhat = decolorize(img, beta_r, beta_k, nthreads)
+    return recolour(img, lhat, t, saturation), t

@@ -452,6 +452,31 @@ double ref_colour_channel(double c, double lhat, double t, double s)
     return v < 1.0 ? v : 1.0;
 }
 
+/* The colour output of any tone map: every channel of every pixel
+ * re-coloured by ref_colour_channel from the image's Lhat and tone-mapped T
+ * (W*H doubles each, row-major) into rgb_out (W*H*3, channels interleaved).
+ * Returns 0, or -1 on a bad argument. */
+int ref_recolour_image(const void *src, int dtype, int W, int H, int64_t pitch_bytes,
+                       const double *lhat, const double *t, double saturation, double *rgb_out)
+{
+    if (!src || !lhat || !t || !rgb_out || W < 0 || H < 0 || dtype < 0 || dtype > 2 ||
+        !(saturation >= 0.0))
+        return -1;
+    int es = dtype_size(dtype);
+    double unit = dtype == REF_U8 ? 255.0 : 1.0;
+    for (int y = 0; y < H; ++y) {
+        const unsigned char *row = (const unsigned char *)src + (int64_t)y * pitch_bytes;
+        for (int x = 0; x < W; ++x) {
+            const unsigned char *p = row + (int64_t)3 * es * x;
+            int64_t i = (int64_t)y * W + x;
+            for (int c = 0; c < 3; ++c)
+                rgb_out[3 * i + c] = ref_colour_channel(load_channel(p, dtype, c) / unit, lhat[i],
+                                                        t[i], saturation);
+        }
+    }
+    return 0;
+}
+
 /* Colour global tone map of one image: T, Lhat and the statistics as
  * ref_tonemap_image, then the re-coloured RGB of every pixel into rgb_out
  * (W*H*3 doubles, row-major, channels interleaved). lhat_out may be NULL.
@@ -472,20 +497,8 @@ int ref_tonemap_colour_image(const void *src, int dtype, int W, int H, int64_t p
     }
     int rc = ref_tonemap_image(src, dtype, W, H, pitch_bytes, beta_r, beta_k, eps, contrast,
                                sigma_floor, lhat, t_out, stats, nthreads);
-    if (rc == 0) {
-        int es = dtype_size(dtype);
-        double unit = dtype == REF_U8 ? 255.0 : 1.0;
-        for (int y = 0; y < H; ++y) {
-            const unsigned char *row = (const unsigned char *)src + (int64_t)y * pitch_bytes;
-            for (int x = 0; x < W; ++x) {
-                const unsigned char *p = row + (int64_t)3 * es * x;
-                int64_t i = (int64_t)y * W + x;
-                for (int c = 0; c < 3; ++c)
-                    rgb_out[3 * i + c] = ref_colour_channel(load_channel(p, dtype, c) / unit,
-                                                            lhat[i], t_out[i], saturation);
-            }
-        }
-    }
+    if (rc == 0)
+        rc = ref_recolour_image(src, dtype, W, H, pitch_bytes, lhat, t_out, saturation, rgb_out);
     if (!lhat_out)
         free(lhat);
     return rc;

@@ -131,3 +131,25 @@ def test_sampled_evaluation_matches_full(oracle_mod):
     part, st2 = oracle_mod.tonemap_local(img, strength=0.6, sample=idx, **TM)
     np.testing.assert_array_equal(part, full.ravel()[idx])
     assert st == st2
+
+
+def test_local_colour_output_keeps_ratios_and_luminance(oracle_mod):
+    """The local map's colour output is the same re-colouring as the global
+    one: at s = 1 every unclamped pixel keeps its channel ratios and has
+    Eqs. (1)-(6) luminance equal to its local T (degree-1 homogeneity)."""
+    img = synth.sdr_pixels(np.random.default_rng(49), 70, 90)
+    rgb, t = oracle_mod.tonemap_local_colour(img, strength=0.7, saturation=1.0, **TM)
+    free = rgb.max(axis=2) < 1.0
+    assert free.sum() > 1000
+    ys, xs = np.nonzero(free)
+    for y, x in zip(ys[::37], xs[::37]):
+        assert abs(oracle_mod.luminance(*rgb[y, x]) - t[y, x]) <= 1e-12
+    src = img.astype(np.float64)
+    np.testing.assert_allclose((rgb[..., 0] * src[..., 1])[free], (rgb[..., 1] * src[..., 0])[free],
+                               rtol=1e-12, atol=1e-15)
+
+
+def test_recolour_matches_global_colour(oracle_mod):
+    img = synth.hdr_pixels(np.random.default_rng(50), 20, 30)
+    rgb, t, lhat, _ = oracle_mod.tonemap_colour(img, saturation=0.6, **TM)
+    np.testing.assert_array_equal(oracle_mod.recolour(img, lhat, t, 0.6), rgb)
