@@ -107,7 +107,7 @@ typedef struct dc_tm_params {
  * dst_pitch >= width * sizeof(dst element); dst2 (optional, NULL with
  * dst2_dtype = DC_NONE) likewise. Outputs must not overlap the input or each
  * other. flags is 0, or DC_IMG_RGB_OUT in a tone-map call (dc_tonemap_global,
- * DC_PLAN_TONEMAP plans, server requests): dst then receives the re-coloured
+ * dc_tonemap_local, their plans, server requests): dst then receives the re-coloured
  * interleaved RGB (3 channels, R first, dst_pitch >= 3 * width * sizeof(dst
  * element)) instead of the gray T; dst2 keeps its meaning. Other calls reject
  * the flag with DC_ERR_UNSUPPORTED; unknown bits are DC_ERR_INVALID_ARG. */
@@ -204,9 +204,10 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
  *       grid's edges);
  *   T = (1 - local_strength) T_g + local_strength T_l, with T_g the global
  *       curve above (statistics as dc_tonemap_global, written to stats).
- * Gray output only: images flagged DC_IMG_RGB_OUT give DC_ERR_UNSUPPORTED.
- * Histograms hold integer masses (2^-19 per pixel), so results do not depend
- * on the order of the additions. Otherwise as dc_tonemap_global. */
+ * Images flagged DC_IMG_RGB_OUT get the same colour output as the global map
+ * with this T: min(1, T (C / Lhat)^s) per channel. Histograms hold integer
+ * masses (2^-19 per pixel), so results do not depend on the order of the
+ * additions. Otherwise as dc_tonemap_global. */
 int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                      const dc_tm_params *tm, dc_stats *stats, void *stream);
 

@@ -426,24 +426,24 @@ def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, 
 def tonemap_local(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
                   eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR,
                   strength=TM_LOCAL_STRENGTH, outs=None, lhats=None, stats=None, want_stats=True,
-                  stream=None):
+                  stream=None, colour=False, saturation=TM_SATURATION):
     """Local tone map (Sec. III-B.2: smoothed local histogram equalisation on
     64-pixel tiles, blended with the global curve by ``strength``) of a list of
-    images. Returns (T outputs, Lhat outputs or None, stats) as
-    ``tonemap_global``."""
+    images. Returns (outputs, Lhat outputs or None, stats) as ``tonemap_global``;
+    colour=True (or HxWx3 ``outs``) gives the re-coloured RGB."""
     xs = list(xs)
     if not xs:
         return [], None, None
     dev = xs[0].device
     if outs is None:
-        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
+        outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1], colour) for x in xs]
     if lhats is None and lhat_dtype is not None:
         lhats = [_alloc(x, lhat_dtype, x.shape[0], x.shape[1]) for x in xs]
     if stats is None and want_stats:
         stats = torch.empty((len(xs), STATS_BYTES), dtype=torch.uint8, device=dev)
     arr = _image_array(xs, outs, lhats)
     p = _params(beta_r, beta_k)
-    tm = DcTmParams(eps, contrast, sigma_floor, TM_SATURATION, strength)
+    tm = DcTmParams(eps, contrast, sigma_floor, saturation, strength)
     _check(lib().dc_tonemap_local(context(dev).handle, arr, len(xs), ctypes.byref(p),
                                   ctypes.byref(tm),
                                   ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),

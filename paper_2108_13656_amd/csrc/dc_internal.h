@@ -140,6 +140,9 @@ hipError_t launch_ltm_tables(const DevImage *table, const int64_t *tile_end, int
 hipError_t launch_ltm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                             int64_t t0, int64_t t1, int src_dtype, TmArgs tm, const Curve *curves,
                             const LtmCoef *coef, int64_t grid, hipStream_t s);
+hipError_t launch_ltm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                             int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
+                             const Curve *curves, const LtmCoef *coef, hipStream_t s);
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                            int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
                            const Curve *curves, int64_t grid, hipStream_t s);

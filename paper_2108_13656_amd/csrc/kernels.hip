@@ -1505,6 +1505,138 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
     __syncthreads();
 }
 
+// Colour output of one pixel from a tone-mapped T (the local map's blend):
+// every channel T (C / L)^s clamped to at most 1, grey T where there is no
+// colour to carry, in the same three modes and 8-bit scaling as colour_px
+// (which takes the global curve's exponential instead of T).
+template <int SRC, int MODE, bool U8>
+__device__ __forceinline__ void colour_of_t(float R, float G, float B, float l, float T, float s,
+                                            float *o)
+{
+    constexpr float kOut = U8 ? 255.0f : 1.0f;
+    if constexpr (SRC != 0) {
+        R = fmaxf(R, 0.0f);
+        G = fmaxf(G, 0.0f);
+        B = fmaxf(B, 0.0f);
+    }
+    if constexpr (MODE == kColourGrey) {
+        o[0] = o[1] = o[2] = T * kOut;
+        return;
+    }
+    const float S = (R + G) + B;
+    const bool grey = !(l > fmaf(S, 1e-6f, SRC == 0 ? 1e-6f : 0.0f));
+    const float C[3] = {R, G, B};
+    const float il = hw_rcp(fmaxf(l, 1e-30f));
+    if constexpr (MODE == kColourRatio) {
+        const float ko = T * il * kOut;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            o[c] = grey ? T * kOut : (U8 ? C[c] * ko : fminf(C[c] * ko, 1.0f));
+    } else {
+        const float lT = hw_log2(T);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            o[c] = grey ? T * kOut : hw_exp2(fminf(fmaf(s, hw_log2(C[c] * il), lT), 0.0f)) * kOut;
+    }
+}
+
+// Curve pass of the local tone map with colour output over one tile: reads
+// the input (the colour needs it), T as ltm_pass2_tile, 3 channels per pixel.
+template <int SRC, int MODE, bool U8>
+__device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile, TmArgs tm,
+                                                Curve cv, const LtmCoef *__restrict__ coef,
+                                                LtmLds *lds)
+{
+    constexpr int PPU = unit_px(SRC);
+    constexpr int U = kStatsPxPerThread / PPU;
+    constexpr int ES = elem_size(SRC);
+    const LtmRef r = ltm_ref(im, tile);
+    const Enc e{1.0f, 1.0f};
+    const float lo2 = hw_log2(tm.eps);
+    const int dt = U8 ? 0 : im.dst_dtype;
+    uint8_t *dst = im.dst + (int64_t)r.ty * kLtmTile * r.dp +
+                   (int64_t)r.tx * kLtmTile * 3 * elem_size(im.dst_dtype);
+    if (r.vec) {
+        unsigned w[U][3];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            load_unit(r.src + min(row, r.bh - 1) * r.sp + col * 3 * ES, w[i]);
+        }
+        ltm_stage(im, r, coef, lds);
+        int col0, row0;
+        ltm_slot<PPU>(0, 0, row0, col0);
+        int cx0[PPU], cx1[PPU];
+        float wx[PPU];
+#pragma unroll
+        for (int j = 0; j < PPU; ++j)
+            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], cx1[j], wx[j]);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            int row, col;
+            ltm_slot<PPU>(i, 0, row, col);
+            if (row < r.bh) {
+                int cy0, cy1;
+                float wy;
+                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                float o[3 * PPU];
+#pragma unroll
+                for (int j = 0; j < PPU; ++j) {
+                    const float R = chan<SRC>(w[i], 3 * j), G = chan<SRC>(w[i], 3 * j + 1),
+                                B = chan<SRC>(w[i], 3 * j + 2);
+                    const float l = lum<SRC>(R, G, B, im.k);
+                    const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j],
+                                              cx1[j], wx[j], cy0, cy1, wy);
+                    colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, &o[3 * j]);
+                }
+                store_rgb_unit<PPU>(dst + row * r.dp, dt, col, o);
+            }
+        }
+    } else {
+        ltm_stage(im, r, coef, lds);
+#pragma unroll 1
+        for (int sl = 0; sl < kStatsPxPerThread; ++sl) {
+            int row, col;
+            ltm_slot<PPU>(sl / PPU, sl % PPU, row, col);
+            if (row < r.bh && col < r.bw) {
+                float R, G, B;
+                load_px<SRC>(r.src + row * r.sp + col * 3 * ES, R, G, B);
+                const float l = lum<SRC>(R, G, B, im.k);
+                int cx0, cx1, cy0, cy1;
+                float wx, wy;
+                ltm_axis(col, r.tx, r.nx, cx0, cx1, wx);
+                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0, cx1, wx,
+                                          cy0, cy1, wy);
+                float o[3];
+                colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, o);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    store_px<false, false>(dst + row * r.dp, dt, 3 * col + c, o[c], e);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int SRC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_ltm_colour(const DevImage *__restrict__ table,
+                                                       const int64_t *__restrict__ tile_end,
+                                                       int img0, int nimg, int64_t t0, int64_t t1,
+                                                       TmArgs tm, const Curve *__restrict__ curves,
+                                                       const LtmCoef *__restrict__ coef)
+{
+    __shared__ LtmLds lds[9 * kLtmBins];
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
+        const DevImage im = table[i];
+        if (im.dst_dtype == 0)
+            ltm_colour_tile<SRC, MODE, true>(im, tile - im.tile_begin, tm, curves[i], coef, lds);
+        else
+            ltm_colour_tile<SRC, MODE, false>(im, tile - im.tile_begin, tm, curves[i], coef, lds);
+    });
+}
+
 // SRC 3 = the staged form (FP32 output holding x2), whatever the input type.
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict__ table,
@@ -1719,6 +1851,30 @@ hipError_t launch_ltm_pass2(const DevImage *table, const int64_t *tile_end, int 
     else
         DC_LAUNCH_L2(3);
 #undef DC_LAUNCH_L2
+    return hipGetLastError();
+}
+
+hipError_t launch_ltm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
+                             int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
+                             const Curve *curves, const LtmCoef *coef, hipStream_t s)
+{
+    const dim3 g(grid_of(t1 - t0, 0));
+#define DC_LAUNCH_LC(S, M)                                                                        \
+    hipLaunchKernelGGL((k_ltm_colour<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,   \
+                       t0, t1, tm, curves, coef)
+    switch (src_dtype * 4 + mode) {
+    case 0 * 4 + kColourGrey: DC_LAUNCH_LC(0, kColourGrey); break;
+    case 0 * 4 + kColourRatio: DC_LAUNCH_LC(0, kColourRatio); break;
+    case 0 * 4 + kColourPow: DC_LAUNCH_LC(0, kColourPow); break;
+    case 1 * 4 + kColourGrey: DC_LAUNCH_LC(1, kColourGrey); break;
+    case 1 * 4 + kColourRatio: DC_LAUNCH_LC(1, kColourRatio); break;
+    case 1 * 4 + kColourPow: DC_LAUNCH_LC(1, kColourPow); break;
+    case 2 * 4 + kColourGrey: DC_LAUNCH_LC(2, kColourGrey); break;
+    case 2 * 4 + kColourRatio: DC_LAUNCH_LC(2, kColourRatio); break;
+    case 2 * 4 + kColourPow: DC_LAUNCH_LC(2, kColourPow); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DC_LAUNCH_LC
     return hipGetLastError();
 }
 

@@ -274,7 +274,7 @@ dc::DevImage describe_local(const dc_image &m, int index, const dc_params *param
     const bool out16 = (uintptr_t)m.dst % 16 == 0 && m.dst_pitch % 16 == 0 &&
                        (!m.dst2 || ((uintptr_t)m.dst2 % 16 == 0 && m.dst2_pitch % 16 == 0));
     d.walk = (src4 && out16) ? dc::kWalkRows : dc::kWalkScalar;
-    d.staged = m.dst_dtype == DC_F32 ? 1 : 0;
+    d.staged = (m.dst_dtype == DC_F32 && !(m.flags & DC_IMG_RGB_OUT)) ? 1 : 0;
     return d;
 }
 
@@ -405,11 +405,12 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
         order[i] = i;
     if (kind != kTabDecolor)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            // second key: colour output (tone map) or FP32 staging (local tone map)
-            const int ra = kind == kTabLocal ? imgs[a].dst_dtype == DC_F32
-                                             : imgs[a].flags & DC_IMG_RGB_OUT;
-            const int rb = kind == kTabLocal ? imgs[b].dst_dtype == DC_F32
-                                             : imgs[b].flags & DC_IMG_RGB_OUT;
+            // second key: colour output, then (local tone map) FP32 staging
+            auto key = [&](const dc_image &m) {
+                const int rgb = (m.flags & DC_IMG_RGB_OUT) ? 2 : 0;
+                return kind == kTabLocal ? (rgb ? rgb : (m.dst_dtype == DC_F32 ? 1 : 0)) : rgb;
+            };
+            const int ra = key(imgs[a]), rb = key(imgs[b]);
             return imgs[a].src_dtype != imgs[b].src_dtype ? imgs[a].src_dtype < imgs[b].src_dtype
                                                           : ra < rb;
         });
@@ -533,6 +534,13 @@ int ensure_fork(dc_ctx *ctx, size_t n)
     return DC_OK;
 }
 
+// Colour mode of a saturation: s = 0 grey, s = 1 ratio, anything else power.
+int colour_mode(float saturation)
+{
+    return saturation == 0.0f ? dc::kColourGrey
+                              : (saturation == 1.0f ? dc::kColourRatio : dc::kColourPow);
+}
+
 // Curve pass over tiles [t0, t1) of images img0 .. img0 + nimg - 1, all of
 // input type src and all with (rgb) or without colour output.
 hipError_t launch_curve(const DevBufs &b, int img0, int nimg, int64_t t0, int64_t t1, int src,
@@ -541,11 +549,8 @@ hipError_t launch_curve(const DevBufs &b, int img0, int nimg, int64_t t0, int64_
     if (!rgb)
         return dc::launch_tm_pass2(b.table, b.tile_end, img0, nimg, t0, t1, 0, src, a, b.curves,
                                    grid, st);
-    const int mode = a.saturation == 0.0f   ? dc::kColourGrey
-                     : a.saturation == 1.0f ? dc::kColourRatio
-                                            : dc::kColourPow;
-    return dc::launch_tm_colour(b.table, b.tile_end, img0, nimg, t0, t1, src, mode, a, b.curves,
-                                grid, st);
+    return dc::launch_tm_colour(b.table, b.tile_end, img0, nimg, t0, t1, src,
+                                colour_mode(a.saturation), a, b.curves, grid, st);
 }
 
 // Kernel sequence of a tone map over a staged table. Mode 0: the statistics
@@ -644,8 +649,11 @@ int enqueue_local(dc_ctx *ctx, const HostTable &h, const DevBufs &b, dc::TmArgs 
     for (const auto &r : h.runs) {
         const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
         if (e == hipSuccess)
-            e = dc::launch_ltm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1,
-                                     r.staged ? 3 : r.src, a, b.curves, b.coef, 0, st);
+            e = r.rgb ? dc::launch_ltm_colour(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0,
+                                              t1, r.src, colour_mode(a.saturation), a, b.curves,
+                                              b.coef, st)
+                      : dc::launch_ltm_pass2(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1,
+                                             r.staged ? 3 : r.src, a, b.curves, b.coef, 0, st);
     }
     mark(ctx, marks, 3, st);
     if (e != hipSuccess)
@@ -1121,18 +1129,6 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
     return release_slot(slot, st);
 }
 
-namespace {
-// The local tone map writes gray T only.
-int reject_rgb(const dc_image *imgs, int32_t n)
-{
-    for (int32_t i = 0; i < n; ++i)
-        if (imgs[i].flags & DC_IMG_RGB_OUT)
-            return fail(DC_ERR_UNSUPPORTED, "the local tone map has no colour output (image " +
-                                                std::to_string(i) + ")");
-    return DC_OK;
-}
-} // namespace
-
 int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                      const dc_tm_params *tm, dc_stats *stats, void *stream)
 {
@@ -1141,8 +1137,6 @@ int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_para
     if (rc != DC_OK)
         return rc;
     rc = dc_validate(imgs, n, params, tm);
-    if (rc == DC_OK)
-        rc = reject_rgb(imgs, n);
     if (rc != DC_OK || n == 0)
         return rc;
     const hipStream_t st = (hipStream_t)stream;
@@ -1213,8 +1207,6 @@ int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
     if (kind == DC_PLAN_DECOLORIZE && (tm || stats))
         return fail(DC_ERR_INVALID_ARG, "tm and stats apply to tone-map plans only");
     rc = dc_validate(imgs, n, params, kind == DC_PLAN_DECOLORIZE ? nullptr : tm);
-    if (rc == DC_OK && kind == DC_PLAN_LOCAL)
-        rc = reject_rgb(imgs, n);
     if (rc != DC_OK)
         return rc;
     return plan_build(ctx, kind, imgs, n, params, tm, stats, flags, ctx->tune, plan);

@@ -117,8 +117,29 @@ def test_local_plan_graph_replays(dev):
     plan.close()
 
 
-def test_local_rejects_colour_output(dev):
-    x = to_dev(_image("u8", 8, 8, 60), dev)
-    with pytest.raises(P.DecolorError) as e:
-        P.tonemap_local([x], outs=[torch.empty((8, 8, 3), device=dev)])
-    assert e.value.status == P.DC_ERR_UNSUPPORTED
+@pytest.mark.parametrize("s", [1.0, 0.6, 0.0])
+@pytest.mark.parametrize("kind,shape", [("u8", (64, 64)), ("f16", (130, 1001)), ("u8", (300, 517)),
+                                        ("f32", (70, 33))])
+def test_local_colour_vs_oracle(dev, kind, shape, s):
+    h, w = shape
+    img = _image(kind, h, w, h + w)
+    rgb_ref, _ = oracle.tonemap_local_colour(img, strength=0.6, saturation=s, **TM)
+    x = to_dev(img, dev)
+    got = P.tonemap_local([x], torch.float32, colour=True, strength=0.6, saturation=s, **TM)[0][0]
+    assert got.shape == (h, w, 3)
+    check_f32(got.cpu().numpy(), rgb_ref, "local colour %s %dx%d s=%g" % (kind, h, w, s))
+    g8 = P.tonemap_local([x], torch.uint8, colour=True, strength=0.6, saturation=s, **TM)[0][0]
+    check_u8(g8.cpu().numpy(), oracle.encode_u8(rgb_ref), "local colour u8", max_fraction=2e-3)
+
+
+def test_local_gray_and_colour_in_one_call(dev):
+    imgs = [_image("u8", 100, 150, 61), _image("f16", 64, 700, 62), _image("u8", 33, 65, 63)]
+    xs = [to_dev(a, dev) for a in imgs]
+    outs = [torch.empty((100, 150, 3), dtype=torch.uint8, device=dev),
+            torch.empty((64, 700), device=dev),
+            torch.empty((33, 65, 3), dtype=torch.float16, device=dev)]
+    P.tonemap_local(xs, outs=outs, strength=0.8, saturation=0.7, **TM)
+    for x, o in zip(xs, outs):
+        one = P.tonemap_local([x], o.dtype, colour=o.dim() == 3, strength=0.8, saturation=0.7,
+                              **TM)[0][0]
+        assert torch.equal(one, o)
