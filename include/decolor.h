@@ -333,8 +333,11 @@ typedef struct dc_request {
 
 /* A finished request. Times are seconds on the server clock (dc_server_clock):
  * submitted (for replays: the scheduled arrival), admitted, launched, and the
- * step that saw its launch complete. status is DC_OK, or DC_ERR_NO_MEMORY for a
- * request whose output is larger than the whole budget (rejected at once). */
+ * step that saw its launch complete. status is DC_OK; DC_ERR_NO_MEMORY for a
+ * request whose output is larger than the whole budget (rejected at once); or,
+ * when enqueueing its launch failed, that failure's status (the step that saw
+ * it returns it too, after waiting for the lane and freeing the batch's
+ * memory). */
 typedef struct dc_completion {
     int64_t id;
     int32_t status;
@@ -364,10 +367,13 @@ int dc_server_replay(dc_server *server, const dc_request *reqs, const double *ar
 
 /* Measurement hooks (instrumentation, not part of the method). With on != 0,
  * every later compute call on ctx records timing events on its stream before
- * and after each kernel it launches: decolorize and decolorize_batch record one
- * interval (the decolorization kernel); tonemap_global records three (the
- * statistics pass, the two-level combine, the curve pass), or one (the whole
- * sequence) when the two-stream schedule is selected. dc_last_timings waits for the
+ * and after each kernel it launches: decolorize, decolorize_batch,
+ * decolorize_batch_betas and channel_batch record one interval (their one
+ * kernel, or run of kernels); tonemap_global records three (the statistics
+ * pass, the two-level combine, the curve pass), or one (the whole sequence)
+ * when the two-stream schedule is selected; tonemap_local records three (the
+ * statistics-and-histogram pass, the combine with the curve tables, the curve
+ * pass). dc_last_timings waits for the
  * last such call to finish and writes up to cap interval lengths in
  * milliseconds to ms (host array); it returns how many it wrote, or a negative
  * status. Only the most recent call's intervals are kept. */

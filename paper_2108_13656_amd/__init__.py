@@ -83,7 +83,7 @@ class DcTuning(ctypes.Structure):
             t.groups[i] = g
         t.mixed_groups = d["mixed_groups"]
         t.decolor_grid_per_cu = d["decolor_grid_per_cu"]
-        t.mixed_grid_per_cu = d.get("mixed_grid_per_cu", 4)
+        t.mixed_grid_per_cu = d.get("mixed_grid_per_cu", 0)
         t.pass1_grid_per_cu = d["pass1_grid_per_cu"]
         t.pass2_grid_per_cu = d["pass2_grid_per_cu"]
         t.tonemap_pipeline = d.get("tonemap_pipeline", 0)

@@ -1478,6 +1478,24 @@ void complete(dc_server *sv, const dc_server::Req &q, int status, int batch, dou
     --sv->in_system;
 }
 
+// A launch on a lane failed: its requests complete with that status and give
+// their memory back, so none of them is later reported as done by a batch it
+// never ran in. Copies or kernels already enqueued on the lane may still write
+// that memory, so the lane is drained first.
+int fail_lane(dc_server *sv, dc_server::Lane &ln, int status)
+{
+    (void)hipStreamSynchronize(ln.s);
+    const double t = server_now(sv);
+    for (auto &r : ln.batch) {
+        if (r.owned)
+            arena_free(sv, r.off, r.bytes);
+        complete(sv, r, status, 0, t);
+    }
+    ln.batch.clear();
+    ln.busy = false;
+    return status;
+}
+
 int server_step(dc_server *sv)
 {
     // 1. retire finished launches
@@ -1562,7 +1580,7 @@ int server_step(dc_server *sv)
                                            (size_t)q.r.img.src_pitch, (size_t)pitch, rows,
                                            hipMemcpyHostToDevice, ln.s);
                 if (ce != hipSuccess)
-                    return hip_fail(ce, "host input copy");
+                    return fail_lane(sv, ln, hip_fail(ce, "host input copy"));
                 imgs[i].src = d;
                 imgs[i].src_pitch = pitch;
                 imgs[i].flags &= ~DC_IMG_HOST_SRC;
@@ -1579,10 +1597,10 @@ int server_step(dc_server *sv)
         if (rc == DC_OK)
             rc = release_slot(slot, ln.s);
         if (rc != DC_OK)
-            return rc;
+            return fail_lane(sv, ln, rc);
         const hipError_t e = hipEventRecord(ln.done, ln.s);
         if (e != hipSuccess)
-            return hip_fail(e, "hipEventRecord");
+            return fail_lane(sv, ln, hip_fail(e, "hipEventRecord"));
         ln.busy = true;
     }
     return DC_OK;
