@@ -72,6 +72,7 @@ struct DevImage {
     int32_t width;          // pixels per row (local tone map's 2-D tile walk)
     int32_t height;         // rows
     int32_t staged;         // local tone map: the FP32 dst carries x2 between passes
+    int32_t shared_src;     // decolorization: another image of the call reads the same input
     float unit;             // Lhat = L * unit (1/255 for 8-bit input)
     Coef k;                 // per-pixel constants for this image's input type
 };

@@ -175,12 +175,26 @@ __device__ __forceinline__ float chan(const unsigned (&w)[3], int e)
 }
 
 // One unit: three dwords from a 4-byte aligned address (a single dwordx3).
+// The loads are nontemporal (NT): a pass reads each input byte once, and an
+// input that a later pass reads again (the tone map's curve pass) is, at the
+// batch sizes that matter, far larger than the caches. Streaming loads leave
+// L2 to the small shared data (descriptors, partials, curves) and made the
+// tone map's curve pass about 6 % faster on MI355X. A decolorization call
+// that reads one input for several images (the weight sweep) keeps plain
+// loads for it, so the repeats hit in cache.
+template <bool NT = true>
 __device__ __forceinline__ void load_unit(const uint8_t *p, unsigned (&w)[3])
 {
     const DC_GLOBAL unsigned *q = gp<unsigned>(p);
-    w[0] = q[0];
-    w[1] = q[1];
-    w[2] = q[2];
+    if constexpr (NT) {
+        w[0] = __builtin_nontemporal_load(&q[0]);
+        w[1] = __builtin_nontemporal_load(&q[1]);
+        w[2] = __builtin_nontemporal_load(&q[2]);
+    } else {
+        w[0] = q[0];
+        w[1] = q[1];
+        w[2] = q[2];
+    }
 }
 
 template <int SRC>
@@ -436,9 +450,15 @@ __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile)
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= TILE) {
         unsigned w[U][3];
+        if (im.shared_src) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+            for (int u = 0; u < U; ++u)
+                load_unit<false>(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             float v[PPU];

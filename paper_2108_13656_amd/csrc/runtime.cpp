@@ -14,6 +14,7 @@
 #include <deque>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -437,6 +438,16 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
         h.tile_end[i] = total;
     }
     h.total_tiles = total;
+    if (kind == kTabDecolor) {
+        // inputs read for more than one image of the call keep cached loads
+        std::vector<std::pair<const uint8_t *, int32_t>> srcs((size_t)n);
+        for (int32_t i = 0; i < n; ++i)
+            srcs[i] = {h.d[i].src, i};
+        std::sort(srcs.begin(), srcs.end());
+        for (int32_t i = 0; i + 1 < n; ++i)
+            if (srcs[i].first == srcs[i + 1].first)
+                h.d[srcs[i].second].shared_src = h.d[srcs[i + 1].second].shared_src = 1;
+    }
     int64_t grps = 0;
     for (int32_t i = 0; i < n; ++i) {
         h.d[i].grp_begin = grps;
