@@ -13,6 +13,9 @@ times: autotuned launch shapes and a HIP-graph plan over resident buffers.
   image against the oracle (which still builds every tile's histogram).
 - uneven batch of 256 images (half 8-bit, half binary16, 64..4096 per side),
   one persistent launch: every pixel against the oracle.
+- 8-bit frames of the video batch (8 x 1080p + 8 x 2160p) through the global
+  tone map, 8-bit T and FP32 Lhat out (the serving mix's SDR request): every
+  image's statistics, and every pixel of both outputs, against the oracle.
 """
 import os
 
@@ -111,6 +114,36 @@ def test_hdr_tonemap_full(dev):
     report("hdr tone map 16x4096^2: max |d mu| %.2e, max |d sigma|/sigma %.2e, max |dT| %.2e "
            "(65536 sampled px per image)" % (worst_mu, worst_sig, worst_t))
     assert worst_mu <= 2e-5 and worst_sig <= 2e-5 and worst_t <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_sdr_tonemap_every_pixel(dev, lut):
+    frames = [synth.video_frame(i) for i in list(range(8)) + list(range(32, 40))]
+    xs = [to_dev(f, dev) for f in frames]
+    outs = [torch.empty(f.shape[:2], dtype=torch.uint8, device=dev) for f in frames]
+    lh = [torch.empty(f.shape[:2], dtype=torch.float32, device=dev) for f in frames]
+    stats = torch.zeros((len(frames), P.STATS_BYTES), dtype=torch.uint8, device=dev)
+    _run_plan(P.PLAN_TONEMAP, xs, outs, lh, stats=stats, **TM)
+    st = P.stats_to_host(stats)
+    worst_l, worst_mu, off, total = 0.0, 0.0, 0, 0
+    for i, f in enumerate(frames):
+        lhat = lut[_codes(f)] / 255.0
+        ref = oracle.tonemap_stats(lhat, TM["eps"])
+        worst_mu = max(worst_mu, abs(st[i]["mu"] - ref["mu"]),
+                       abs(st[i]["sigma"] - ref["sigma"]) / ref["sigma"])
+        assert st[i]["count"] == ref["count"]
+        worst_l = max(worst_l, float(np.max(np.abs(lh[i].cpu().numpy() - lhat))))
+        t_ref = oracle.tonemap_curve(lhat, ref["mu"], ref["sigma"], **TM)
+        d = np.abs(outs[i].cpu().numpy().astype(np.int32) -
+                   oracle.encode_u8(t_ref).astype(np.int32))
+        assert d.max() <= 1, i
+        off += int(np.count_nonzero(d))
+        total += d.size
+    report("sdr tone map 8x1080p + 8x2160p: max |d mu|, |d sigma|/sigma %.2e, max |dLhat| %.2e, "
+           "u8 T codes off by one: %d of %d (fraction %.3e)" %
+           (worst_mu, worst_l, off, total, off / total))
+    assert worst_mu <= 2e-5 and worst_l <= 1e-5
+    assert off / total <= 1e-3
 
 
 @pytest.mark.timeout(900)
