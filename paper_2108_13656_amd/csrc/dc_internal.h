@@ -84,6 +84,15 @@ struct Part {
     float n, mean, m2, lo, hi;
 };
 
+// What a wave of a statistics pass writes for its 1024 pixels: the count, the
+// shift K (x2 of the wave's first pixel), the sums of d = x2 - K and d^2, and
+// the extremes of L in input units. The combine turns it into a Part (mean =
+// K + s / n, m2 = q - s^2 / n, extremes times the image's unit), so the
+// statistics pass spends no division or scaling per wave.
+struct WavePart {
+    float n, K, s, q, lo, hi;
+};
+
 // Per-image curve of the tone map: T = 1 / (1 + exp2(a * (x2 - mu2))).
 struct Curve {
     float a, mu2;
@@ -122,9 +131,9 @@ hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int im
                           hipStream_t s);
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                            int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
-                           Part *parts, int64_t grid, hipStream_t s);
+                           WavePart *parts, int64_t grid, hipStream_t s);
 hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int img0, int nimg,
-                             int64_t g0, int64_t g1, const Part *parts, Part *parts2,
+                             int64_t g0, int64_t g1, const WavePart *parts, Part *parts2,
                              hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
                               const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s);
@@ -132,7 +141,7 @@ hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int 
                             int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
                             const Curve *curves, int64_t grid, hipStream_t s);
 hipError_t launch_ltm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, Part *parts,
+                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, WavePart *parts,
                             unsigned *hist, int64_t grid, hipStream_t s);
 hipError_t launch_ltm_tables(const DevImage *table, const int64_t *tile_end, int nimg,
                              int64_t total_tiles, const unsigned *hist, LtmCoef *coef,

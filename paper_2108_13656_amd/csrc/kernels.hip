@@ -57,12 +57,16 @@ __device__ __forceinline__ float lum_code(float R, float G, float B, Coef k)
 // values (the same four constants), finished as sqrt(Y) / S. Binary16 spans
 // 6e-8 .. 65504, so Y stays between about 1e-30 and 5e20 and no intermediate
 // leaves the FP32 normal range; NaN and negative channels read as 0 (max
-// returns the non-NaN operand), and a black pixel gives 0 * (1 / 1e-30) = 0.
+// returns the non-NaN operand). Blue reads as at least 1e-30, which keeps
+// S > 0 without a clamp of its own and changes no result: binary16 has no
+// value below 6e-8 but 0, and every term of 1e-30 either underflows to 0
+// (B^2, C^2) or is absorbed (in S, G + B), so a black pixel still gives
+// sqrt(0) * (1 / 1e-30) = 0.
 __device__ __forceinline__ float lum_half(float R, float G, float B, Coef k)
 {
     R = fmaxf(R, 0.0f);
     G = fmaxf(G, 0.0f);
-    B = fmaxf(B, 0.0f);
+    B = fmaxf(B, 1e-30f);
     const float rr = R * R, gg = G * G;
     const float Q = hw_sqrt(fmaf(B, B, rr + gg));                 // sqrt(3) * Eq. (1)
     const float Lgr3 = hw_sqrt(fmaf(k.cr, rr, k.cg * gg));        // sqrt(3) * Eq. (3)
@@ -71,7 +75,7 @@ __device__ __forceinline__ float lum_half(float R, float G, float B, Coef k)
     const float A = fmaf(R, Lgr3, (G + B) * Q);                   // sqrt(3) S * Eq. (4)
     const float C = B * fmaf(1.73205080756887729f, rg, Q);        // sqrt(3) S * Eq. (5)
     const float Y = fmaf(k.ck * A, A, k.cc * (C * C));            // S^2 * Eq. (6)^2
-    return hw_sqrt(Y) * hw_rcp(fmaxf(S, 1e-30f));
+    return hw_sqrt(Y) * hw_rcp(S);
 }
 
 // L for linear float input. The pixel is first normalised by S, so every
@@ -666,7 +670,7 @@ __device__ __forceinline__ float wave_max(float v)
 // call or on the launch shape.
 template <int SRC>
 __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
-                                              Part *__restrict__ parts)
+                                              WavePart *__restrict__ parts)
 {
     constexpr int PPU = unit_px(SRC);
     constexpr int U = kStatsPxPerThread / PPU;
@@ -676,7 +680,8 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
     const Enc e{im.unit, 255.0f};
     const bool vec = im.walk != kWalkScalar;
     float K, s = 0.0f, q = 0.0f, cnt, lo = __builtin_inff(), hi = -__builtin_inff();
-    if (vec && t.rem >= kStatsChunkPx) {
+    const bool full = vec && t.rem >= kStatsChunkPx;
+    if (full) {
         float lv[NV];
         tile_lum_full<SRC, U>(t, im.k, lv);
         if (t.dst2)
@@ -722,17 +727,12 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
     }
     s = wave_sum(s);
     q = wave_sum(q);
-    const float n = wave_sum(cnt);
+    const float n = full ? (float)(64 * NV) : wave_sum(cnt); // a full tile fills every lane
     lo = wave_min(lo);
     hi = wave_max(hi);
-    if ((threadIdx.x & 63) == 0) {
-        Part p = part_empty();
-        if (n > 0.0f) {
-            const float m = s / n;
-            p = Part{n, K + m, fmaxf(fmaf(-s, m, q), 0.0f), lo * im.unit, hi * im.unit};
-        }
-        parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] = p;
-    }
+    if ((threadIdx.x & 63) == 0)
+        parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] =
+            WavePart{n, K, s, q, lo, hi};
 }
 
 // Tone-map kernels cover tiles [t0, t1) of images img0 .. img0 + nimg - 1, so
@@ -743,7 +743,7 @@ template <int SRC, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
                                                      int img0, int nimg, int64_t t0, int64_t t1,
-                                                     TmArgs tm, Part *__restrict__ parts)
+                                                     TmArgs tm, WavePart *__restrict__ parts)
 {
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
@@ -761,13 +761,23 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict_
     });
 }
 
+// A wave's raw partial as a Part: mean = K + s / n, m2 = q - s (s / n)
+// (never below 0), extremes in Lhat units.
+__device__ __forceinline__ Part part_of(const WavePart &w, float unit)
+{
+    if (!(w.n > 0.0f))
+        return part_empty();
+    const float m = w.s / w.n;
+    return Part{w.n, w.K + m, fmaxf(fmaf(-w.s, m, w.q), 0.0f), w.lo * unit, w.hi * unit};
+}
+
 // Level 1 of the statistics combine: block g merges the fixed group of up to
 // kBlock consecutive wave partials g - grp_begin of its image (one per thread,
 // loaded in parallel) with a fixed LDS tree, and writes one group partial.
 __global__ __launch_bounds__(kBlock) void k_tm_combine(const DevImage *__restrict__ table,
                                                        const int64_t *__restrict__ grp_end,
                                                        int img0, int nimg, int64_t g0,
-                                                       const Part *__restrict__ parts,
+                                                       const WavePart *__restrict__ parts,
                                                        Part *__restrict__ parts2)
 {
     __shared__ Part sh[kBlock];
@@ -784,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_tm_combine(const DevImage *__restric
     const int64_t nparts = im.ntiles * kWavesPerBlock;
     const int64_t c = (g - im.grp_begin) * kBlock + threadIdx.x;
     const int tid = threadIdx.x;
-    sh[tid] = c < nparts ? parts[im.chunk_begin + c] : part_empty();
+    sh[tid] = c < nparts ? part_of(parts[im.chunk_begin + c], im.unit) : part_empty();
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
         if (tid < s)
@@ -1160,7 +1170,7 @@ __device__ __forceinline__ float ltm_u(float x2, float lo2)
 // curve pass to read instead of the input (im.staged).
 template <int SRC>
 __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
-                                               Part *__restrict__ parts,
+                                               WavePart *__restrict__ parts,
                                                unsigned *__restrict__ hist, unsigned *lds_hist)
 {
     constexpr int PPU = unit_px(SRC);
@@ -1249,14 +1259,9 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
     const float n = wave_sum(cnt);
     lo = wave_min(lo);
     hi = wave_max(hi);
-    if ((threadIdx.x & 63) == 0) {
-        Part p = part_empty();
-        if (n > 0.0f) {
-            const float m = s / n;
-            p = Part{n, K + m, fmaxf(fmaf(-s, m, q), 0.0f), lo * im.unit, hi * im.unit};
-        }
-        parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] = p;
-    }
+    if ((threadIdx.x & 63) == 0)
+        parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] =
+            WavePart{n, K, s, q, lo, hi};
     __syncthreads();
     if (threadIdx.x < kLtmBins)
         hist[(im.tile_begin + tile) * kLtmBins + threadIdx.x] = lds_hist[threadIdx.x];
@@ -1267,7 +1272,7 @@ template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_ltm_pass1(const DevImage *__restrict__ table,
                                                       const int64_t *__restrict__ tile_end,
                                                       int img0, int nimg, int64_t t0, int64_t t1,
-                                                      TmArgs tm, Part *__restrict__ parts,
+                                                      TmArgs tm, WavePart *__restrict__ parts,
                                                       unsigned *__restrict__ hist)
 {
     __shared__ unsigned lds_hist[kLtmBins];
@@ -1779,7 +1784,7 @@ hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int im
 
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                            int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
-                           Part *parts, int64_t grid, hipStream_t s)
+                           WavePart *parts, int64_t grid, hipStream_t s)
 {
     const dim3 g(grid_of(t1 - t0, grid));
 #define DC_LAUNCH_P1(S, M)                                                                        \
@@ -1798,7 +1803,7 @@ hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int i
 }
 
 hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int img0, int nimg,
-                             int64_t g0, int64_t g1, const Part *parts, Part *parts2,
+                             int64_t g0, int64_t g1, const WavePart *parts, Part *parts2,
                              hipStream_t s)
 {
     hipLaunchKernelGGL(k_tm_combine, dim3((unsigned)(g1 - g0)), dim3(kBlock), 0, s, table, grp_end,
@@ -1839,7 +1844,7 @@ hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int 
 }
 
 hipError_t launch_ltm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, Part *parts,
+                            int64_t t0, int64_t t1, int src_dtype, TmArgs tm, WavePart *parts,
                             unsigned *hist, int64_t grid, hipStream_t s)
 {
     const dim3 g(grid_of(t1 - t0, grid));

@@ -474,7 +474,7 @@ Layout layout_of(const HostTable &h)
     l.gends = l.ends + align_up(sizeof(int64_t) * n, 256);
     l.parts = l.gends + align_up(sizeof(int64_t) * n, 256);
     l.upload = l.parts;
-    l.parts2 = l.parts + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_tiles *
+    l.parts2 = l.parts + (h.tonemap ? align_up(sizeof(dc::WavePart) * (size_t)h.total_tiles *
                                                    dc::kWavesPerBlock, 256) : 0);
     l.curves = l.parts2 + (h.tonemap ? align_up(sizeof(dc::Part) * (size_t)h.total_grps, 256) : 0);
     l.hist = l.curves + (h.tonemap ? align_up(sizeof(dc::Curve) * n, 256) : 0);
@@ -495,7 +495,7 @@ struct DevBufs {
     const dc::DevImage *table;
     const int64_t *tile_end;
     const int64_t *grp_end;
-    dc::Part *parts;
+    dc::WavePart *parts;
     dc::Part *parts2;
     dc::Curve *curves;
     unsigned *hist;
@@ -506,7 +506,7 @@ DevBufs bufs_of(void *dev, const Layout &l)
 {
     char *p = (char *)dev;
     return DevBufs{(const dc::DevImage *)(p + l.table), (const int64_t *)(p + l.ends),
-                   (const int64_t *)(p + l.gends), (dc::Part *)(p + l.parts),
+                   (const int64_t *)(p + l.gends), (dc::WavePart *)(p + l.parts),
                    (dc::Part *)(p + l.parts2), (dc::Curve *)(p + l.curves),
                    (unsigned *)(p + l.hist), (dc::LtmCoef *)(p + l.coef)};
 }
