@@ -39,15 +39,42 @@ def check_f32(got, want_lhat, what, rel=False):
     return worst
 
 
-def check_u8(got, want_codes, what, max_fraction=U8_MAX_MISMATCH_FRACTION):
+def u8_mismatches_at_ties(got, want, slack=255.0 * F32_ABS_TOL):
+    """Largest distance, in code units, between the oracle's unrounded value
+    255 * want and the midpoint of the two codes wherever the GPU code differs
+    from the oracle's: every such pixel must sit within the FP32 error of a
+    rounding midpoint (the kernel rounds its FP32 value, the oracle its FP64
+    value, and only near a midpoint can the two round apart). Returns that
+    distance (0 when no code differs) after asserting it is <= slack."""
+    import oracle
+    want = np.asarray(want, np.float64)
+    codes = oracle.encode_u8(want).astype(np.int32)
     got = np.asarray(got).astype(np.int32)
-    want = np.asarray(want_codes).astype(np.int32)
-    diff = np.abs(got - want)
+    off = got != codes
+    if not np.any(off):
+        return 0.0
+    mid = (got[off] + codes[off]) / 2.0
+    dist = float(np.max(np.abs(255.0 * want[off] - mid)))
+    assert dist <= slack, "a code differs away from a rounding midpoint (%.3e)" % dist
+    return dist
+
+
+def check_u8(got, want, what, max_fraction=U8_MAX_MISMATCH_FRACTION):
+    """8-bit GPU codes vs the oracle's min(255, floor(255 want + 0.5)) of its
+    unrounded values want (the [0, 1] scale): at most one code apart, only at
+    rounding midpoints (u8_mismatches_at_ties), in at most max_fraction of
+    the pixels."""
+    import oracle
+    got = np.asarray(got).astype(np.int32)
+    codes = oracle.encode_u8(np.asarray(want, np.float64)).astype(np.int32)
+    diff = np.abs(got - codes)
     n_off = int(np.count_nonzero(diff))
     frac = n_off / max(1, diff.size)
-    report("%s: u8 max |diff| %d, %d of %d codes off by one (fraction %.3e)" %
-           (what, int(diff.max()) if diff.size else 0, n_off, diff.size, frac))
     assert int(diff.max() if diff.size else 0) <= U8_MAX_LSB, what
+    dist = u8_mismatches_at_ties(got, want)
+    report("%s: u8 max |diff| %d, %d of %d codes off by one (fraction %.3e), all within %.2e "
+           "of a rounding midpoint" % (what, int(diff.max()) if diff.size else 0, n_off, diff.size,
+                                       frac, dist))
     assert frac <= max_fraction, what
     return frac
 

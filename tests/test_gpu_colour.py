@@ -62,7 +62,7 @@ def test_colour_encodings(dev, kind, s):
     o8 = P.tonemap_global([x], torch.uint8, colour=True, saturation=s, **TM)[0][0]
     o16 = P.tonemap_global([x], torch.float16, colour=True, saturation=s, **TM)[0][0]
     name = "colour %s s=%g" % (kind, s)
-    check_u8(o8.cpu().numpy(), oracle.encode_u8(rgb_ref), name + " u8",
+    check_u8(o8.cpu().numpy(), rgb_ref, name + " u8",
              max_fraction=U8_COLOUR_FRACTION)
     check_f16(o16.cpu().numpy(), oracle.encode_f16(rgb_ref), name + " f16")
 

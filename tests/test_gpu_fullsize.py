@@ -26,7 +26,7 @@ import torch
 import oracle
 import paper_2108_13656_amd as P
 import synth
-from gpuhelp import check_f32, check_u8, need_gpu, report, to_dev
+from gpuhelp import check_f32, check_u8, need_gpu, report, to_dev, u8_mismatches_at_ties
 
 pytestmark = pytest.mark.gpu
 WORKERS = min(16, os.cpu_count() or 1)
@@ -79,8 +79,10 @@ def test_video_batch_every_pixel(dev, lut):
         want = lut[_codes(f)]
         err = np.abs(b.cpu().numpy().astype(np.float64) - want / 255.0)
         worst = max(worst, float(err.max()))
-        d = np.abs(a.cpu().numpy().astype(np.int32) - oracle.encode_u8(want / 255.0).astype(np.int32))
+        codes = a.cpu().numpy()
+        d = np.abs(codes.astype(np.int32) - oracle.encode_u8(want / 255.0).astype(np.int32))
         assert d.max() <= 1
+        u8_mismatches_at_ties(codes, want / 255.0)
         off += int(np.count_nonzero(d))
         total += d.size
     report("video batch: %d px, max |dL| %.3e, u8 codes off by one: %d (fraction %.3e)" %
@@ -134,9 +136,10 @@ def test_sdr_tonemap_every_pixel(dev, lut):
         assert st[i]["count"] == ref["count"]
         worst_l = max(worst_l, float(np.max(np.abs(lh[i].cpu().numpy() - lhat))))
         t_ref = oracle.tonemap_curve(lhat, ref["mu"], ref["sigma"], **TM)
-        d = np.abs(outs[i].cpu().numpy().astype(np.int32) -
-                   oracle.encode_u8(t_ref).astype(np.int32))
+        codes = outs[i].cpu().numpy()
+        d = np.abs(codes.astype(np.int32) - oracle.encode_u8(t_ref).astype(np.int32))
         assert d.max() <= 1, i
+        u8_mismatches_at_ties(codes, t_ref)
         off += int(np.count_nonzero(d))
         total += d.size
     report("sdr tone map 8x1080p + 8x2160p: max |d mu|, |d sigma|/sigma %.2e, max |dLhat| %.2e, "
@@ -166,6 +169,7 @@ def test_hdr_colour_tonemap_full(dev, s):
         got = outs[i].view(-1, 3)[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.int32)
         d = np.abs(got - oracle.encode_u8(want).astype(np.int32))
         assert d.max() <= 1, i
+        u8_mismatches_at_ties(got, want)
         off += int(np.count_nonzero(d))
         total += d.size
     report("hdr colour tone map 16x4096^2 -> u8 RGB, s=%g: %d sampled codes, %d off by one "

@@ -61,7 +61,7 @@ def test_local_encodings_and_lhat(dev, kind):
     x = to_dev(img, dev)
     o8, l8, _ = P.tonemap_local([x], torch.uint8, torch.float32, strength=0.7, **TM)
     o16 = P.tonemap_local([x], torch.float16, strength=0.7, **TM)[0][0]
-    check_u8(o8[0].cpu().numpy(), oracle.encode_u8(t_ref), "local %s u8" % kind,
+    check_u8(o8[0].cpu().numpy(), t_ref, "local %s u8" % kind,
              max_fraction=1e-3)
     check_f16(o16.cpu().numpy(), oracle.encode_f16(t_ref), "local %s f16" % kind)
     check_f32(l8[0].cpu().numpy(), oracle.decolorize(img), "local %s lhat" % kind,
@@ -129,7 +129,7 @@ def test_local_colour_vs_oracle(dev, kind, shape, s):
     assert got.shape == (h, w, 3)
     check_f32(got.cpu().numpy(), rgb_ref, "local colour %s %dx%d s=%g" % (kind, h, w, s))
     g8 = P.tonemap_local([x], torch.uint8, colour=True, strength=0.6, saturation=s, **TM)[0][0]
-    check_u8(g8.cpu().numpy(), oracle.encode_u8(rgb_ref), "local colour u8", max_fraction=2e-3)
+    check_u8(g8.cpu().numpy(), rgb_ref, "local colour u8", max_fraction=2e-3)
 
 
 def test_local_gray_and_colour_in_one_call(dev):
