@@ -5,6 +5,7 @@
 // capture, the autotuner and the continuous-batching server.
 #include "../../include/decolor.h"
 #include "dc_internal.h"
+#include "serve_policy.h"
 
 #include <algorithm>
 #include <chrono>
@@ -1406,8 +1407,7 @@ struct dc_server {
     dc_ctx *ctx = nullptr;
     dc_server_config cfg{};
     char *arena = nullptr;
-    size_t arena_bytes = 0;
-    std::map<size_t, size_t> free_blocks; // offset -> size
+    dc::Arena blocks; // offsets into `arena`
     std::deque<Req> waiting, admitted;
     std::vector<Lane> lanes;
     std::vector<dc_completion> done;
@@ -1417,44 +1417,9 @@ struct dc_server {
 
 namespace {
 
-constexpr size_t kGranule = 256;
-
 double server_now(const dc_server *sv)
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
-}
-
-bool arena_alloc(dc_server *sv, size_t bytes, size_t *off)
-{
-    for (auto it = sv->free_blocks.begin(); it != sv->free_blocks.end(); ++it) {
-        if (it->second >= bytes) {
-            *off = it->first;
-            const size_t rest = it->second - bytes;
-            const size_t at = it->first + bytes;
-            sv->free_blocks.erase(it);
-            if (rest)
-                sv->free_blocks[at] = rest;
-            return true;
-        }
-    }
-    return false;
-}
-
-void arena_free(dc_server *sv, size_t off, size_t bytes)
-{
-    auto it = sv->free_blocks.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != sv->free_blocks.end() && it->first + it->second == next->first) {
-        it->second += next->second;
-        sv->free_blocks.erase(next);
-    }
-    if (it != sv->free_blocks.begin()) {
-        auto prev = std::prev(it);
-        if (prev->first + prev->second == it->first) {
-            prev->second += it->second;
-            sv->free_blocks.erase(it);
-        }
-    }
 }
 
 // Bytes of a server-allocated output. Rows are packed (pitch = row bytes), so a
@@ -1463,16 +1428,14 @@ size_t out_bytes(const dc_image &m, int64_t *pitch)
 {
     const int64_t ch = (m.flags & DC_IMG_RGB_OUT) ? 3 : 1;
     *pitch = ch * dc::elem_size(m.dst_dtype) * m.width;
-    const size_t b = (size_t)*pitch * (size_t)m.height;
-    return (b + kGranule - 1) / kGranule * kGranule;
+    return dc::granules((size_t)*pitch * (size_t)m.height);
 }
 
 // Bytes of the device copy of a host input (rows packed), granule-rounded.
 size_t in_bytes(const dc_image &m, int64_t *pitch)
 {
     *pitch = 3 * dc::elem_size(m.src_dtype) * m.width;
-    const size_t b = (size_t)*pitch * (size_t)m.height;
-    return (b + kGranule - 1) / kGranule * kGranule;
+    return dc::granules((size_t)*pitch * (size_t)m.height);
 }
 
 void complete(dc_server *sv, const dc_server::Req &q, int status, int batch, double t_done)
@@ -1499,7 +1462,7 @@ int fail_lane(dc_server *sv, dc_server::Lane &ln, int status)
     const double t = server_now(sv);
     for (auto &r : ln.batch) {
         if (r.owned)
-            arena_free(sv, r.off, r.bytes);
+            sv->blocks.release(r.off, r.bytes);
         complete(sv, r, status, 0, t);
     }
     ln.batch.clear();
@@ -1521,46 +1484,41 @@ int server_step(dc_server *sv)
         const double t = server_now(sv);
         for (auto &r : ln.batch) {
             if (r.owned)
-                arena_free(sv, r.off, r.bytes);
+                sv->blocks.release(r.off, r.bytes);
             complete(sv, r, DC_OK, (int)ln.batch.size(), t);
         }
         ln.batch.clear();
         ln.busy = false;
     }
-    // 2. admit in FIFO order while inputs copies and outputs fit
-    while (!sv->waiting.empty()) {
-        dc_server::Req &q = sv->waiting.front();
-        const bool host = (q.r.img.flags & DC_IMG_HOST_SRC) != 0;
-        if (q.r.img.dst && !host) {
-            q.t_admit = server_now(sv);
-            sv->admitted.push_back(q);
-            sv->waiting.pop_front();
-            continue;
-        }
-        int64_t in_pitch = 0, out_pitch = 0;
-        const size_t ib = host ? in_bytes(q.r.img, &in_pitch) : 0;
-        const size_t ob = q.r.img.dst ? 0 : out_bytes(q.r.img, &out_pitch);
-        const size_t bytes = ib + ob;
-        if (bytes > sv->arena_bytes) {
-            complete(sv, q, DC_ERR_NO_MEMORY, 0, server_now(sv));
-            sv->waiting.pop_front();
-            continue;
-        }
-        size_t off = 0;
-        if (!arena_alloc(sv, bytes, &off))
-            break;
-        q.off = off;
-        q.bytes = bytes;
-        q.in_bytes = ib;
-        q.owned = true;
-        if (!q.r.img.dst) {
-            q.r.img.dst = sv->arena + off + ib;
-            q.r.img.dst_pitch = out_pitch;
-        }
-        q.t_admit = server_now(sv);
-        sv->admitted.push_back(q);
-        sv->waiting.pop_front();
-    }
+    // 2. admit in FIFO order while input copies and outputs fit
+    const double t_admit = server_now(sv);
+    dc::admit_fifo(
+        sv->waiting, sv->admitted, sv->blocks,
+        [](const dc_server::Req &q) -> size_t {
+            // a device input with a caller output takes no budget
+            int64_t pitch = 0;
+            const bool host = (q.r.img.flags & DC_IMG_HOST_SRC) != 0;
+            return (host ? in_bytes(q.r.img, &pitch) : 0) +
+                   (q.r.img.dst ? 0 : out_bytes(q.r.img, &pitch));
+        },
+        [&](dc_server::Req &q, size_t off, size_t bytes) {
+            q.t_admit = t_admit;
+            if (!bytes)
+                return;
+            int64_t in_pitch = 0, out_pitch = 0;
+            const size_t ib =
+                (q.r.img.flags & DC_IMG_HOST_SRC) ? in_bytes(q.r.img, &in_pitch) : 0;
+            q.off = off;
+            q.bytes = bytes;
+            q.in_bytes = ib;
+            q.owned = true;
+            if (!q.r.img.dst) {
+                (void)out_bytes(q.r.img, &out_pitch);
+                q.r.img.dst = sv->arena + off + ib;
+                q.r.img.dst_pitch = out_pitch;
+            }
+        },
+        [&](const dc_server::Req &q) { complete(sv, q, DC_ERR_NO_MEMORY, 0, server_now(sv)); });
     // 3. launch admitted work on idle lanes
     for (auto &ln : sv->lanes) {
         if (sv->admitted.empty())
@@ -1644,12 +1602,12 @@ int dc_server_create(dc_ctx *ctx, const dc_server_config *cfg, dc_server **out)
         return fail(DC_ERR_NO_MEMORY, "server allocation failed");
     sv->ctx = ctx;
     sv->cfg = *cfg;
-    sv->arena_bytes = (size_t)cfg->budget_bytes / kGranule * kGranule;
-    if (hipMalloc((void **)&sv->arena, sv->arena_bytes) != hipSuccess) {
+    const size_t arena_bytes = (size_t)cfg->budget_bytes / dc::kGranule * dc::kGranule;
+    if (hipMalloc((void **)&sv->arena, arena_bytes) != hipSuccess) {
         delete sv;
         return fail(DC_ERR_NO_MEMORY, "server arena allocation failed");
     }
-    sv->free_blocks[0] = sv->arena_bytes;
+    sv->blocks.reset(arena_bytes);
     sv->lanes.resize((size_t)cfg->max_inflight);
     for (auto &ln : sv->lanes) {
         if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess ||
