@@ -228,7 +228,7 @@ def serve_leg(args, P, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus %d is not supported by this build" % args.gpus,
+        print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -360,7 +360,7 @@ def main():
                                        "max_abs_err_T_vs_unrounded_radiance": err_exact}
             log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
             # Eqs. (1)-(6) alone, as in the paper's run-time table: one thread,
-            # and the oracle's row split over the host cores this box gives one
+            # and the oracle's row split over the host cores a one-GPU share has
             # GPU (16).
             ncores = min(WORKERS, 16)
             t0 = time.time()

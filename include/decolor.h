@@ -69,7 +69,7 @@ extern "C" {
 /* Status codes. */
 #define DC_OK 0
 #define DC_ERR_INVALID_ARG (-1) /* null pointer, bad size, pitch, dtype or parameter */
-#define DC_ERR_UNSUPPORTED (-2) /* a combination this build does not implement */
+#define DC_ERR_UNSUPPORTED (-2) /* a combination the library does not implement */
 #define DC_ERR_ALIAS (-3)       /* an output overlaps an input or another output */
 #define DC_ERR_NO_MEMORY (-4)   /* workspace allocation failed */
 #define DC_ERR_HIP (-5)         /* a HIP runtime call failed */
