@@ -360,7 +360,7 @@ def main():
                                        "max_abs_err_T_vs_unrounded_radiance": err_exact}
             log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
             # Eqs. (1)-(6) alone, as in the paper's run-time table: one thread,
-            # and the oracle's row split over the host cores a one-GPU share has
+            # and the oracle's row split over the host cores that go with one
             # GPU (16).
             ncores = min(WORKERS, 16)
             t0 = time.time()
