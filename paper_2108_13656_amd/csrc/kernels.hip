@@ -1354,17 +1354,17 @@ __global__ __launch_bounds__(64) void k_ltm_tables(const DevImage *__restrict__ 
     coef[g * kLtmBins + b] = c;
 }
 
-// Corner indices in the 3 x 3 tile neighbourhood and the weight of the second
-// corner along one axis, for tile-local coordinate p of tile t in a grid of n:
-// the pixel lies between the centres of tiles t - 1 and t (p < 32) or t and
-// t + 1, at distance (p + 1/2) / 64 -/+ 1/2 from the first (exact in FP32);
-// at the grid's edges it takes tile t alone.
-__device__ __forceinline__ void ltm_axis(int p, int t, int n, int &c0, int &c1, float &w)
+// First corner index in the 3 x 3 tile neighbourhood (the second is the next
+// one) and the weight of the second corner along one axis, for tile-local
+// coordinate p of tile t in a grid of n: the pixel lies between the centres of
+// tiles t - 1 and t (p < 32) or t and t + 1, at distance (p + 1/2) / 64 -/+ 1/2
+// from the first (exact in FP32); at the grid's edges it takes tile t alone
+// (weight 0 on the second corner, which then may lie outside the grid).
+__device__ __forceinline__ void ltm_axis(int p, int t, int n, int &c0, float &w)
 {
     const bool lower = p < kLtmTile / 2;
     const bool edge = lower ? t == 0 : t == n - 1;
     c0 = (lower && !edge) ? 0 : 1;
-    c1 = edge ? 1 : c0 + 1;
     w = edge ? 0.0f : fmaf((float)p + 0.5f, 1.0f / kLtmTile, lower ? 0.5f : -0.5f);
 }
 
@@ -1385,6 +1385,9 @@ __device__ __forceinline__ void ltm_stage(const DevImage &im, const LtmRef &r,
         if (sx >= 0 && sx < r.nx && sy >= 0 && sy < r.ny) {
             const LtmCoef c = coef[(im.tile_begin + (int64_t)sy * r.nx + sx) * kLtmBins + bin];
             lds[idx] = LtmLds{c.a, c.b, c.c};
+        } else {
+            // read only with weight 0 at the grid's edges: any finite value
+            lds[idx] = LtmLds{0.0f, 0.0f, 0.0f};
         }
     }
     __syncthreads();
@@ -1392,21 +1395,21 @@ __device__ __forceinline__ void ltm_stage(const DevImage &im, const LtmRef &r,
 
 // T of one pixel from its x2 = log2(Lhat + eps): the global curve T_g, the
 // bilinear blend T_l of the four corner tiles' curves at u, and
-// T = T_g + strength (T_l - T_g). cy0/cy1/wy: the row's axis; cx0/cx1/wx:
-// the column's.
+// T = T_g + strength (T_l - T_g). cy0/wy: the row's axis; cx0/wx: the
+// column's.
 __device__ __forceinline__ float ltm_value(float x2, float lo2, TmArgs tm, Curve cv,
-                                           const LtmLds *lds, int cx0, int cx1, float wx,
-                                           int cy0, int cy1, float wy)
+                                           const LtmLds *lds, int cx0, float wx, int cy0, float wy)
 {
     const float tg = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
     const float u = ltm_u(x2, lo2);
     const int k = min((int)u, kLtmBins - 2);
     const float f = u - (float)k;
-    auto F = [&](int cx, int cy) {
-        const LtmLds c = lds[(cy * 3 + cx) * kLtmBins + k];
-        return fmaf(f, fmaf(f, c.c, c.b), c.a);
-    };
-    const float f00 = F(cx0, cy0), f10 = F(cx1, cy0), f01 = F(cx0, cy1), f11 = F(cx1, cy1);
+    // the four corners' entries for bin k sit at fixed distances from the
+    // first one, so a single address serves all four LDS reads
+    const LtmLds *c = lds + (cy0 * 3 + cx0) * kLtmBins + k;
+    auto F = [&](const LtmLds &e) { return fmaf(f, fmaf(f, e.c, e.b), e.a); };
+    const float f00 = F(c[0]), f10 = F(c[kLtmBins]), f01 = F(c[3 * kLtmBins]),
+                f11 = F(c[4 * kLtmBins]);
     const float top = fmaf(wx, f10 - f00, f00);
     const float bot = fmaf(wx, f11 - f01, f01);
     const float tl = fmaf(wy, bot - top, top);
@@ -1441,26 +1444,26 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
         ltm_stage(im, r, coef, lds);
         int col0, row0;
         ltm_slot<PPU>(0, 0, row0, col0);
-        int cx0[PPU], cx1[PPU];
+        int cx0[PPU];
         float wx[PPU];
 #pragma unroll
         for (int j = 0; j < PPU; ++j)
-            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], cx1[j], wx[j]);
+            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], wx[j]);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
             if (row < r.bh) {
-                int cy0, cy1;
+                int cy0;
                 float wy;
-                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                ltm_axis(row, r.ty, r.ny, cy0, wy);
                 float v[PPU];
 #pragma unroll
                 for (int j = 0; j < PPU; ++j) {
                     const float l = lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
                                              chan<SRC>(w[i], 3 * j + 2), im.k);
-                    v[j] = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j], cx1[j],
-                                     wx[j], cy0, cy1, wy);
+                    v[j] = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j], wx[j],
+                                     cy0, wy);
                 }
                 store_unit<PPU, false, true>(r.dst + row * r.dp, im.dst_dtype, col, v, e);
             }
@@ -1474,13 +1477,13 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
             if (row < r.bh && col < r.bw) {
                 float l;
                 lum_at_px<SRC>(r.src + row * r.sp + col * 3 * ES, im.k, l);
-                int cx0, cx1, cy0, cy1;
+                int cx0, cy0;
                 float wx, wy;
-                ltm_axis(col, r.tx, r.nx, cx0, cx1, wx);
-                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                ltm_axis(col, r.tx, r.nx, cx0, wx);
+                ltm_axis(row, r.ty, r.ny, cy0, wy);
                 store_px<false, true>(r.dst + row * r.dp, im.dst_dtype, col,
                                       ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0,
-                                                cx1, wx, cy0, cy1, wy),
+                                                wx, cy0, wy),
                                       e);
             }
         }
@@ -1517,24 +1520,24 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
         ltm_stage(im, r, coef, lds);
         int col0, row0;
         ltm_slot<PPU>(0, 0, row0, col0);
-        int cx0[PPU], cx1[PPU];
+        int cx0[PPU];
         float wx[PPU];
 #pragma unroll
         for (int j = 0; j < PPU; ++j)
-            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], cx1[j], wx[j]);
+            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], wx[j]);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
             if (row < r.bh) {
-                int cy0, cy1;
+                int cy0;
                 float wy;
-                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                ltm_axis(row, r.ty, r.ny, cy0, wy);
                 unsigned o[PPU];
 #pragma unroll
                 for (int j = 0; j < PPU; ++j)
                     o[j] = __builtin_bit_cast(unsigned, ltm_value(w[i][j], lo2, tm, cv, lds, cx0[j],
-                                                                  cx1[j], wx[j], cy0, cy1, wy));
+                                                                  wx[j], cy0, wy));
                 put(gpw<u32x4>(r.dst + row * r.dp + col * 4), u32x4{o[0], o[1], o[2], o[3]});
             }
         }
@@ -1546,11 +1549,11 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
             ltm_slot<PPU>(sl / PPU, sl % PPU, row, col);
             if (row < r.bh && col < r.bw) {
                 DC_GLOBAL float *p = gpw<float>(r.dst + row * r.dp) + col;
-                int cx0, cx1, cy0, cy1;
+                int cx0, cy0;
                 float wx, wy;
-                ltm_axis(col, r.tx, r.nx, cx0, cx1, wx);
-                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
-                *p = ltm_value(*p, lo2, tm, cv, lds, cx0, cx1, wx, cy0, cy1, wy);
+                ltm_axis(col, r.tx, r.nx, cx0, wx);
+                ltm_axis(row, r.ty, r.ny, cy0, wy);
+                *p = ltm_value(*p, lo2, tm, cv, lds, cx0, wx, cy0, wy);
             }
         }
     }
@@ -1619,19 +1622,19 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
         ltm_stage(im, r, coef, lds);
         int col0, row0;
         ltm_slot<PPU>(0, 0, row0, col0);
-        int cx0[PPU], cx1[PPU];
+        int cx0[PPU];
         float wx[PPU];
 #pragma unroll
         for (int j = 0; j < PPU; ++j)
-            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], cx1[j], wx[j]);
+            ltm_axis(col0 + j, r.tx, r.nx, cx0[j], wx[j]);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             int row, col;
             ltm_slot<PPU>(i, 0, row, col);
             if (row < r.bh) {
-                int cy0, cy1;
+                int cy0;
                 float wy;
-                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
+                ltm_axis(row, r.ty, r.ny, cy0, wy);
                 float o[3 * PPU];
 #pragma unroll
                 for (int j = 0; j < PPU; ++j) {
@@ -1639,7 +1642,7 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
                                 B = chan<SRC>(w[i], 3 * j + 2);
                     const float l = lum<SRC>(R, G, B, im.k);
                     const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j],
-                                              cx1[j], wx[j], cy0, cy1, wy);
+                                              wx[j], cy0, wy);
                     colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, &o[3 * j]);
                 }
                 store_rgb_unit<PPU>(dst + row * r.dp, dt, col, o);
@@ -1655,12 +1658,12 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
                 float R, G, B;
                 load_px<SRC>(r.src + row * r.sp + col * 3 * ES, R, G, B);
                 const float l = lum<SRC>(R, G, B, im.k);
-                int cx0, cx1, cy0, cy1;
+                int cx0, cy0;
                 float wx, wy;
-                ltm_axis(col, r.tx, r.nx, cx0, cx1, wx);
-                ltm_axis(row, r.ty, r.ny, cy0, cy1, wy);
-                const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0, cx1, wx,
-                                          cy0, cy1, wy);
+                ltm_axis(col, r.tx, r.nx, cx0, wx);
+                ltm_axis(row, r.ty, r.ny, cy0, wy);
+                const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0, wx,
+                                          cy0, wy);
                 float o[3];
                 colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, o);
 #pragma unroll
