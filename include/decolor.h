@@ -53,7 +53,9 @@
  * aborts and no C++ exception crosses this interface. dc_last_error_message()
  * gives a thread-local description of the last failure.
  *
- * Threads. A context is not thread-safe; use one per host thread.
+ * Threads. A context is not thread-safe: use one per host thread, or
+ * serialise the calls that use it (its plans' and servers' calls included),
+ * as the Python binding does with one lock per device context.
  */
 #ifndef DECOLOR_H
 #define DECOLOR_H

@@ -10,6 +10,7 @@ present, every compute call raises.
 """
 import ctypes
 import os
+import threading
 
 import torch
 
@@ -187,11 +188,15 @@ def _check(status):
 
 
 class Context:
-    """Owns one ``dc_ctx`` (workspace ring) on one device."""
+    """Owns one ``dc_ctx`` (workspace ring) on one device. A dc_ctx serves one
+    host thread at a time and ctypes releases the GIL during a call, so every
+    call that uses the context (directly, or through a plan or server made
+    from it) holds ``lock``."""
 
     def __init__(self, device=None):
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.device = dev
+        self.lock = threading.RLock()
         self._h = ctypes.c_void_p()
         with torch.cuda.device(dev):
             _check(lib().dc_create(ctypes.byref(self._h), dev.index))
@@ -200,10 +205,16 @@ class Context:
     def handle(self):
         return self._h
 
+    def call(self, fn, *args):
+        """fn(handle, *args) under the lock; raises DecolorError on failure."""
+        with self.lock:
+            _check(fn(self._h, *args))
+
     def close(self):
-        if self._h:
-            lib().dc_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        with self.lock:
+            if self._h:
+                lib().dc_destroy(self._h)
+                self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -213,14 +224,23 @@ class Context:
 
 
 _contexts = {}
+_contexts_lock = threading.Lock()
 
 
 def context(device=None):
     """The shared context of a device (created on first use)."""
-    idx = torch.cuda.current_device() if device is None else torch.device(device).index
-    if idx not in _contexts:
-        _contexts[idx] = Context(idx)
-    return _contexts[idx]
+    if device is None:
+        idx = None
+    elif isinstance(device, int):
+        idx = device
+    else:
+        idx = torch.device(device).index
+    if idx is None:
+        idx = torch.cuda.current_device()
+    with _contexts_lock:
+        if idx not in _contexts:
+            _contexts[idx] = Context(idx)
+        return _contexts[idx]
 
 
 # ------------------------------------------------------------- marshalling
@@ -311,9 +331,8 @@ def decolorize(x, out_dtype=torch.float32, out2_dtype=None, beta_r=BETA_R, beta_
         out2 = _alloc(x, out2_dtype, h, w)
     d = _image(x, out, out2)
     p = _params(beta_r, beta_k)
-    ctx = context(x.device)
-    _check(lib().dc_decolorize(ctx.handle, ctypes.byref(d), ctypes.byref(p),
-                               _stream_ptr(stream, x.device)))
+    context(x.device).call(lib().dc_decolorize, ctypes.byref(d), ctypes.byref(p),
+                           _stream_ptr(stream, x.device))
     return out if out2 is None else (out, out2)
 
 
@@ -339,8 +358,8 @@ def decolorize_batch(xs, out_dtype=torch.float32, out2_dtype=None, beta_r=BETA_R
         outs2 = [_alloc(x, out2_dtype, x.shape[0], x.shape[1]) for x in xs]
     arr = _image_array(xs, outs, outs2)
     p = _params(beta_r, beta_k)
-    _check(lib().dc_decolorize_batch(context(dev).handle, arr, len(xs), ctypes.byref(p),
-                                     _stream_ptr(stream, dev)))
+    context(dev).call(lib().dc_decolorize_batch, arr, len(xs), ctypes.byref(p),
+                      _stream_ptr(stream, dev))
     return outs if outs2 is None else list(zip(outs, outs2))
 
 
@@ -357,8 +376,7 @@ def decolorize_betas(xs, betas, out_dtype=torch.float32, outs=None, stream=None)
         outs = [_alloc(x, out_dtype, x.shape[0], x.shape[1]) for x in xs]
     arr = _image_array(xs, outs, None)
     pa = (DcParams * len(xs))(*[DcParams(float(a), float(b)) for a, b in betas])
-    _check(lib().dc_decolorize_batch_betas(context(dev).handle, arr, len(xs), pa,
-                                           _stream_ptr(stream, dev)))
+    context(dev).call(lib().dc_decolorize_batch_betas, arr, len(xs), pa, _stream_ptr(stream, dev))
     return outs
 
 
@@ -389,8 +407,8 @@ def channel_batch(xs, channel, out_dtype=torch.float32, out2_dtype=None, outs=No
     if outs2 is None and out2_dtype is not None:
         outs2 = [_alloc(x, out2_dtype, x.shape[0], x.shape[1]) for x in xs]
     arr = _image_array(xs, outs, outs2)
-    _check(lib().dc_channel_batch(context(dev).handle, arr, len(xs), CHANNELS[channel],
-                                  _stream_ptr(stream, dev)))
+    context(dev).call(lib().dc_channel_batch, arr, len(xs), CHANNELS[channel],
+                      _stream_ptr(stream, dev))
     return outs if outs2 is None else list(zip(outs, outs2))
 
 
@@ -416,10 +434,9 @@ def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, 
     arr = _image_array(xs, outs, lhats)
     p = _params(beta_r, beta_k)
     tm = DcTmParams(eps, contrast, sigma_floor, saturation, TM_LOCAL_STRENGTH)
-    _check(lib().dc_tonemap_global(context(dev).handle, arr, len(xs), ctypes.byref(p),
-                                   ctypes.byref(tm),
-                                   ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
-                                   _stream_ptr(stream, dev)))
+    context(dev).call(lib().dc_tonemap_global, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
+                      ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                      _stream_ptr(stream, dev))
     return outs, lhats, stats
 
 
@@ -444,10 +461,9 @@ def tonemap_local(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, b
     arr = _image_array(xs, outs, lhats)
     p = _params(beta_r, beta_k)
     tm = DcTmParams(eps, contrast, sigma_floor, saturation, strength)
-    _check(lib().dc_tonemap_local(context(dev).handle, arr, len(xs), ctypes.byref(p),
-                                  ctypes.byref(tm),
-                                  ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
-                                  _stream_ptr(stream, dev)))
+    context(dev).call(lib().dc_tonemap_local, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
+                      ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                      _stream_ptr(stream, dev))
     return outs, lhats, stats
 
 
@@ -488,17 +504,20 @@ class Plan:
         tm = (DcTmParams(eps, contrast, sigma_floor, saturation, local_strength)
               if kind in (PLAN_TONEMAP, PLAN_LOCAL) else None)
         self._h = ctypes.c_void_p()
-        _check(lib().dc_plan_create(context(self.device).handle, kind, arr, len(xs),
-                                    ctypes.byref(p), ctypes.byref(tm) if tm is not None else None,
-                                    ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
-                                    PLAN_GRAPH if graph else 0, ctypes.byref(self._h)))
+        self._ctx = context(self.device)
+        self._ctx.call(lib().dc_plan_create, kind, arr, len(xs), ctypes.byref(p),
+                       ctypes.byref(tm) if tm is not None else None,
+                       ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                       PLAN_GRAPH if graph else 0, ctypes.byref(self._h))
 
     def run(self, stream=None):
-        _check(lib().dc_plan_run(self._h, _stream_ptr(stream, self.device)))
+        with self._ctx.lock:
+            _check(lib().dc_plan_run(self._h, _stream_ptr(stream, self.device)))
 
     def close(self):
         if self._h:
-            lib().dc_plan_destroy(self._h)
+            with self._ctx.lock:
+                lib().dc_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -562,24 +581,27 @@ class Server:
                              DcTmParams(eps, contrast, sigma_floor, saturation,
                                         TM_LOCAL_STRENGTH))
         self._h = ctypes.c_void_p()
-        _check(lib().dc_server_create(context(self.device).handle, ctypes.byref(cfg),
-                                      ctypes.byref(self._h)))
+        self._ctx = context(self.device)
+        self._ctx.call(lib().dc_server_create, ctypes.byref(cfg), ctypes.byref(self._h))
 
     def submit(self, reqs, t_submit=-1.0):
         arr = (DcRequest * len(reqs))(*reqs)
-        _check(lib().dc_server_submit(self._h, arr, len(reqs), t_submit))
+        with self._ctx.lock:
+            _check(lib().dc_server_submit(self._h, arr, len(reqs), t_submit))
 
     def step(self):
-        n = lib().dc_server_step(self._h)
-        if n < 0:
-            _check(n)
+        with self._ctx.lock:
+            n = lib().dc_server_step(self._h)
+            if n < 0:
+                _check(n)
         return n
 
     def poll(self, cap=4096):
         buf = (DcCompletion * cap)()
-        n = lib().dc_server_poll(self._h, buf, cap)
-        if n < 0:
-            _check(n)
+        with self._ctx.lock:
+            n = lib().dc_server_poll(self._h, buf, cap)
+            if n < 0:
+                _check(n)
         return [buf[i] for i in range(n)]
 
     def clock(self):
@@ -591,12 +613,14 @@ class Server:
         arr = (DcRequest * n)(*reqs)
         times = (ctypes.c_double * n)(*arrivals)
         out = (DcCompletion * n)()
-        _check(lib().dc_server_replay(self._h, arr, times, n, out))
+        with self._ctx.lock:
+            _check(lib().dc_server_replay(self._h, arr, times, n, out))
         return [out[i] for i in range(n)]
 
     def close(self):
         if self._h:
-            lib().dc_server_destroy(self._h)
+            with self._ctx.lock:
+                lib().dc_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -608,13 +632,13 @@ class Server:
 
 def get_tuning(device=None):
     t = DcTuning()
-    _check(lib().dc_get_tuning(context(device).handle, ctypes.byref(t)))
+    context(device).call(lib().dc_get_tuning, ctypes.byref(t))
     return t.as_dict()
 
 
 def set_tuning(d, device=None):
     t = DcTuning.from_dict(d)
-    _check(lib().dc_set_tuning(context(device).handle, ctypes.byref(t)))
+    context(device).call(lib().dc_set_tuning, ctypes.byref(t))
 
 
 def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
@@ -628,22 +652,24 @@ def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EP
     p = _params(beta_r, beta_k)
     tm = DcTmParams(eps, contrast, sigma_floor, saturation, TM_LOCAL_STRENGTH)
     t = DcTuning()
-    _check(lib().dc_autotune(context(dev).handle, kind, arr, len(xs), ctypes.byref(p),
-                             ctypes.byref(tm), _stream_ptr(stream, dev), ctypes.byref(t)))
+    context(dev).call(lib().dc_autotune, kind, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
+                      _stream_ptr(stream, dev), ctypes.byref(t))
     return t.as_dict()
 
 
 def set_profiling(on, device=None):
     """Records per-kernel timing events on later calls of this device's context."""
-    _check(lib().dc_set_profiling(context(device).handle, 1 if on else 0))
+    context(device).call(lib().dc_set_profiling, 1 if on else 0)
 
 
 def last_timings(device=None, cap=8):
     """Per-kernel durations (ms) of the most recent profiled call."""
     buf = (ctypes.c_float * cap)()
-    n = lib().dc_last_timings(context(device).handle, buf, cap)
-    if n < 0:
-        _check(n)
+    ctx = context(device)
+    with ctx.lock:
+        n = lib().dc_last_timings(ctx.handle, buf, cap)
+        if n < 0:
+            _check(n)
     return [float(buf[i]) for i in range(n)]
 
 
