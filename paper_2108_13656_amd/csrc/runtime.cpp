@@ -14,6 +14,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <utility>
 #include <vector>
@@ -26,6 +28,31 @@ int fail(int status, const std::string &msg)
 {
     g_last_error = msg;
     return status;
+}
+
+// Runs the body of an entry point so that no C++ exception crosses the C
+// interface: a failed host allocation becomes DC_ERR_NO_MEMORY, a size beyond
+// the host containers' limits DC_ERR_INVALID_ARG.
+template <class F>
+int guarded(F &&body) noexcept
+{
+    auto note = [](int status, const char *msg) noexcept {
+        try {
+            g_last_error = msg;
+        } catch (...) {
+            g_last_error.clear();
+        }
+        return status;
+    };
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return note(DC_ERR_NO_MEMORY, "host memory allocation failed");
+    } catch (const std::length_error &) {
+        return note(DC_ERR_INVALID_ARG, "sizes exceed what the host containers hold");
+    } catch (...) {
+        return note(DC_ERR_INVALID_ARG, "unexpected host exception");
+    }
 }
 
 bool dtype_ok(int32_t d) { return d == DC_U8 || d == DC_F16 || d == DC_F32; }
@@ -919,464 +946,498 @@ const char *dc_last_error_message(void) { return g_last_error.c_str(); }
 
 int dc_validate(const dc_image *imgs, int32_t n, const dc_params *params, const dc_tm_params *tm)
 {
-    g_last_error.clear();
-    int rc = validate_params(params);
-    if (rc == DC_OK)
-        rc = validate_tm(tm);
-    if (rc == DC_OK)
-        rc = validate_images(imgs, n, tm != nullptr ? DC_IMG_RGB_OUT : 0);
-    return rc;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = validate_params(params);
+        if (rc == DC_OK)
+            rc = validate_tm(tm);
+        if (rc == DC_OK)
+            rc = validate_images(imgs, n, tm != nullptr ? DC_IMG_RGB_OUT : 0);
+        return rc;
+    });
 }
 
 int dc_create(dc_ctx **out, int device)
 {
-    g_last_error.clear();
-    if (!out)
-        return fail(DC_ERR_INVALID_ARG, "ctx out-pointer is NULL");
-    *out = nullptr;
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
-        return fail(DC_ERR_NO_DEVICE, "no HIP device is visible");
-    if (device < 0 || device >= count)
-        return fail(DC_ERR_NO_DEVICE, "device index out of range");
-    hipError_t e = hipSetDevice(device);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipSetDevice");
-    dc_ctx *ctx = new (std::nothrow) dc_ctx();
-    if (!ctx)
-        return fail(DC_ERR_NO_MEMORY, "context allocation failed");
-    ctx->device = device;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
-        cus > 0)
-        ctx->num_cu = cus;
-    for (auto &s : ctx->slots) {
-        e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            dc_destroy(ctx);
-            return hip_fail(e, "hipEventCreate");
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!out)
+            return fail(DC_ERR_INVALID_ARG, "ctx out-pointer is NULL");
+        *out = nullptr;
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+            return fail(DC_ERR_NO_DEVICE, "no HIP device is visible");
+        if (device < 0 || device >= count)
+            return fail(DC_ERR_NO_DEVICE, "device index out of range");
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipSetDevice");
+        dc_ctx *ctx = new (std::nothrow) dc_ctx();
+        if (!ctx)
+            return fail(DC_ERR_NO_MEMORY, "context allocation failed");
+        ctx->device = device;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+            cus > 0)
+            ctx->num_cu = cus;
+        for (auto &s : ctx->slots) {
+            e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                dc_destroy(ctx);
+                return hip_fail(e, "hipEventCreate");
+            }
         }
-    }
-    *out = ctx;
-    return DC_OK;
+        *out = ctx;
+        return DC_OK;
+    });
 }
 
 int dc_destroy(dc_ctx *ctx)
 {
-    if (!ctx)
-        return DC_OK;
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    for (auto &s : ctx->slots) {
-        if (s.host)
-            (void)hipHostFree(s.host);
-        if (s.dev)
-            (void)hipFree(s.dev);
-        if (s.done)
-            (void)hipEventDestroy(s.done);
-    }
-    for (auto &e : ctx->prof)
-        if (e)
+    return guarded([&]() -> int {
+        if (!ctx)
+            return DC_OK;
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto &s : ctx->slots) {
+            if (s.host)
+                (void)hipHostFree(s.host);
+            if (s.dev)
+                (void)hipFree(s.dev);
+            if (s.done)
+                (void)hipEventDestroy(s.done);
+        }
+        for (auto &e : ctx->prof)
+            if (e)
+                (void)hipEventDestroy(e);
+        for (auto &e : ctx->fork)
             (void)hipEventDestroy(e);
-    for (auto &e : ctx->fork)
-        (void)hipEventDestroy(e);
-    if (ctx->side)
-        (void)hipStreamDestroy(ctx->side);
-    delete ctx;
-    return DC_OK;
+        if (ctx->side)
+            (void)hipStreamDestroy(ctx->side);
+        delete ctx;
+        return DC_OK;
+    });
 }
 
 int dc_get_tuning(dc_ctx *ctx, dc_tuning *out)
 {
-    g_last_error.clear();
-    if (!ctx || !out)
-        return fail(DC_ERR_INVALID_ARG, "context or output is NULL");
-    *out = to_public(ctx->tune);
-    return DC_OK;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!ctx || !out)
+            return fail(DC_ERR_INVALID_ARG, "context or output is NULL");
+        *out = to_public(ctx->tune);
+        return DC_OK;
+    });
 }
 
 int dc_set_tuning(dc_ctx *ctx, const dc_tuning *t)
 {
-    g_last_error.clear();
-    if (!ctx || !t)
-        return fail(DC_ERR_INVALID_ARG, "context or tuning is NULL");
-    if (!tune_ok(*t))
-        return fail(DC_ERR_INVALID_ARG, "groups must be 1, 2 or 4, grids per CU in [0, 64] and "
-                                        "tonemap_pipeline 0 or 1");
-    ctx->tune = from_public(*t);
-    return DC_OK;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!ctx || !t)
+            return fail(DC_ERR_INVALID_ARG, "context or tuning is NULL");
+        if (!tune_ok(*t))
+            return fail(DC_ERR_INVALID_ARG, "groups must be 1, 2 or 4, grids per CU in [0, 64] and "
+                                            "tonemap_pipeline 0 or 1");
+        ctx->tune = from_public(*t);
+        return DC_OK;
+    });
 }
 
 int dc_set_profiling(dc_ctx *ctx, int on)
 {
-    g_last_error.clear();
-    if (!ctx)
-        return fail(DC_ERR_INVALID_ARG, "context is NULL");
-    if (on) {
-        (void)hipSetDevice(ctx->device);
-        const int rc = ensure_prof_events(ctx);
-        if (rc != DC_OK)
-            return rc;
-    }
-    ctx->profiling = on != 0;
-    ctx->prof_used = 0;
-    return DC_OK;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!ctx)
+            return fail(DC_ERR_INVALID_ARG, "context is NULL");
+        if (on) {
+            (void)hipSetDevice(ctx->device);
+            const int rc = ensure_prof_events(ctx);
+            if (rc != DC_OK)
+                return rc;
+        }
+        ctx->profiling = on != 0;
+        ctx->prof_used = 0;
+        return DC_OK;
+    });
 }
 
 int dc_last_timings(dc_ctx *ctx, float *ms, int32_t cap)
 {
-    g_last_error.clear();
-    if (!ctx || (!ms && cap > 0) || cap < 0)
-        return fail(DC_ERR_INVALID_ARG, "bad context or output array");
-    if (ctx->prof_used < 2)
-        return 0;
-    hipError_t e = hipEventSynchronize(ctx->prof[ctx->prof_used - 1]);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipEventSynchronize");
-    int n = 0;
-    for (int i = 0; i + 1 < ctx->prof_used && n < cap; ++i, ++n) {
-        e = hipEventElapsedTime(&ms[n], ctx->prof[i], ctx->prof[i + 1]);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!ctx || (!ms && cap > 0) || cap < 0)
+            return fail(DC_ERR_INVALID_ARG, "bad context or output array");
+        if (ctx->prof_used < 2)
+            return 0;
+        hipError_t e = hipEventSynchronize(ctx->prof[ctx->prof_used - 1]);
         if (e != hipSuccess)
-            return hip_fail(e, "hipEventElapsedTime");
-    }
-    return n;
+            return hip_fail(e, "hipEventSynchronize");
+        int n = 0;
+        for (int i = 0; i + 1 < ctx->prof_used && n < cap; ++i, ++n) {
+            e = hipEventElapsedTime(&ms[n], ctx->prof[i], ctx->prof[i + 1]);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipEventElapsedTime");
+        }
+        return n;
+    });
 }
 
 int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, void *stream)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    if (!img)
-        return fail(DC_ERR_INVALID_ARG, "image is NULL");
-    rc = dc_validate(img, 1, params, nullptr);
-    if (rc != DC_OK)
-        return rc;
-    const int g = ctx->tune.groups[img->src_dtype];
-    const dc::DevImage d =
-        describe(*img, 0, (int64_t)dc::kBlock * g * dc::group_px(img->src_dtype), params);
-    const hipStream_t st = (hipStream_t)stream;
-    mark(ctx, true, 0, st);
-    hipError_t e = dc::launch_decolor_single(d, g, grid_blocks(ctx, ctx->tune.decolor_gpc), st);
-    if (e != hipSuccess)
-        return hip_fail(e, "decolorize launch");
-    mark(ctx, true, 1, st);
-    return DC_OK;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        if (!img)
+            return fail(DC_ERR_INVALID_ARG, "image is NULL");
+        rc = dc_validate(img, 1, params, nullptr);
+        if (rc != DC_OK)
+            return rc;
+        const int g = ctx->tune.groups[img->src_dtype];
+        const dc::DevImage d =
+            describe(*img, 0, (int64_t)dc::kBlock * g * dc::group_px(img->src_dtype), params);
+        const hipStream_t st = (hipStream_t)stream;
+        mark(ctx, true, 0, st);
+        hipError_t e = dc::launch_decolor_single(d, g, grid_blocks(ctx, ctx->tune.decolor_gpc), st);
+        if (e != hipSuccess)
+            return hip_fail(e, "decolorize launch");
+        mark(ctx, true, 1, st);
+        return DC_OK;
+    });
 }
 
 int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                         void *stream)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    rc = dc_validate(imgs, n, params, nullptr);
-    if (rc != DC_OK || n == 0)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    HostTable h;
-    build_table(imgs, n, params, kTabDecolor, ctx->tune, h);
-    dc_ctx::Slot *slot = nullptr;
-    DevBufs b;
-    rc = stage(ctx, h, st, &slot, &b);
-    if (rc != DC_OK)
-        return rc;
-    rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
-    if (rc != DC_OK)
-        return rc;
-    return release_slot(slot, st);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        rc = dc_validate(imgs, n, params, nullptr);
+        if (rc != DC_OK || n == 0)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        HostTable h;
+        build_table(imgs, n, params, kTabDecolor, ctx->tune, h);
+        dc_ctx::Slot *slot = nullptr;
+        DevBufs b;
+        rc = stage(ctx, h, st, &slot, &b);
+        if (rc != DC_OK)
+            return rc;
+        rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
+        if (rc != DC_OK)
+            return rc;
+        return release_slot(slot, st);
+    });
 }
 
 int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
                               const dc_params *betas, void *stream)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    if (betas)
-        for (int32_t i = 0; i < n && rc == DC_OK; ++i)
-            rc = validate_params(&betas[i]);
-    if (rc == DC_OK)
-        rc = dc_validate(imgs, n, nullptr, nullptr);
-    if (rc != DC_OK || n == 0)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    HostTable h;
-    build_table(imgs, n, nullptr, kTabDecolor, ctx->tune, h, betas);
-    dc_ctx::Slot *slot = nullptr;
-    DevBufs b;
-    rc = stage(ctx, h, st, &slot, &b);
-    if (rc != DC_OK)
-        return rc;
-    rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
-    if (rc != DC_OK)
-        return rc;
-    return release_slot(slot, st);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        if (betas)
+            for (int32_t i = 0; i < n && rc == DC_OK; ++i)
+                rc = validate_params(&betas[i]);
+        if (rc == DC_OK)
+            rc = dc_validate(imgs, n, nullptr, nullptr);
+        if (rc != DC_OK || n == 0)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        HostTable h;
+        build_table(imgs, n, nullptr, kTabDecolor, ctx->tune, h, betas);
+        dc_ctx::Slot *slot = nullptr;
+        DevBufs b;
+        rc = stage(ctx, h, st, &slot, &b);
+        if (rc != DC_OK)
+            return rc;
+        rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
+        if (rc != DC_OK)
+            return rc;
+        return release_slot(slot, st);
+    });
 }
 
 int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                       const dc_tm_params *tm, dc_stats *stats, void *stream)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    rc = dc_validate(imgs, n, params, tm);
-    if (rc != DC_OK || n == 0)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    HostTable h;
-    build_table(imgs, n, params, kTabTonemap, ctx->tune, h);
-    dc_ctx::Slot *slot = nullptr;
-    DevBufs b;
-    rc = stage(ctx, h, st, &slot, &b);
-    if (rc != DC_OK)
-        return rc;
-    rc = enqueue_tonemap(ctx, h, b, ctx->tune, tm_of(tm), (dc::StatsOut *)stats, st, true);
-    if (rc != DC_OK)
-        return rc;
-    return release_slot(slot, st);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        rc = dc_validate(imgs, n, params, tm);
+        if (rc != DC_OK || n == 0)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        HostTable h;
+        build_table(imgs, n, params, kTabTonemap, ctx->tune, h);
+        dc_ctx::Slot *slot = nullptr;
+        DevBufs b;
+        rc = stage(ctx, h, st, &slot, &b);
+        if (rc != DC_OK)
+            return rc;
+        rc = enqueue_tonemap(ctx, h, b, ctx->tune, tm_of(tm), (dc::StatsOut *)stats, st, true);
+        if (rc != DC_OK)
+            return rc;
+        return release_slot(slot, st);
+    });
 }
 
 int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                      const dc_tm_params *tm, dc_stats *stats, void *stream)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    rc = dc_validate(imgs, n, params, tm);
-    if (rc != DC_OK || n == 0)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    HostTable h;
-    build_table(imgs, n, params, kTabLocal, ctx->tune, h);
-    dc_ctx::Slot *slot = nullptr;
-    DevBufs b;
-    rc = stage(ctx, h, st, &slot, &b);
-    if (rc != DC_OK)
-        return rc;
-    rc = enqueue_local(ctx, h, b, tm_of(tm), (dc::StatsOut *)stats, st, true);
-    if (rc != DC_OK)
-        return rc;
-    return release_slot(slot, st);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        rc = dc_validate(imgs, n, params, tm);
+        if (rc != DC_OK || n == 0)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        HostTable h;
+        build_table(imgs, n, params, kTabLocal, ctx->tune, h);
+        dc_ctx::Slot *slot = nullptr;
+        DevBufs b;
+        rc = stage(ctx, h, st, &slot, &b);
+        if (rc != DC_OK)
+            return rc;
+        rc = enqueue_local(ctx, h, b, tm_of(tm), (dc::StatsOut *)stats, st, true);
+        if (rc != DC_OK)
+            return rc;
+        return release_slot(slot, st);
+    });
 }
 
 int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t channel, void *stream)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    if (channel < DC_CH_Y601 || channel > DC_CH_CIELAB_L)
-        return fail(DC_ERR_INVALID_ARG, "channel must be DC_CH_Y601, DC_CH_HSV_V or DC_CH_CIELAB_L");
-    rc = dc_validate(imgs, n, nullptr, nullptr);
-    if (rc != DC_OK || n == 0)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    HostTable h;
-    build_table(imgs, n, nullptr, kTabChannel, ctx->tune, h);
-    dc_ctx::Slot *slot = nullptr;
-    DevBufs b;
-    rc = stage(ctx, h, st, &slot, &b);
-    if (rc != DC_OK)
-        return rc;
-    mark(ctx, true, 0, st);
-    hipError_t e = hipSuccess;
-    for (const auto &r : h.runs) {
-        if (e == hipSuccess)
-            e = dc::launch_channel(b.table, b.tile_end, r.img0, r.img1 - r.img0,
-                                   h.d[r.img0].tile_begin, h.tile_end[r.img1 - 1], r.src, channel,
-                                   0, st);
-    }
-    if (e != hipSuccess)
-        return hip_fail(e, "channel launch");
-    mark(ctx, true, 1, st);
-    return release_slot(slot, st);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        if (channel < DC_CH_Y601 || channel > DC_CH_CIELAB_L)
+            return fail(DC_ERR_INVALID_ARG, "channel must be DC_CH_Y601, DC_CH_HSV_V or DC_CH_CIELAB_L");
+        rc = dc_validate(imgs, n, nullptr, nullptr);
+        if (rc != DC_OK || n == 0)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        HostTable h;
+        build_table(imgs, n, nullptr, kTabChannel, ctx->tune, h);
+        dc_ctx::Slot *slot = nullptr;
+        DevBufs b;
+        rc = stage(ctx, h, st, &slot, &b);
+        if (rc != DC_OK)
+            return rc;
+        mark(ctx, true, 0, st);
+        hipError_t e = hipSuccess;
+        for (const auto &r : h.runs) {
+            if (e == hipSuccess)
+                e = dc::launch_channel(b.table, b.tile_end, r.img0, r.img1 - r.img0,
+                                       h.d[r.img0].tile_begin, h.tile_end[r.img1 - 1], r.src, channel,
+                                       0, st);
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "channel launch");
+        mark(ctx, true, 1, st);
+        return release_slot(slot, st);
+    });
 }
 
 int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                    const dc_params *params, const dc_tm_params *tm, dc_stats *stats, int32_t flags,
                    dc_plan **plan)
 {
-    g_last_error.clear();
-    if (!plan)
-        return fail(DC_ERR_INVALID_ARG, "plan out-pointer is NULL");
-    *plan = nullptr;
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP && kind != DC_PLAN_LOCAL)
-        return fail(DC_ERR_INVALID_ARG,
-                    "kind must be DC_PLAN_DECOLORIZE, DC_PLAN_TONEMAP or DC_PLAN_LOCAL");
-    if (flags & ~DC_PLAN_GRAPH)
-        return fail(DC_ERR_INVALID_ARG, "unknown plan flags");
-    if (n < 1)
-        return fail(DC_ERR_INVALID_ARG, "a plan needs at least one image");
-    if (kind == DC_PLAN_DECOLORIZE && (tm || stats))
-        return fail(DC_ERR_INVALID_ARG, "tm and stats apply to tone-map plans only");
-    rc = dc_validate(imgs, n, params, kind == DC_PLAN_DECOLORIZE ? nullptr : tm);
-    if (rc != DC_OK)
-        return rc;
-    return plan_build(ctx, kind, imgs, n, params, tm, stats, flags, ctx->tune, plan);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!plan)
+            return fail(DC_ERR_INVALID_ARG, "plan out-pointer is NULL");
+        *plan = nullptr;
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP && kind != DC_PLAN_LOCAL)
+            return fail(DC_ERR_INVALID_ARG,
+                        "kind must be DC_PLAN_DECOLORIZE, DC_PLAN_TONEMAP or DC_PLAN_LOCAL");
+        if (flags & ~DC_PLAN_GRAPH)
+            return fail(DC_ERR_INVALID_ARG, "unknown plan flags");
+        if (n < 1)
+            return fail(DC_ERR_INVALID_ARG, "a plan needs at least one image");
+        if (kind == DC_PLAN_DECOLORIZE && (tm || stats))
+            return fail(DC_ERR_INVALID_ARG, "tm and stats apply to tone-map plans only");
+        rc = dc_validate(imgs, n, params, kind == DC_PLAN_DECOLORIZE ? nullptr : tm);
+        if (rc != DC_OK)
+            return rc;
+        return plan_build(ctx, kind, imgs, n, params, tm, stats, flags, ctx->tune, plan);
+    });
 }
 
 int dc_plan_run(dc_plan *p, void *stream)
 {
-    g_last_error.clear();
-    if (!p)
-        return fail(DC_ERR_INVALID_ARG, "plan is NULL");
-    int rc = check_ctx(p->ctx);
-    if (rc != DC_OK)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    if (!p->graph)
-        return plan_enqueue(p, st, true);
-    if (!st)
-        return fail(DC_ERR_INVALID_ARG, "graph plans need a non-null stream");
-    if (!p->exec) {
-        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess)
-            return hip_fail(e, "hipStreamBeginCapture");
-        rc = plan_enqueue(p, st, false);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(st, &g);
-        if (rc != DC_OK) {
-            if (g)
-                (void)hipGraphDestroy(g);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!p)
+            return fail(DC_ERR_INVALID_ARG, "plan is NULL");
+        int rc = check_ctx(p->ctx);
+        if (rc != DC_OK)
             return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        if (!p->graph)
+            return plan_enqueue(p, st, true);
+        if (!st)
+            return fail(DC_ERR_INVALID_ARG, "graph plans need a non-null stream");
+        if (!p->exec) {
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipStreamBeginCapture");
+            rc = plan_enqueue(p, st, false);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(st, &g);
+            if (rc != DC_OK) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                p->exec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
         }
+        hipError_t e = hipGraphLaunch(p->exec, st);
         if (e != hipSuccess)
-            return hip_fail(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            p->exec = nullptr;
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-    }
-    hipError_t e = hipGraphLaunch(p->exec, st);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipGraphLaunch");
-    return DC_OK;
+            return hip_fail(e, "hipGraphLaunch");
+        return DC_OK;
+    });
 }
 
 int dc_plan_destroy(dc_plan *p)
 {
-    if (!p)
+    return guarded([&]() -> int {
+        if (!p)
+            return DC_OK;
+        (void)hipSetDevice(p->ctx->device);
+        (void)hipDeviceSynchronize();
+        plan_free(p);
         return DC_OK;
-    (void)hipSetDevice(p->ctx->device);
-    (void)hipDeviceSynchronize();
-    plan_free(p);
-    return DC_OK;
+    });
 }
 
 int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 const dc_params *params, const dc_tm_params *tm, void *stream, dc_tuning *chosen)
 {
-    g_last_error.clear();
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP)
-        return fail(DC_ERR_INVALID_ARG, "kind must be DC_PLAN_DECOLORIZE or DC_PLAN_TONEMAP");
-    if (n < 1)
-        return fail(DC_ERR_INVALID_ARG, "tuning needs at least one image");
-    rc = dc_validate(imgs, n, params, kind == DC_PLAN_TONEMAP ? tm : nullptr);
-    if (rc != DC_OK)
-        return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    const int gpcs[] = {0, 1, 2, 4, 8, 16};
-    const int reps = 10;
-    // A candidate replaces the current choice only when it is faster by more
-    // than this factor, so run-to-run noise does not flip between shapes whose
-    // times are within it; the current shapes are measured first.
-    const float margin = 0.98f;
-    Tune best = ctx->tune;
-    std::vector<float> ms;
-    auto run = [&](const Tune &t, std::vector<float> *out) -> int {
-        dc_plan *p = nullptr;
-        int r = plan_build(ctx, kind, imgs, n, params, tm, nullptr, 0, t, &p);
-        if (r == DC_OK)
-            r = time_plan(p, st, reps, out);
-        if (p) {
-            (void)hipStreamSynchronize(st);
-            plan_free(p);
-        }
-        return r;
-    };
-    if (kind == DC_PLAN_DECOLORIZE) {
-        bool mixed = false;
-        for (int32_t i = 1; i < n; ++i)
-            mixed |= imgs[i].src_dtype != imgs[0].src_dtype;
-        rc = run(ctx->tune, &ms);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
         if (rc != DC_OK)
             return rc;
-        float best_ms = ms[0];
-        for (int g : {1, 2, 4}) {
+        if (kind != DC_PLAN_DECOLORIZE && kind != DC_PLAN_TONEMAP)
+            return fail(DC_ERR_INVALID_ARG, "kind must be DC_PLAN_DECOLORIZE or DC_PLAN_TONEMAP");
+        if (n < 1)
+            return fail(DC_ERR_INVALID_ARG, "tuning needs at least one image");
+        rc = dc_validate(imgs, n, params, kind == DC_PLAN_TONEMAP ? tm : nullptr);
+        if (rc != DC_OK)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        const int gpcs[] = {0, 1, 2, 4, 8, 16};
+        const int reps = 10;
+        // A candidate replaces the current choice only when it is faster by more
+        // than this factor, so run-to-run noise does not flip between shapes whose
+        // times are within it; the current shapes are measured first.
+        const float margin = 0.98f;
+        Tune best = ctx->tune;
+        std::vector<float> ms;
+        auto run = [&](const Tune &t, std::vector<float> *out) -> int {
+            dc_plan *p = nullptr;
+            int r = plan_build(ctx, kind, imgs, n, params, tm, nullptr, 0, t, &p);
+            if (r == DC_OK)
+                r = time_plan(p, st, reps, out);
+            if (p) {
+                (void)hipStreamSynchronize(st);
+                plan_free(p);
+            }
+            return r;
+        };
+        if (kind == DC_PLAN_DECOLORIZE) {
+            bool mixed = false;
+            for (int32_t i = 1; i < n; ++i)
+                mixed |= imgs[i].src_dtype != imgs[0].src_dtype;
+            rc = run(ctx->tune, &ms);
+            if (rc != DC_OK)
+                return rc;
+            float best_ms = ms[0];
+            for (int g : {1, 2, 4}) {
+                for (int c : gpcs) {
+                    Tune t = ctx->tune;
+                    if (mixed) {
+                        t.mixed_groups = g;
+                        t.mixed_gpc = c;
+                    } else {
+                        t.groups[imgs[0].src_dtype] = g;
+                        t.decolor_gpc = c;
+                    }
+                    rc = run(t, &ms);
+                    if (rc != DC_OK)
+                        return rc;
+                    if (ms[0] < margin * best_ms) {
+                        best_ms = ms[0];
+                        best = t;
+                    }
+                }
+            }
+        } else {
+            Tune cur = ctx->tune;
+            cur.tm_pipeline = 0;
+            rc = run(cur, &ms);
+            if (rc != DC_OK)
+                return rc;
+            float b1 = ms[0], b2 = ms[2];
             for (int c : gpcs) {
                 Tune t = ctx->tune;
-                if (mixed) {
-                    t.mixed_groups = g;
-                    t.mixed_gpc = c;
-                } else {
-                    t.groups[imgs[0].src_dtype] = g;
-                    t.decolor_gpc = c;
-                }
+                t.tm_pipeline = 0;
+                t.pass1_gpc = c;
+                t.pass2_gpc = c;
                 rc = run(t, &ms);
                 if (rc != DC_OK)
                     return rc;
-                if (ms[0] < margin * best_ms) {
-                    best_ms = ms[0];
-                    best = t;
+                if (ms[0] < margin * b1) {
+                    b1 = ms[0];
+                    best.pass1_gpc = c;
+                }
+                if (ms[2] < margin * b2) {
+                    b2 = ms[2];
+                    best.pass2_gpc = c;
                 }
             }
-        }
-    } else {
-        Tune cur = ctx->tune;
-        cur.tm_pipeline = 0;
-        rc = run(cur, &ms);
-        if (rc != DC_OK)
-            return rc;
-        float b1 = ms[0], b2 = ms[2];
-        for (int c : gpcs) {
-            Tune t = ctx->tune;
-            t.tm_pipeline = 0;
-            t.pass1_gpc = c;
-            t.pass2_gpc = c;
-            rc = run(t, &ms);
-            if (rc != DC_OK)
-                return rc;
-            if (ms[0] < margin * b1) {
-                b1 = ms[0];
-                best.pass1_gpc = c;
+            // Whole-sequence time of the two schedules with the chosen grids.
+            float whole[2];
+            for (int pl = 0; pl < 2; ++pl) {
+                Tune t = best;
+                t.tm_pipeline = pl;
+                rc = run(t, &ms);
+                if (rc != DC_OK)
+                    return rc;
+                whole[pl] = 0.0f;
+                for (float m : ms)
+                    whole[pl] += m;
             }
-            if (ms[2] < margin * b2) {
-                b2 = ms[2];
-                best.pass2_gpc = c;
-            }
+            best.tm_pipeline = whole[1] < margin * whole[0] ? 1 : 0;
         }
-        // Whole-sequence time of the two schedules with the chosen grids.
-        float whole[2];
-        for (int pl = 0; pl < 2; ++pl) {
-            Tune t = best;
-            t.tm_pipeline = pl;
-            rc = run(t, &ms);
-            if (rc != DC_OK)
-                return rc;
-            whole[pl] = 0.0f;
-            for (float m : ms)
-                whole[pl] += m;
-        }
-        best.tm_pipeline = whole[1] < margin * whole[0] ? 1 : 0;
-    }
-    ctx->tune = best;
-    if (chosen)
-        *chosen = to_public(best);
-    return DC_OK;
+        ctx->tune = best;
+        if (chosen)
+            *chosen = to_public(best);
+        return DC_OK;
+    });
 }
 
 } // extern "C"
@@ -1581,154 +1642,166 @@ extern "C" {
 
 int dc_server_create(dc_ctx *ctx, const dc_server_config *cfg, dc_server **out)
 {
-    g_last_error.clear();
-    if (!out)
-        return fail(DC_ERR_INVALID_ARG, "server out-pointer is NULL");
-    *out = nullptr;
-    int rc = check_ctx(ctx);
-    if (rc != DC_OK)
-        return rc;
-    if (!cfg || cfg->budget_bytes <= 0 || cfg->max_batch < 1 || cfg->max_inflight < 1 ||
-        cfg->max_inflight > 8 || cfg->flags != 0)
-        return fail(DC_ERR_INVALID_ARG,
-                    "budget_bytes > 0, max_batch >= 1, max_inflight in [1, 8] and flags 0 are required");
-    rc = validate_params(&cfg->params);
-    if (rc == DC_OK)
-        rc = validate_tm(&cfg->tm);
-    if (rc != DC_OK)
-        return rc;
-    dc_server *sv = new (std::nothrow) dc_server();
-    if (!sv)
-        return fail(DC_ERR_NO_MEMORY, "server allocation failed");
-    sv->ctx = ctx;
-    sv->cfg = *cfg;
-    const size_t arena_bytes = (size_t)cfg->budget_bytes / dc::kGranule * dc::kGranule;
-    if (hipMalloc((void **)&sv->arena, arena_bytes) != hipSuccess) {
-        delete sv;
-        return fail(DC_ERR_NO_MEMORY, "server arena allocation failed");
-    }
-    sv->blocks.reset(arena_bytes);
-    sv->lanes.resize((size_t)cfg->max_inflight);
-    for (auto &ln : sv->lanes) {
-        if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
-            dc_server_destroy(sv);
-            return fail(DC_ERR_HIP, "server stream or event creation failed");
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!out)
+            return fail(DC_ERR_INVALID_ARG, "server out-pointer is NULL");
+        *out = nullptr;
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        if (!cfg || cfg->budget_bytes <= 0 || cfg->max_batch < 1 || cfg->max_inflight < 1 ||
+            cfg->max_inflight > 8 || cfg->flags != 0)
+            return fail(DC_ERR_INVALID_ARG,
+                        "budget_bytes > 0, max_batch >= 1, max_inflight in [1, 8] and flags 0 are required");
+        rc = validate_params(&cfg->params);
+        if (rc == DC_OK)
+            rc = validate_tm(&cfg->tm);
+        if (rc != DC_OK)
+            return rc;
+        dc_server *sv = new (std::nothrow) dc_server();
+        if (!sv)
+            return fail(DC_ERR_NO_MEMORY, "server allocation failed");
+        sv->ctx = ctx;
+        sv->cfg = *cfg;
+        const size_t arena_bytes = (size_t)cfg->budget_bytes / dc::kGranule * dc::kGranule;
+        if (hipMalloc((void **)&sv->arena, arena_bytes) != hipSuccess) {
+            delete sv;
+            return fail(DC_ERR_NO_MEMORY, "server arena allocation failed");
         }
-    }
-    sv->t0 = std::chrono::steady_clock::now();
-    *out = sv;
-    return DC_OK;
+        sv->blocks.reset(arena_bytes);
+        sv->lanes.resize((size_t)cfg->max_inflight);
+        for (auto &ln : sv->lanes) {
+            if (hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+                dc_server_destroy(sv);
+                return fail(DC_ERR_HIP, "server stream or event creation failed");
+            }
+        }
+        sv->t0 = std::chrono::steady_clock::now();
+        *out = sv;
+        return DC_OK;
+    });
 }
 
 int dc_server_destroy(dc_server *sv)
 {
-    if (!sv)
-        return DC_OK;
-    (void)hipSetDevice(sv->ctx->device);
-    for (auto &ln : sv->lanes) {
-        if (ln.s) {
-            (void)hipStreamSynchronize(ln.s);
-            (void)hipStreamDestroy(ln.s);
+    return guarded([&]() -> int {
+        if (!sv)
+            return DC_OK;
+        (void)hipSetDevice(sv->ctx->device);
+        for (auto &ln : sv->lanes) {
+            if (ln.s) {
+                (void)hipStreamSynchronize(ln.s);
+                (void)hipStreamDestroy(ln.s);
+            }
+            if (ln.done)
+                (void)hipEventDestroy(ln.done);
         }
-        if (ln.done)
-            (void)hipEventDestroy(ln.done);
-    }
-    if (sv->arena)
-        (void)hipFree(sv->arena);
-    delete sv;
-    return DC_OK;
+        if (sv->arena)
+            (void)hipFree(sv->arena);
+        delete sv;
+        return DC_OK;
+    });
 }
 
 double dc_server_clock(dc_server *sv) { return sv ? server_now(sv) : 0.0; }
 
 int dc_server_submit(dc_server *sv, const dc_request *reqs, int32_t n, double t_submit)
 {
-    g_last_error.clear();
-    if (!sv || n < 0 || (n > 0 && !reqs))
-        return fail(DC_ERR_INVALID_ARG, "bad server or request list");
-    for (int32_t i = 0; i < n; ++i) {
-        const dc_image &m = reqs[i].img;
-        const std::string at = " (request " + std::to_string(reqs[i].id) + ")";
-        Range r;
-        int rc = check_src(m, at, r);
-        if (rc != DC_OK)
-            return rc;
-        if (!dtype_ok(m.dst_dtype) || m.dst2 || m.dst2_dtype != DC_NONE ||
-            (m.flags & ~(DC_IMG_RGB_OUT | DC_IMG_HOST_SRC)))
-            return fail(DC_ERR_INVALID_ARG, "dst_dtype must be set; dst2 must be absent; flags "
-                                            "DC_IMG_RGB_OUT and DC_IMG_HOST_SRC only" + at);
-        if (m.dst) {
-            rc = validate_images(&m, 1, DC_IMG_RGB_OUT | DC_IMG_HOST_SRC);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!sv || n < 0 || (n > 0 && !reqs))
+            return fail(DC_ERR_INVALID_ARG, "bad server or request list");
+        for (int32_t i = 0; i < n; ++i) {
+            const dc_image &m = reqs[i].img;
+            const std::string at = " (request " + std::to_string(reqs[i].id) + ")";
+            Range r;
+            int rc = check_src(m, at, r);
             if (rc != DC_OK)
                 return rc;
+            if (!dtype_ok(m.dst_dtype) || m.dst2 || m.dst2_dtype != DC_NONE ||
+                (m.flags & ~(DC_IMG_RGB_OUT | DC_IMG_HOST_SRC)))
+                return fail(DC_ERR_INVALID_ARG, "dst_dtype must be set; dst2 must be absent; flags "
+                                                "DC_IMG_RGB_OUT and DC_IMG_HOST_SRC only" + at);
+            if (m.dst) {
+                rc = validate_images(&m, 1, DC_IMG_RGB_OUT | DC_IMG_HOST_SRC);
+                if (rc != DC_OK)
+                    return rc;
+            }
         }
-    }
-    const double t = t_submit >= 0.0 ? t_submit : server_now(sv);
-    for (int32_t i = 0; i < n; ++i) {
-        dc_server::Req q;
-        q.r = reqs[i];
-        q.t_submit = t;
-        sv->waiting.push_back(q);
-        ++sv->in_system;
-    }
-    return DC_OK;
+        const double t = t_submit >= 0.0 ? t_submit : server_now(sv);
+        for (int32_t i = 0; i < n; ++i) {
+            dc_server::Req q;
+            q.r = reqs[i];
+            q.t_submit = t;
+            sv->waiting.push_back(q);
+            ++sv->in_system;
+        }
+        return DC_OK;
+    });
 }
 
 int dc_server_step(dc_server *sv)
 {
-    g_last_error.clear();
-    if (!sv)
-        return fail(DC_ERR_INVALID_ARG, "server is NULL");
-    int rc = check_ctx(sv->ctx);
-    if (rc == DC_OK)
-        rc = server_step(sv);
-    return rc != DC_OK ? rc : (int)std::min<int64_t>(sv->in_system, 0x7fffffff);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!sv)
+            return fail(DC_ERR_INVALID_ARG, "server is NULL");
+        int rc = check_ctx(sv->ctx);
+        if (rc == DC_OK)
+            rc = server_step(sv);
+        return rc != DC_OK ? rc : (int)std::min<int64_t>(sv->in_system, 0x7fffffff);
+    });
 }
 
 int dc_server_poll(dc_server *sv, dc_completion *out, int32_t cap)
 {
-    g_last_error.clear();
-    if (!sv || cap < 0 || (cap > 0 && !out))
-        return fail(DC_ERR_INVALID_ARG, "bad server or output array");
-    const int32_t n = (int32_t)std::min<size_t>(sv->done.size(), (size_t)cap);
-    std::copy(sv->done.begin(), sv->done.begin() + n, out);
-    sv->done.erase(sv->done.begin(), sv->done.begin() + n);
-    return n;
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!sv || cap < 0 || (cap > 0 && !out))
+            return fail(DC_ERR_INVALID_ARG, "bad server or output array");
+        const int32_t n = (int32_t)std::min<size_t>(sv->done.size(), (size_t)cap);
+        std::copy(sv->done.begin(), sv->done.begin() + n, out);
+        sv->done.erase(sv->done.begin(), sv->done.begin() + n);
+        return n;
+    });
 }
 
 int dc_server_replay(dc_server *sv, const dc_request *reqs, const double *arrival_s, int32_t n,
                      dc_completion *out)
 {
-    g_last_error.clear();
-    if (!sv || n < 0 || (n > 0 && (!reqs || !arrival_s || !out)))
-        return fail(DC_ERR_INVALID_ARG, "bad replay arguments");
-    for (int32_t i = 1; i < n; ++i)
-        if (!(arrival_s[i] >= arrival_s[i - 1]))
-            return fail(DC_ERR_INVALID_ARG, "arrival times must be non-decreasing");
-    int rc = check_ctx(sv->ctx);
-    if (rc != DC_OK)
-        return rc;
-    const double base = server_now(sv);
-    int32_t next = 0, got = 0;
-    while (got < n) {
-        const double now = server_now(sv) - base;
-        int32_t k = next;
-        while (k < n && arrival_s[k] <= now)
-            ++k;
-        for (int32_t i = next; i < k; ++i) {
-            rc = dc_server_submit(sv, &reqs[i], 1, base + arrival_s[i]);
-            if (rc != DC_OK)
-                return rc;
-        }
-        next = k;
-        rc = server_step(sv);
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!sv || n < 0 || (n > 0 && (!reqs || !arrival_s || !out)))
+            return fail(DC_ERR_INVALID_ARG, "bad replay arguments");
+        for (int32_t i = 1; i < n; ++i)
+            if (!(arrival_s[i] >= arrival_s[i - 1]))
+                return fail(DC_ERR_INVALID_ARG, "arrival times must be non-decreasing");
+        int rc = check_ctx(sv->ctx);
         if (rc != DC_OK)
             return rc;
-        const int32_t m = dc_server_poll(sv, out + got, n - got);
-        got += m;
-    }
-    return DC_OK;
+        const double base = server_now(sv);
+        int32_t next = 0, got = 0;
+        while (got < n) {
+            const double now = server_now(sv) - base;
+            int32_t k = next;
+            while (k < n && arrival_s[k] <= now)
+                ++k;
+            for (int32_t i = next; i < k; ++i) {
+                rc = dc_server_submit(sv, &reqs[i], 1, base + arrival_s[i]);
+                if (rc != DC_OK)
+                    return rc;
+            }
+            next = k;
+            rc = server_step(sv);
+            if (rc != DC_OK)
+                return rc;
+            const int32_t m = dc_server_poll(sv, out + got, n - got);
+            got += m;
+        }
+        return DC_OK;
+    });
 }
 
 } // extern "C"
