@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--images", type=int, default=16, help="HDR images per step")
     ap.add_argument("--size", type=int, default=4096, help="HDR image side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-images", type=int, default=8)
+    ap.add_argument("--cpu-sample-images", type=int, default=16)
     ap.add_argument("--skip-video", action="store_true")
     ap.add_argument("--skip-uneven", action="store_true")
     ap.add_argument("--no-per-image", action="store_true",
