@@ -76,6 +76,7 @@ extern "C" {
 #define DC_ERR_NO_MEMORY (-4)   /* workspace allocation failed */
 #define DC_ERR_HIP (-5)         /* a HIP runtime call failed */
 #define DC_ERR_NO_DEVICE (-6)   /* no usable GPU, or the device index is out of range */
+#define DC_ERR_CANCELLED (-7)   /* serving: the request was cancelled before its launch */
 
 /* Element types. DC_NONE marks an absent optional output. */
 #define DC_NONE (-1)
@@ -336,7 +337,9 @@ typedef struct dc_request {
 /* A finished request. Times are seconds on the server clock (dc_server_clock):
  * submitted (for replays: the scheduled arrival), admitted, launched, and the
  * step that saw its launch complete. status is DC_OK; DC_ERR_NO_MEMORY for a
- * request whose output is larger than the whole budget (rejected at once); or,
+ * request whose output is larger than the whole budget (rejected at once);
+ * DC_ERR_CANCELLED for a request cancelled before its launch (t_launch is 0
+ * for a request that never launched; t_admit too if it was never admitted); or,
  * when enqueueing its launch failed, that failure's status (the step that saw
  * it returns it too, after waiting for the lane and freeing the batch's
  * memory). */
@@ -359,6 +362,13 @@ int dc_server_submit(dc_server *server, const dc_request *reqs, int32_t n, doubl
 int dc_server_step(dc_server *server);
 /* Moves up to cap completions (oldest first) into out (HOST); returns the count. */
 int dc_server_poll(dc_server *server, dc_completion *out, int32_t cap);
+/* Cancels request `id` if it has not been launched yet (it is still waiting,
+ * or admitted but not yet in a launch): it completes at once with status
+ * DC_ERR_CANCELLED and its memory returns to the budget. Returns 1 when a
+ * request was cancelled, 0 when no queued request has that id (unknown,
+ * already launched or already complete), or a negative status. With several
+ * queued requests of one id, the oldest is cancelled. */
+int dc_server_cancel(dc_server *server, int64_t id);
 double dc_server_clock(dc_server *server);
 /* Trace replay: submits reqs[i] when arrival_s[i] (seconds from the call,
  * non-decreasing) has passed, stepping the server in a busy loop until all n

@@ -24,6 +24,7 @@ DC_ERR_ALIAS = -3
 DC_ERR_NO_MEMORY = -4
 DC_ERR_HIP = -5
 DC_ERR_NO_DEVICE = -6
+DC_ERR_CANCELLED = -7
 
 DC_NONE, DC_U8, DC_F16, DC_F32 = -1, 0, 1, 2
 _TORCH_TO_DC = {torch.uint8: DC_U8, torch.float16: DC_F16, torch.float32: DC_F32}
@@ -157,6 +158,7 @@ def lib():
     L.dc_server_submit.argtypes = [vp, req_p, i32, ctypes.c_double]
     L.dc_server_step.argtypes = [vp]
     L.dc_server_poll.argtypes = [vp, comp_p, i32]
+    L.dc_server_cancel.argtypes = [vp, ctypes.c_int64]
     L.dc_server_clock.argtypes = [vp]
     L.dc_server_clock.restype = ctypes.c_double
     L.dc_server_replay.argtypes = [vp, req_p, ctypes.POINTER(ctypes.c_double), i32, comp_p]
@@ -169,6 +171,7 @@ def lib():
                  "dc_plan_create", "dc_plan_run", "dc_plan_destroy", "dc_get_tuning",
                  "dc_set_tuning", "dc_autotune", "dc_server_create", "dc_server_destroy",
                  "dc_server_submit", "dc_server_step", "dc_server_poll", "dc_server_replay",
+                 "dc_server_cancel",
                  "dc_channel_batch", "dc_decolorize_batch_betas", "dc_tonemap_local"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -603,6 +606,15 @@ class Server:
             if n < 0:
                 _check(n)
         return [buf[i] for i in range(n)]
+
+    def cancel(self, rid):
+        """Cancels request rid if it is still queued (not launched); True if
+        it was. It then completes with status DC_ERR_CANCELLED."""
+        with self._ctx.lock:
+            n = lib().dc_server_cancel(self._h, rid)
+            if n < 0:
+                _check(n)
+        return n == 1
 
     def clock(self):
         return lib().dc_server_clock(self._h)

@@ -938,6 +938,7 @@ const char *dc_status_string(int status)
     case DC_ERR_NO_MEMORY: return "out of memory";
     case DC_ERR_HIP: return "HIP runtime error";
     case DC_ERR_NO_DEVICE: return "no usable device";
+    case DC_ERR_CANCELLED: return "cancelled";
     default: return "unknown status";
     }
 }
@@ -1765,6 +1766,25 @@ int dc_server_poll(dc_server *sv, dc_completion *out, int32_t cap)
         std::copy(sv->done.begin(), sv->done.begin() + n, out);
         sv->done.erase(sv->done.begin(), sv->done.begin() + n);
         return n;
+    });
+}
+
+int dc_server_cancel(dc_server *sv, int64_t id)
+{
+    return guarded([&]() -> int {
+        g_last_error.clear();
+        if (!sv)
+            return fail(DC_ERR_INVALID_ARG, "server is NULL");
+        const bool hit = dc::cancel_queued(
+            sv->waiting, sv->admitted, sv->blocks,
+            [id](const dc_server::Req &q) { return q.r.id == id; },
+            [](const dc_server::Req &q) {
+                return std::pair<size_t, size_t>(q.off, q.owned ? q.bytes : 0);
+            },
+            [&](const dc_server::Req &q) {
+                complete(sv, q, DC_ERR_CANCELLED, 0, server_now(sv));
+            });
+        return hit ? 1 : 0;
     });
 }
 

@@ -1,6 +1,7 @@
 // Host-only policy pieces of the continuous-batching server: the device-memory
 // arena (first fit over a sorted free list, blocks rounded to 256-byte
-// granules, neighbours coalesced on release) and FIFO admission against it.
+// granules, neighbours coalesced on release), FIFO admission against it, and
+// cancellation of requests that are still queued.
 // No HIP here, so the policy can be exercised on the CPU with simulated
 // launches; runtime.cpp drives it with real streams and events.
 #ifndef DC_SERVE_POLICY_H
@@ -10,6 +11,7 @@
 #include <deque>
 #include <iterator>
 #include <map>
+#include <utility>
 
 namespace dc {
 
@@ -95,6 +97,34 @@ void admit_fifo(std::deque<Req> &waiting, std::deque<Req> &admitted, Arena &aren
         admitted.push_back(q);
         waiting.pop_front();
     }
+}
+
+// Cancels the first queued request that match(q) accepts, looking in
+// `waiting` and then in `admitted` (requests not yet in a launch); an
+// admitted request's block (block(q) -> {offset, bytes}, bytes 0 for none)
+// returns to the arena. drop(q) sees the request before it leaves its queue.
+// True when a request was cancelled; a request that is already launched
+// cannot be.
+template <class Req, class Match, class Block, class Drop>
+bool cancel_queued(std::deque<Req> &waiting, std::deque<Req> &admitted, Arena &arena, Match match,
+                   Block block, Drop drop)
+{
+    for (auto it = waiting.begin(); it != waiting.end(); ++it)
+        if (match(*it)) {
+            drop(*it);
+            waiting.erase(it);
+            return true;
+        }
+    for (auto it = admitted.begin(); it != admitted.end(); ++it)
+        if (match(*it)) {
+            const auto b = block(*it);
+            if (b.second)
+                arena.release(b.first, b.second);
+            drop(*it);
+            admitted.erase(it);
+            return true;
+        }
+    return false;
 }
 
 } // namespace dc

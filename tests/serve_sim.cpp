@@ -3,13 +3,16 @@
 // in FIFO order against the arena, launched in batches of up to max_batch on
 // idle lanes, and retire after a duration proportional to their bytes. The
 // checks are the policy's promises: admission order is submission order (less
-// the rejected), no two live blocks overlap and none leaves the arena, every
-// request completes, requests larger than the arena are rejected, the free
-// list never holds two adjacent blocks, and the arena is one free block again
-// at the end.
+// the rejected and those cancelled while waiting), no two live blocks overlap
+// and none leaves the arena, every request completes exactly once (run,
+// rejected or cancelled), requests larger than the arena are rejected, a
+// cancel succeeds exactly when the request is still queued and returns its
+// block, the free list never holds two adjacent blocks, and the arena is one
+// free block again at the end.
 //
 // usage: serve_sim SEED
-// prints "ok <admitted> <rejected> <max bytes in use> <steps that left requests waiting>"
+// prints "ok <admitted> <rejected> <max bytes in use> <steps that left requests waiting>
+// <cancelled>"
 #include "../paper_2108_13656_amd/csrc/serve_policy.h"
 
 #include <algorithm>
@@ -78,7 +81,9 @@ int main(int argc, char **argv)
     std::deque<Req> waiting, admitted;
     std::vector<Lane> lanes(nlanes);
     std::map<size_t, std::pair<size_t, int>> live; // off -> (bytes, id)
-    std::vector<int> admit_order, done(nreq, 0), rejected(nreq, 0);
+    std::vector<int> admit_order, done(nreq, 0), rejected(nreq, 0), cancelled(nreq, 0),
+        was_admitted(nreq, 0);
+    int ncancel = 0;
     size_t in_use = 0, max_in_use = 0;
     int next = 0, finished = 0, blocked = 0;
     double now = 0;
@@ -113,6 +118,7 @@ int main(int argc, char **argv)
                 q.off = off;
                 q.bytes = bytes;
                 admit_order.push_back(q.id);
+                was_admitted[q.id] = 1;
                 if (!bytes)
                     return;
                 check(bytes == q.need, "block size", q.id);
@@ -135,6 +141,31 @@ int main(int argc, char **argv)
                 rejected[q.id] += 1;
                 ++finished;
             });
+        // now and then a client cancels one of the requests it has sent
+        if (next > 0 && u01(rng) < 0.1) {
+            const int span = next < 40 ? next : 40; // mostly recent requests
+            const int id = next - 1 - (int)(rng() % (uint64_t)span);
+            bool queued = false;
+            for (const auto &q : waiting)
+                queued |= q.id == id;
+            for (const auto &q : admitted)
+                queued |= q.id == id;
+            const bool hit = dc::cancel_queued(
+                waiting, admitted, arena, [id](const Req &q) { return q.id == id; },
+                [](const Req &q) { return std::pair<size_t, size_t>(q.off, q.bytes); },
+                [&](const Req &q) {
+                    if (q.bytes) {
+                        check(live.count(q.off) && live[q.off].second == q.id, "cancel a live block",
+                              q.id);
+                        live.erase(q.off);
+                        in_use -= q.bytes;
+                    }
+                    cancelled[q.id] += 1;
+                    ++finished;
+                });
+            check(hit == queued, "cancel succeeds exactly for queued requests", id);
+            ncancel += hit;
+        }
         check(in_use <= arena_bytes, "budget", -1);
         if (!waiting.empty())
             ++blocked; // the front request waits for memory: FIFO holds the rest back
@@ -173,16 +204,18 @@ int main(int argc, char **argv)
         now = nxt > now ? nxt : now;
     }
 
-    // FIFO: admission order is submission order without the rejected
+    // FIFO: admission order is submission order without the rejected and
+    // those cancelled while still waiting
     std::vector<int> want;
     for (int i = 0; i < nreq; ++i)
-        if (!rejected[i])
+        if (!rejected[i] && !(cancelled[i] && !was_admitted[i]))
             want.push_back(i);
     check(admit_order == want, "FIFO admission order", -1);
     for (int i = 0; i < nreq; ++i) {
-        check(done[i] + rejected[i] == 1, "each request completes exactly once", i);
+        check(done[i] + rejected[i] + cancelled[i] == 1, "each request completes exactly once", i);
         check(!rejected[i] || trace[i].need > arena_bytes, "only oversized requests rejected", i);
     }
+    check(ncancel > 0, "some cancels hit queued requests", -1);
     check(live.empty() && in_use == 0, "all blocks returned", -1);
     check(arena.free_blocks().size() == 1 && arena.free_blocks().begin()->first == 0 &&
               arena.free_blocks().begin()->second == arena_bytes,
@@ -192,6 +225,6 @@ int main(int argc, char **argv)
         nrej += r;
     if (fails)
         return 1;
-    std::printf("ok %zu %d %zu %d\n", admit_order.size(), nrej, max_in_use, blocked);
+    std::printf("ok %zu %d %zu %d %d\n", admit_order.size(), nrej, max_in_use, blocked, ncancel);
     return 0;
 }

@@ -45,7 +45,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_version_and_status_strings(lib):
     assert lib.dc_version() == 1
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.dc_status_string(code).decode()
     assert lib.dc_status_string(-99).decode() == "unknown status"
 
@@ -203,6 +203,7 @@ def test_server_calls_reject_bad_arguments(lib):
     assert lib.dc_server_step(None) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_submit(None, None, 0, -1.0) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_poll(None, None, 0) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_cancel(None, 7) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_destroy(None) == P.DC_OK
     assert lib.dc_plan_destroy(None) == P.DC_OK
     assert lib.dc_plan_run(None, None) == P.DC_ERR_INVALID_ARG

@@ -1,7 +1,8 @@
 """GPU tests of the continuous-batching tone-map server (dc_server_*): every
 request's result is bit-identical alone and inside a mixed continuous batch,
 admission by the device-memory budget never deadlocks, oversized requests are
-rejected, and trace replay completes every request."""
+rejected, queued requests can be cancelled, and trace replay completes every
+request."""
 import numpy as np
 import pytest
 import torch
@@ -50,6 +51,59 @@ def test_results_identical_alone_and_in_mix(dev):
     for i, (x, o) in enumerate(zip(xs, outs)):
         alone, _, _ = P.tonemap_global([x], o.dtype)
         assert torch.equal(alone[0], o), i
+
+
+def test_cancel_queued_requests(dev):
+    """Requests cancelled before their launch complete with DC_ERR_CANCELLED
+    and leave their caller output untouched; a cancel of a request that has
+    finished (or never existed) returns False; the rest run as usual."""
+    xs, outs = _mixed_requests(dev, 24, 4)
+    for o in outs:
+        o.fill_(7 if o.dtype == torch.uint8 else 7.0)
+    srv = P.Server(budget_bytes=64 << 20, max_batch=4, max_inflight=1)
+    srv.submit([P.request_for(i, x, o) for i, (x, o) in enumerate(zip(xs, outs))])
+    cancel = {3, 10, 11, 23}
+    for i in sorted(cancel):
+        assert srv.cancel(i)  # nothing has been stepped: all are still queued
+    assert not srv.cancel(1000)
+    done = []
+    while len(done) < len(xs):
+        srv.step()
+        done += srv.poll()
+    assert not srv.cancel(0)  # already complete
+    srv.close()
+    torch.cuda.synchronize()
+    by_id = {c.id: c for c in done}
+    assert sorted(by_id) == list(range(len(xs)))
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        if i in cancel:
+            assert by_id[i].status == P.DC_ERR_CANCELLED
+            assert bool((o == 7).all()), i
+        else:
+            assert by_id[i].status == P.DC_OK
+            assert torch.equal(P.tonemap_global([x], o.dtype)[0][0], o), i
+
+
+def test_cancel_admitted_request(dev):
+    """A request that is admitted (its output allocated from the budget) but
+    not yet launched can be cancelled: one lane taking one request per
+    launch, a budget for two outputs; the first step admits requests 0 and 1
+    and launches 0, so 1 is cancelled from the admitted queue, and 2 runs."""
+    rng = np.random.default_rng(5)
+    xs = [to_dev(synth.sdr_pixels(rng, 256, 256), dev) for _ in range(3)]
+    budget = 2 * 256 * 256 * 4 + 4096  # two f32 outputs
+    srv = P.Server(budget_bytes=budget, max_batch=1, max_inflight=1)
+    srv.submit([P.request_for(i, x, out_dtype=torch.float32) for i, x in enumerate(xs)])
+    srv.step()
+    assert srv.cancel(1)
+    done = []
+    while len(done) < 3:
+        srv.step()
+        done += srv.poll()
+    srv.close()
+    by_id = {c.id: c for c in done}
+    assert by_id[0].status == P.DC_OK and by_id[2].status == P.DC_OK
+    assert by_id[1].status == P.DC_ERR_CANCELLED and by_id[1].t_launch == 0.0
 
 
 def test_budget_admission_and_rejection(dev):

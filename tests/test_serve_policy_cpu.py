@@ -1,8 +1,9 @@
 """The serving loop's admission policy (paper_2108_13656_amd/csrc/serve_policy.h,
 the code dc_server_step runs) under simulated launches on the CPU: FIFO
 admission, no overlapping or out-of-arena blocks, every request completed
-once, only oversized requests rejected, a coalesced free list, and the whole
-arena free again at the end (tests/serve_sim.cpp checks these and prints "ok").
+once, only oversized requests rejected, cancels that succeed exactly for
+queued requests, a coalesced free list, and the whole arena free again at the
+end (tests/serve_sim.cpp checks these and prints "ok").
 Several seeds vary the budget, lane count, batch size and request mix."""
 import os
 import shutil
@@ -28,7 +29,8 @@ def sim(tmp_path_factory):
 def test_policy_invariants(sim, seed):
     out = subprocess.run([sim, str(seed)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
-    ok, admitted, rejected, max_in_use, blocked = out.stdout.split()
+    ok, admitted, rejected, max_in_use, blocked, cancelled = out.stdout.split()
     assert ok == "ok"
     assert int(admitted) > 0 and int(rejected) > 0 and int(max_in_use) > 0
     assert int(blocked) > 0  # the load filled the arena, so the FIFO rule was exercised
+    assert int(cancelled) > 0
