@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--requests", type=int, default=10000, help="serving trace length")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="serving memory budget")
+    ap.add_argument("--serve-log", default=None,
+                    help="append one JSON line per served request (times, size, format, bytes)")
     ap.add_argument("--no-h2d", action="store_true",
                     help="skip the serving variant with pinned host inputs")
     ap.add_argument("--skip-colour", action="store_true")
@@ -152,11 +154,23 @@ def serve_leg(args, P, dev):
     budget = int(args.budget_gib * (1 << 30))
     torch.cuda.synchronize()
 
-    def run(max_batch, max_inflight, arrivals):
+    def run(max_batch, max_inflight, arrivals, name):
         srv = P.Server(budget, max_batch=max_batch, max_inflight=max_inflight, device=dev)
         srv.replay(reqs[:64], [0.0] * 64)  # warm-up (workspace growth)
         done = srv.replay(reqs, list(arrivals))
         srv.close()
+        if args.serve_log:
+            # one JSON object per request: times on the server clock, size, format, bytes
+            meta = {r["id"]: r for r in trace}
+            with open(args.serve_log, "a") as f:
+                for c in done:
+                    r = meta[c.id]
+                    f.write(json.dumps({
+                        "run": name, "id": c.id, "status": c.status, "batch": c.batch_size,
+                        "t_submit": c.t_submit, "t_admit": c.t_admit, "t_launch": c.t_launch,
+                        "t_done": c.t_done, "w": r["w"], "h": r["h"], "fmt": r["fmt"],
+                        "in_bytes": r["w"] * r["h"] * (3 if r["fmt"] == "u8" else 6),
+                        "out_bytes": r["w"] * r["h"] * (1 if r["fmt"] == "u8" else 4)}) + "\n")
         ok = [c for c in done if c.status == P.DC_OK]
         lat = np.array([c.t_done - c.t_submit for c in ok])
         t_first = min(c.t_submit for c in done)
@@ -170,11 +184,11 @@ def serve_leg(args, P, dev):
                 "mean_batch": round(float(sizes.mean()), 2), "rejected": len(done) - len(ok),
                 "wall_s": round(t_last - t_first, 4)}
 
-    sat = run(64, 4, np.zeros(len(reqs)))
+    sat = run(64, 4, np.zeros(len(reqs)), "saturated")
     rate = 0.7 * sat["gpx_s"] * 1e9 / px.mean()
     arrivals = unit_arrivals / rate
-    served = run(64, 4, arrivals)
-    fifo = run(1, 1, arrivals)
+    served = run(64, 4, arrivals, "served")
+    fifo = run(1, 1, arrivals, "fifo_per_image")
     # The same trace with inputs in pinned host memory: the server copies each
     # request's crop into its budget (DC_IMG_HOST_SRC) on the lane's stream,
     # so PCIe transfers of one lane overlap kernels of the others.
@@ -193,9 +207,9 @@ def serve_leg(args, P, dev):
             reqs.append(P.make_request(r["id"], hpools[r["fmt"]].data_ptr() + off, dt, r["w"],
                                        r["h"], r["w"] * bpp, q.img.dst_dtype,
                                        flags=P.DC_IMG_HOST_SRC))
-        hsat = run(64, 4, np.zeros(len(reqs)))
+        hsat = run(64, 4, np.zeros(len(reqs)), "host_saturated")
         hrate = 0.7 * hsat["gpx_s"] * 1e9 / px.mean()
-        hserved = run(64, 4, unit_arrivals / hrate)
+        hserved = run(64, 4, unit_arrivals / hrate, "host_served")
         in_bytes = sum(r["w"] * r["h"] * (3 if r["fmt"] == "u8" else 6) for r in trace)
         h2d = {"saturated_gpx_s": hsat["gpx_s"],
                "saturated_h2d_gbs": round(in_bytes / hsat["wall_s"] / 1e9, 1),
