@@ -20,6 +20,10 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
              "--offload-arch=" + ARCH]
 
 
+# roctx: named host ranges around the entry points for rocprofv3's marker trace.
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
+
 def hipcc():
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -30,7 +34,7 @@ def hipcc():
 def build(verbose=False):
     """Compiles every source into libdecolor.so (always recompiles)."""
     out_tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-o", out_tmp] + SOURCES
+    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-o", out_tmp] + SOURCES + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

@@ -7,6 +7,8 @@
 #include "dc_internal.h"
 #include "serve_policy.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -29,6 +31,16 @@ int fail(int status, const std::string &msg)
     g_last_error = msg;
     return status;
 }
+
+// A named host range around an entry point or a server step, visible to
+// `rocprofv3 --marker-trace` next to the kernels it enqueues (a no-op cost
+// when no tracer is attached).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePush(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Runs the body of an entry point so that no C++ exception crosses the C
 // interface: a failed host allocation becomes DC_ERR_NO_MEMORY, a size beyond
@@ -1087,6 +1099,7 @@ int dc_last_timings(dc_ctx *ctx, float *ms, int32_t cap)
 int dc_decolorize(dc_ctx *ctx, const dc_image *img, const dc_params *params, void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_decolorize");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1113,6 +1126,7 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
                         void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_decolorize_batch");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1139,6 +1153,7 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
                               const dc_params *betas, void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_decolorize_batch_betas");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1169,6 +1184,7 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
                       const dc_tm_params *tm, dc_stats *stats, void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_tonemap_global");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1195,6 +1211,7 @@ int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_para
                      const dc_tm_params *tm, dc_stats *stats, void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_tonemap_local");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1220,6 +1237,7 @@ int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_para
 int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t channel, void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_channel_batch");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1257,6 +1275,7 @@ int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                    dc_plan **plan)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_plan_create");
         g_last_error.clear();
         if (!plan)
             return fail(DC_ERR_INVALID_ARG, "plan out-pointer is NULL");
@@ -1283,6 +1302,7 @@ int dc_plan_create(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
 int dc_plan_run(dc_plan *p, void *stream)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_plan_run");
         g_last_error.clear();
         if (!p)
             return fail(DC_ERR_INVALID_ARG, "plan is NULL");
@@ -1338,6 +1358,7 @@ int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 const dc_params *params, const dc_tm_params *tm, void *stream, dc_tuning *chosen)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_autotune");
         g_last_error.clear();
         int rc = check_ctx(ctx);
         if (rc != DC_OK)
@@ -1587,6 +1608,7 @@ int server_step(dc_server *sv)
             break;
         if (ln.busy)
             continue;
+        TraceRange trace("dc_server_launch");
         const size_t k = std::min<size_t>(sv->admitted.size(), (size_t)sv->cfg.max_batch);
         std::vector<dc_image> imgs(k);
         const double t = server_now(sv);
@@ -1711,6 +1733,7 @@ double dc_server_clock(dc_server *sv) { return sv ? server_now(sv) : 0.0; }
 int dc_server_submit(dc_server *sv, const dc_request *reqs, int32_t n, double t_submit)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_server_submit");
         g_last_error.clear();
         if (!sv || n < 0 || (n > 0 && !reqs))
             return fail(DC_ERR_INVALID_ARG, "bad server or request list");
@@ -1746,6 +1769,7 @@ int dc_server_submit(dc_server *sv, const dc_request *reqs, int32_t n, double t_
 int dc_server_step(dc_server *sv)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_server_step");
         g_last_error.clear();
         if (!sv)
             return fail(DC_ERR_INVALID_ARG, "server is NULL");
@@ -1772,6 +1796,7 @@ int dc_server_poll(dc_server *sv, dc_completion *out, int32_t cap)
 int dc_server_cancel(dc_server *sv, int64_t id)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_server_cancel");
         g_last_error.clear();
         if (!sv)
             return fail(DC_ERR_INVALID_ARG, "server is NULL");
@@ -1792,6 +1817,7 @@ int dc_server_replay(dc_server *sv, const dc_request *reqs, const double *arriva
                      dc_completion *out)
 {
     return guarded([&]() -> int {
+        TraceRange trace("dc_server_replay");
         g_last_error.clear();
         if (!sv || n < 0 || (n > 0 && (!reqs || !arrival_s || !out)))
             return fail(DC_ERR_INVALID_ARG, "bad replay arguments");
