@@ -73,7 +73,7 @@ extern "C" {
 #define DC_ERR_INVALID_ARG (-1) /* null pointer, bad size, pitch, dtype or parameter */
 #define DC_ERR_UNSUPPORTED (-2) /* a combination the library does not implement */
 #define DC_ERR_ALIAS (-3)       /* an output overlaps an input or another output */
-#define DC_ERR_NO_MEMORY (-4)   /* workspace allocation failed */
+#define DC_ERR_NO_MEMORY (-4)   /* a device or host allocation failed */
 #define DC_ERR_HIP (-5)         /* a HIP runtime call failed */
 #define DC_ERR_NO_DEVICE (-6)   /* no usable GPU, or the device index is out of range */
 #define DC_ERR_CANCELLED (-7)   /* serving: the request was cancelled before its launch */
