@@ -653,6 +653,67 @@ def set_tuning(d, device=None):
     context(device).call(lib().dc_set_tuning, ctypes.byref(t))
 
 
+# ------------------------------------------------------------- tuning cache
+#
+# A tuning file records the launch shapes together with what they were
+# measured on: the device's name and the SHA-256 of the built library. A file
+# from another device or another build is ignored rather than applied.
+
+TUNING_CACHE_VERSION = 1
+
+
+def library_sha256():
+    import hashlib
+    with open(LIB_PATH, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def tuning_record(tuning, device_name, lib_sha):
+    """The JSON-ready record of a tuning dict for a device and library build."""
+    return {"version": TUNING_CACHE_VERSION, "device": device_name, "library_sha256": lib_sha,
+            "tuning": dict(tuning)}
+
+
+def tuning_from_record(record, device_name, lib_sha):
+    """The tuning dict of a record when it was made for this device and
+    library build, else None."""
+    try:
+        if (record.get("version") == TUNING_CACHE_VERSION and record.get("device") == device_name
+                and record.get("library_sha256") == lib_sha):
+            t = record["tuning"]
+            DcTuning.from_dict(t)  # every field present
+            return dict(t)
+    except (AttributeError, KeyError, TypeError, ValueError):
+        pass
+    return None
+
+
+def save_tuning(path, device=None):
+    """Writes the context's current launch shapes to a tuning file."""
+    import json
+    idx = context(device).device.index
+    rec = tuning_record(get_tuning(idx), torch.cuda.get_device_name(idx), library_sha256())
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
+def load_tuning(path, device=None):
+    """Applies a tuning file if it was written for this device and library
+    build; returns whether it did."""
+    import json
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return False
+    idx = context(device).device.index
+    t = tuning_from_record(rec, torch.cuda.get_device_name(idx), library_sha256())
+    if t is None:
+        return False
+    set_tuning(t, idx)
+    return True
+
+
 def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
              contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stream=None,
              saturation=TM_SATURATION):

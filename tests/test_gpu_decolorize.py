@@ -239,3 +239,25 @@ def test_tuning_roundtrip_and_autotune(dev):
         assert torch.equal(out, ref)
     finally:
         P.set_tuning(t0)
+
+
+def test_tuning_file(dev, tmp_path):
+    """save_tuning / load_tuning: a file written on this device and build is
+    applied; one naming another device is not, and leaves the tuning alone."""
+    import json
+    t0 = P.get_tuning()
+    try:
+        path = str(tmp_path / "tuning.json")
+        P.set_tuning(dict(t0, groups=[2, 1, 4], pass1_grid_per_cu=8))
+        P.save_tuning(path)
+        want = P.get_tuning()
+        P.set_tuning(t0)
+        assert P.load_tuning(path) and P.get_tuning() == want
+        rec = json.load(open(path))
+        rec["device"] = "another device"
+        json.dump(rec, open(path, "w"))
+        P.set_tuning(t0)
+        assert not P.load_tuning(path) and P.get_tuning() == t0
+        assert not P.load_tuning(str(tmp_path / "missing.json"))
+    finally:
+        P.set_tuning(t0)
