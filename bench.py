@@ -48,6 +48,20 @@ def profiled_traffic():
     return found
 
 
+def add_traffic_rates(obj):
+    """In every roofline object with a measured `traffic`, adds the counter
+    rate beside the algorithmic one: traffic_gbs = traffic bytes / kernel time
+    (kernel time = algorithmic_bytes / achieved) and its fraction of peak."""
+    if isinstance(obj, dict):
+        if obj.get("traffic") and obj.get("achieved") and obj.get("algorithmic_bytes"):
+            secs = obj["algorithmic_bytes"] / (obj["achieved"] * 1e9)
+            obj["traffic_gbs"] = round(obj["traffic"] / secs / 1e9, 1)
+            obj["traffic_frac"] = round(obj["traffic_gbs"] / obj["peak"], 4)
+        for v in obj.values():
+            add_traffic_rates(v)
+    return obj
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -694,7 +708,7 @@ def main():
     if args.save_tuning and saved:
         with open(args.save_tuning, "w") as f:
             json.dump(P.get_tuning(dev), f)
-    print(json.dumps(result), flush=True)
+    print(json.dumps(add_traffic_rates(result)), flush=True)
 
 
 if __name__ == "__main__":
