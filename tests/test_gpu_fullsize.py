@@ -245,3 +245,40 @@ def test_image_larger_than_2gib(dev):
     assert st["count"] == h * w
     assert abs(st["mu"] - ref["mu"]) <= 2e-5 * (1 + abs(ref["mu"]))
     assert abs(st["sigma"] - ref["sigma"]) <= 2e-5 * ref["sigma"]
+
+
+@pytest.mark.timeout(900)
+def test_more_than_2_31_pixels(dev, lut):
+    """One 8-bit image of 46400 x 46400 = 2.15e9 pixels (pixel indices past
+    2^31, 6.5 GB of input made on the device): decolorization to 8-bit codes at
+    a million sampled pixels and along the last row against the oracle's table
+    of all colours; the global tone map's pixel count, and its T at the same
+    pixels against the oracle curve evaluated with the statistics the GPU
+    found (the statistics themselves are checked against the oracle on the
+    smaller images above)."""
+    h = w = 46400
+    assert h * w > 2 ** 31
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(97)
+    x = torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device=dev, generator=gen)
+    out = P.decolorize(x, torch.uint8)
+    rng = np.random.default_rng(97)
+    idx = np.concatenate([rng.integers(0, h * w, 1 << 20), np.arange(h * w - w, h * w)])
+    tidx = torch.from_numpy(idx).to(dev)
+    px = x.view(-1, 3)[tidx].cpu().numpy()
+    codes = (px[:, 0].astype(np.int64) << 16) | (px[:, 1].astype(np.int64) << 8) | px[:, 2]
+    lhat = lut[codes] / 255.0
+    got = out.view(-1)[tidx].cpu().numpy()
+    d = np.abs(got.astype(np.int32) - oracle.encode_u8(lhat).astype(np.int32))
+    assert d.max() <= 1
+    u8_mismatches_at_ties(got, lhat)
+    del out
+    t, _, stats = P.tonemap_global([x], torch.float32, **TM)
+    st = P.stats_to_host(stats)[0]
+    assert st["count"] == h * w
+    t_ref = oracle.tonemap_curve(lhat, st["mu"], st["sigma"], **TM)
+    err = float(np.max(np.abs(t[0].view(-1)[tidx].cpu().numpy() - t_ref)))
+    report("46400^2 u8: %d px, codes off by one %d, tone map mu %.6f sigma %.6f, max |dT| %.2e "
+           "at %d sampled px" % (h * w, int(np.count_nonzero(d)), st["mu"], st["sigma"], err,
+                                 idx.size))
+    assert err <= 1e-5
