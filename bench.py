@@ -88,7 +88,8 @@ def parse():
                     help="skip the serving variant with pinned host inputs")
     ap.add_argument("--skip-colour", action="store_true")
     ap.add_argument("--skip-local", action="store_true")
-    ap.add_argument("--only", choices=["tonemap", "colour", "local", "video", "uneven", "serve"],
+    ap.add_argument("--only", choices=["tonemap", "colour", "local", "video", "uneven", "serve",
+                                       "sweep"],
                     default=None,
                     help="time one workload only (for profiler runs)")
     ap.add_argument("--tuning", default=None,
@@ -136,6 +137,33 @@ def kernel_times(fn, reps, P, dev):
     P.set_profiling(False, dev)
     torch.cuda.synchronize()
     return [a / reps for a in acc]
+
+
+def sweep_leg(P, dev, stream, frame, reps, traffic):
+    """Weight sweep (Fig. 4's explorer): one 3840x2160 u8 frame under 20
+    (beta_R, beta_k) pairs, 20 FP32 outputs from one launch that reads the
+    frame once."""
+    import torch
+    betas = [(br, bk) for br in (0.0, 0.3, 0.55, 0.8, 1.0) for bk in (0.2, 0.5, 0.8, 1.0)]
+    sw = torch.empty((len(betas),) + tuple(frame.shape[:2]), dtype=torch.float32, device=dev)
+    with torch.cuda.stream(stream):
+        P.beta_sweep(frame, betas, out=sw, stream=stream)  # warm-up
+        swt = kernel_times(lambda: P.beta_sweep(frame, betas, out=sw, stream=stream), reps,
+                           P, dev)[0]
+    spx = len(betas) * frame.shape[0] * frame.shape[1]
+    # algorithmic bytes: the frame read once, 20 FP32 planes written
+    sbytes = frame.shape[0] * frame.shape[1] * 3 + spx * 4
+    ach = sbytes / (swt * 1e-3) / 1e9
+    sweep = {"workload": "beta_sweep_3840x2160_u8_x20", "pairs": len(betas),
+             "kernel_ms": round(swt, 4),
+             "output_gpx_s": round(spx / (swt * 1e-3) / 1e9, 1),
+             "roofline": {"bound": "hbm", "kernel": "sweep", "achieved": round(ach, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                          "traffic": traffic.get("sweep"), "algorithmic_bytes": sbytes}}
+    log("beta sweep: %d pairs on one 4K frame in %.3f ms (%.0f Gpx/s of outputs, %.0f GB/s)" %
+        (len(betas), swt, sweep["output_gpx_s"], ach))
+    del sw
+    return sweep
 
 
 def serve_leg(args, P, dev):
@@ -554,23 +582,7 @@ def main():
                     comp[ch] = vpx / (t * 1e-3) / 1e9
                 comp = {k: round(v, 1) for k, v in comp.items()}
                 log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
-                # Weight sweep (Fig. 4's explorer): one 3840x2160 frame under 20
-                # (beta_R, beta_k) pairs, 20 FP32 outputs from one launch.
-                betas = [(br, bk) for br in (0.0, 0.3, 0.55, 0.8, 1.0)
-                         for bk in (0.2, 0.5, 0.8, 1.0)]
-                f4k = frames[-1]
-                sw = torch.empty((len(betas),) + tuple(f4k.shape[:2]), dtype=torch.float32,
-                                 device=dev)
-                swt = kernel_times(lambda: P.beta_sweep(f4k, betas, out=sw, stream=stream), 10,
-                                   P, dev)[0]
-                spx = len(betas) * f4k.shape[0] * f4k.shape[1]
-                sweep = {"workload": "beta_sweep_3840x2160_u8_x20", "pairs": len(betas),
-                         "kernel_ms": round(swt, 4),
-                         "output_gpx_s": round(spx / (swt * 1e-3) / 1e9, 1),
-                         "output_write_gbs": round(spx * 4 / (swt * 1e-3) / 1e9, 1)}
-                log("beta sweep: %d pairs on one 4K frame in %.3f ms (%.0f Gpx/s of outputs)" %
-                    (len(betas), swt, sweep["output_gpx_s"]))
-                del sw
+                sweep = sweep_leg(P, dev, stream, frames[-1], 10, traffic)
         # 8-bit and FP32 parity on 4 of the frames against the oracle's value of
         # every 24-bit colour (the LSB-mismatch fraction of the u8 output)
         parity = None
@@ -621,6 +633,18 @@ def main():
                            "roofline": video["roofline"]})
         else:
             result["video_decolorize"] = video
+    # ---------------------------------------------------- weight sweep alone
+    if args.only == "sweep":
+        import synth
+        frame = torch.from_numpy(synth.video_frame(63)).to(dev)
+        sweep = sweep_leg(P, dev, stream, frame, max(args.steps, 1), traffic)
+        result.update({"metric": METRIC, "value": sweep["output_gpx_s"], "unit": "Gpixels/s",
+                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                       "ms_per_step": sweep["kernel_ms"], "higher_is_better": True,
+                       "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                       "data": "synthetic", "config": {"workload": sweep["workload"]},
+                       "roofline": sweep["roofline"], "beta_sweep": sweep})
+        del frame
     # ---------------------------------------------------- uneven batch decolorize
     if args.only in (None, "uneven") and not args.skip_uneven:
         import synth

@@ -175,9 +175,13 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
  * array of n dc_params; NULL means the defaults for all). This is the
  * weight-sweep explorer of Fig. 4, which plots how beta_R and beta_k bias L
  * along colour ramps: a sweep of one image over many (beta_R, beta_k) pairs is
- * n descriptors sharing one src with n outputs, all in one persistent launch.
- * Every weight must be finite and in [0, 1]. Results are bit-identical to
- * dc_decolorize of each image with its weights. */
+ * n descriptors sharing one src with n outputs, all in one launch. When every
+ * descriptor has the same src, size, src_pitch, dst_dtype and dst_pitch, no
+ * dst2, and outputs with the same 16-byte alignment, the launch reads each
+ * input tile once for all the pairs (the weight-independent terms of Eqs.
+ * (1)-(6) are evaluated once per pixel); otherwise it is the tile table of
+ * dc_decolorize_batch. Every weight must be finite and in [0, 1]. Results are
+ * bit-identical to dc_decolorize of each image with its weights either way. */
 int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
                               const dc_params *betas, void *stream);
 

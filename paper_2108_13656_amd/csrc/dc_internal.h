@@ -123,6 +123,10 @@ struct StatsOut {
 
 // Kernel launchers (kernels.hip). All return the hipError_t of the launch.
 hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, hipStream_t s);
+// n images sharing the input and geometry of table[0] (ntiles tiles each):
+// each workgroup reads a tile once for up to `per` of the images.
+hipError_t launch_sweep(const DevImage *table, int n, int per, int64_t ntiles, int src_dtype,
+                        int groups, int64_t grid, hipStream_t s);
 hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
                                 int64_t total_tiles, int mixed_src, int src_dtype, int groups,
                                 int64_t grid, hipStream_t s);

@@ -68,7 +68,7 @@ __device__ __forceinline__ float lum_half(float R, float G, float B, Coef k)
     G = fmaxf(G, 0.0f);
     B = fmaxf(B, 1e-30f);
     const float rr = R * R, gg = G * G;
-    const float Q = hw_sqrt(fmaf(B, B, rr + gg));                 // sqrt(3) * Eq. (1)
+    const float Q = hw_sqrt(fmaf(B, B, fmaf(R, R, gg)));          // sqrt(3) * Eq. (1)
     const float Lgr3 = hw_sqrt(fmaf(k.cr, rr, k.cg * gg));        // sqrt(3) * Eq. (3)
     const float rg = R + G;
     const float S = rg + B;
@@ -91,7 +91,7 @@ __device__ __forceinline__ float lum_linear(float R, float G, float B, Coef k)
     const float inv = hw_rcp(fmaxf(S, 1e-30f));
     const float r = R * inv, g = G * inv, b = B * inv;
     const float rr = r * r, gg = g * g;
-    const float lw = hw_sqrt(fmaf(b, b, rr + gg) * (1.0f / 3.0f)); // Eq. (1)
+    const float lw = hw_sqrt(fmaf(b, b, fmaf(r, r, gg)) * (1.0f / 3.0f)); // Eq. (1)
     const float lgr = hw_sqrt(fmaf(k.cr, rr, k.cg * gg));           // Eq. (3)
     const float warm = fmaf(r, lgr - lw, lw);                       // Eq. (4)
     const float cool = b * ((1.0f - b) + lw);                       // Eq. (5), L_b = b
@@ -520,6 +520,86 @@ __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__rest
             decolor_tile<SRC, 4 * G>(im, lt);
         }
     });
+}
+
+// ------------------------------------------------------------ weight sweep
+
+// The weight sweep (Fig. 4's explorer): n outputs of one input, output j with
+// its own (beta_R, beta_k). Every image of the table shares the input and the
+// geometry of image 0 (the runtime checks this), so a thread loads its units
+// once and evaluates Eqs. (1)-(6) for each pair from the same decoded pixels;
+// the terms that do not depend on the weights are loop-invariant in the pair
+// loop and leave it, so each further pair costs only the weight-dependent part.
+// Each output is the same expression of the same inputs as a single call, so
+// the results are bit-identical to dc_decolorize with that pair.
+template <int SRC, int U>
+__device__ __forceinline__ void sweep_tile(const DevImage *__restrict__ table, int i0, int i1,
+                                           int64_t tile)
+{
+    constexpr int PPU = unit_px(SRC);
+    constexpr int ES = elem_size(SRC);
+    constexpr int64_t TILE = (int64_t)kBlock * U * PPU;
+    constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
+    const DevImage im = table[0];
+    const TileRef t = tile_ref(im, tile, TILE);
+    const int64_t dst_off = t.dst - im.dst; // the tile's output offset, the same in every image
+    const Enc e{im.unit, 255.0f};
+    const bool vec = im.walk != kWalkScalar;
+    if (vec && t.rem >= TILE) {
+        unsigned w[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float R[PPU], G[PPU], B[PPU];
+#pragma unroll
+            for (int j = 0; j < PPU; ++j) {
+                R[j] = chan<SRC>(w[u], 3 * j);
+                G[j] = chan<SRC>(w[u], 3 * j + 1);
+                B[j] = chan<SRC>(w[u], 3 * j + 2);
+            }
+            const uint32_t lp = slot_lp<PPU>(true, u, 0);
+#pragma unroll 1
+            for (int i = i0; i < i1; ++i) {
+                const Coef k = table[i].k;
+                float v[PPU];
+#pragma unroll
+                for (int j = 0; j < PPU; ++j)
+                    v[j] = lum<SRC>(R[j], G[j], B[j], k);
+                store_unit<PPU, SF, SU>(table[i].dst + dst_off, im.dst_dtype, lp, v, e);
+            }
+        }
+        return;
+    }
+    const uint32_t rem = (uint32_t)(t.rem < TILE ? t.rem : TILE);
+#pragma unroll 1
+    for (int sl = 0; sl < U * PPU; ++sl) {
+        const uint32_t p = slot_lp<PPU>(vec, sl / PPU, sl % PPU);
+        if (p < rem) {
+            float R, G, B;
+            load_px<SRC>(t.src + p * (3 * ES), R, G, B);
+#pragma unroll 1
+            for (int i = i0; i < i1; ++i)
+                store_px<SF, SU>(table[i].dst + dst_off, im.dst_dtype, p,
+                                 lum<SRC>(R, G, B, table[i].k), e);
+        }
+    }
+}
+
+// Work item w = (chunk c, tile t) with w = c * ntiles + t: pairs
+// [c * per, min(n, (c + 1) * per)) of tile t. Splitting the pairs into chunks
+// keeps the launch wide on small images; each chunk reads the tile again.
+template <int SRC, int G>
+__global__ __launch_bounds__(kBlock) void k_sweep(const DevImage *__restrict__ table, int n,
+                                                  int per, int64_t ntiles, int64_t nwork)
+{
+    for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int64_t c = w / ntiles;
+        const int i0 = (int)c * per;
+        const int i1 = n - i0 < per ? n : i0 + per;
+        sweep_tile<SRC, 4 * G>(table, i0, i1, w - c * ntiles);
+    }
 }
 
 // ---------------------------------------------------- comparator channels
@@ -1772,6 +1852,32 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
         }
     }
 #undef DC_LAUNCH_TABLE
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const DevImage *table, int n, int per, int64_t ntiles, int src_dtype,
+                        int groups, int64_t grid, hipStream_t s)
+{
+    if (n < 1 || per < 1 || ntiles < 1)
+        return hipErrorInvalidValue;
+    const int64_t nwork = ntiles * ((n + per - 1) / per);
+    const unsigned g = grid_of(nwork, grid);
+#define DC_LAUNCH_SWEEP(S, GG)                                                                    \
+    hipLaunchKernelGGL((k_sweep<S, GG>), dim3(g), dim3(kBlock), 0, s, table, n, per, ntiles,     \
+                       nwork)
+    switch (src_dtype * 8 + groups) {
+    case 0 * 8 + 1: DC_LAUNCH_SWEEP(0, 1); break;
+    case 0 * 8 + 2: DC_LAUNCH_SWEEP(0, 2); break;
+    case 0 * 8 + 4: DC_LAUNCH_SWEEP(0, 4); break;
+    case 1 * 8 + 1: DC_LAUNCH_SWEEP(1, 1); break;
+    case 1 * 8 + 2: DC_LAUNCH_SWEEP(1, 2); break;
+    case 1 * 8 + 4: DC_LAUNCH_SWEEP(1, 4); break;
+    case 2 * 8 + 1: DC_LAUNCH_SWEEP(2, 1); break;
+    case 2 * 8 + 2: DC_LAUNCH_SWEEP(2, 2); break;
+    case 2 * 8 + 4: DC_LAUNCH_SWEEP(2, 4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef DC_LAUNCH_SWEEP
     return hipGetLastError();
 }
 

@@ -566,6 +566,29 @@ int enqueue_decolor(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
     return DC_OK;
 }
 
+// Weight sweep: when every image of a per-image-weights call reads the same
+// input with the same geometry and output type (and has no second output),
+// one pass over the input serves all of them. Returns the pairs per work item
+// (the pairs split into chunks only as far as needed for about four
+// workgroups per CU), or 0 when the table is not a sweep.
+int sweep_per(const dc_ctx *ctx, const HostTable &h)
+{
+    const int n = (int)h.d.size();
+    if (n < 2 || h.mixed)
+        return 0;
+    const dc::DevImage &a = h.d[0];
+    for (const dc::DevImage &m : h.d)
+        if (m.src != a.src || m.dst2 || m.dst_dtype != a.dst_dtype || m.walk != a.walk ||
+            m.seg_len != a.seg_len || m.tiles_per_seg != a.tiles_per_seg ||
+            m.ntiles != a.ntiles || m.src_seg_stride != a.src_seg_stride ||
+            m.dst_seg_stride != a.dst_seg_stride)
+            return 0;
+    const int64_t want = 4 * (int64_t)ctx->num_cu;
+    int64_t chunks = (want + a.ntiles - 1) / a.ntiles;
+    chunks = chunks < 1 ? 1 : (chunks > n ? n : chunks);
+    return (int)((n + chunks - 1) / chunks);
+}
+
 // Events for the per-image pipeline: fork[i] marks "statistics pass of image
 // i done" on the main stream; fork[n] marks "side stream done".
 int ensure_fork(dc_ctx *ctx, size_t n)
@@ -1173,9 +1196,20 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
         rc = stage(ctx, h, st, &slot, &b);
         if (rc != DC_OK)
             return rc;
-        rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
-        if (rc != DC_OK)
-            return rc;
+        const int per = sweep_per(ctx, h);
+        if (per > 0) {
+            mark(ctx, true, 0, st);
+            const hipError_t e =
+                dc::launch_sweep(b.table, n, per, h.d[0].ntiles, h.src0, h.groups,
+                                 grid_blocks(ctx, ctx->tune.decolor_gpc), st);
+            if (e != hipSuccess)
+                return hip_fail(e, "sweep launch");
+            mark(ctx, true, 1, st);
+        } else {
+            rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
+            if (rc != DC_OK)
+                return rc;
+        }
         return release_slot(slot, st);
     });
 }

@@ -27,19 +27,37 @@ def test_colour_ramps_sweep(dev):
             check_f32(got[i], oracle.decolorize(img, br, bk), "%s beta (%g, %g)" % (name, br, bk))
 
 
-@pytest.mark.parametrize("kind", ["u8", "f16", "f32"])
-def test_sweep_equals_single_calls(dev, kind):
+# (input, height, width, output type). Planes of an (n, H, W) output start
+# 16-byte aligned when H * W * (output bytes) is a multiple of 16; then every
+# image of the call has the same walk and the call runs as one pass over the
+# input (the shared-input sweep kernel); 123 x 517 with FP32 output leaves the
+# planes unaligned and takes the per-image table instead. Both must equal
+# single calls bit for bit.
+SWEEP_CASES = [("u8", 123, 517, torch.float32), ("u8", 128, 517, torch.float32),
+               ("u8", 64, 250, torch.uint8), ("u8", 96, 130, torch.float16),
+               ("f16", 64, 1000, torch.float32), ("f16", 64, 1000, torch.float16),
+               ("f32", 40, 77, torch.float32), ("f32", 33, 48, torch.uint8)]
+
+
+def _sweep_image(kind, h, w, seed):
+    rng = np.random.default_rng(seed)
     if kind == "u8":
-        img = synth.sdr_pixels(np.random.default_rng(31), 123, 517)
-    elif kind == "f16":
-        img = synth.hdr_pixels(np.random.default_rng(32), 64, 1000)
-    else:
-        img = synth.random_image(33, 40, 77, np.float32, scale=8.0)
+        return synth.sdr_pixels(rng, h, w)
+    if kind == "f16":
+        return synth.hdr_pixels(rng, h, w)
+    return synth.random_image(seed, h, w, np.float32, scale=8.0)
+
+
+@pytest.mark.parametrize("kind,h,w,odt", SWEEP_CASES)
+def test_sweep_equals_single_calls(dev, kind, h, w, odt):
+    img = _sweep_image(kind, h, w, 31 + h)
     x = to_dev(img, dev)
-    sweep = P.beta_sweep(x, BETAS)
+    sweep = P.beta_sweep(x, BETAS, out_dtype=odt)
     for i, (br, bk) in enumerate(BETAS):
-        one = P.decolorize(x, beta_r=br, beta_k=bk)
+        one = P.decolorize(x, odt, beta_r=br, beta_k=bk)
         assert torch.equal(sweep[i], one), (br, bk)
+    if odt != torch.float32:
+        return
     got = sweep.cpu().numpy()
     for i in (0, 7, len(BETAS) - 1):
         br, bk = BETAS[i]
@@ -47,19 +65,30 @@ def test_sweep_equals_single_calls(dev, kind):
                   rel=kind != "u8")
 
 
-def test_mixed_images_and_weights(dev):
-    imgs = [synth.sdr_pixels(np.random.default_rng(34), 50, 60),
-            synth.hdr_pixels(np.random.default_rng(35), 30, 700),
-            synth.random_image(36, 3, 5, np.float32)]
-    betas = [(0.9, 0.6), (0.55, 0.8), (0.1, 0.95)]
-    xs = [to_dev(a, dev) for a in imgs]
-    outs = P.decolorize_betas(xs, betas, torch.float16)
-    for x, o, (br, bk) in zip(xs, outs, betas):
-        assert torch.equal(o, P.decolorize(x, torch.float16, beta_r=br, beta_k=bk))
+@pytest.mark.parametrize("npairs", [2, 7, 20, 45])
+def test_sweep_pair_chunks(dev, npairs):
+    """More pairs than the image has tiles to spread over: the pairs split into
+    chunks (the last one short) and every output still equals a single call."""
+    rng = np.random.default_rng(40 + npairs)
+    img = synth.sdr_pixels(rng, 300, 400)
+    betas = [(float(a), float(b)) for a, b in rng.uniform(0.0, 1.0, (npairs, 2))]
+    x = to_dev(img, dev)
+    sweep = P.beta_sweep(x, betas)
+    for i, (br, bk) in enumerate(betas):
+        assert torch.equal(sweep[i], P.decolorize(x, beta_r=br, beta_k=bk)), (i, br, bk)
+    got = sweep.cpu().numpy()
+    for i in (0, npairs - 1):
+        check_f32(got[i], oracle.decolorize(img, *betas[i]), "pair %d of %d" % (i, npairs))
 
 
-def test_rejects_bad_weights(dev):
-    x = to_dev(synth.random_image(37, 4, 4, np.uint8), dev)
-    with pytest.raises(P.DecolorError) as e:
-        P.decolorize_betas([x, x], [(0.5, 0.5), (1.5, 0.5)])
-    assert e.value.status == P.DC_ERR_INVALID_ARG
+def test_sweep_row_walk(dev):
+    """A sweep into padded output rows, 16-byte aligned (the row walk: input rows
+    of 624 bytes, output rows of 848) and not (the per-pixel walk)."""
+    img = synth.sdr_pixels(np.random.default_rng(47), 70, 208)
+    x = to_dev(img, dev)
+    for pad in (4, 3):
+        bufs = [torch.full((70, 208 + pad), -1.0, device=dev) for _ in BETAS[:6]]
+        P.decolorize_betas([x] * 6, BETAS[:6], outs=[b[:, :208] for b in bufs])
+        for buf, (br, bk) in zip(bufs, BETAS[:6]):
+            assert torch.equal(buf[:, :208], P.decolorize(x, beta_r=br, beta_k=bk)), (pad, br, bk)
+            assert bool((buf[:, 208:] == -1.0).all())

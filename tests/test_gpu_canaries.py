@@ -66,6 +66,10 @@ def test_outputs_stay_in_bounds(dev, kind, pad):
             b, o, m, s = _guarded(h, w, 1, dt, dev, pad)
             P.decolorize_betas([x], [(0.7, 0.6)], outs=[o])
             cases.append((b, m, s, "betas %s" % dt))
+            sweep = [_guarded(h, w, 1, dt, dev, pad) for _ in range(3)]
+            P.decolorize_betas([x] * 3, [(0.7, 0.6), (0.1, 0.9), (1.0, 0.0)],
+                               outs=[g[1] for g in sweep])
+            cases += [(g[0], g[2], g[3], "sweep %s" % dt) for g in sweep]
             b, o, m, s = _guarded(h, w, 1, dt, dev, pad)
             P.channel_batch([x], "cielab_l", outs=[o])
             cases.append((b, m, s, "channel %s" % dt))
