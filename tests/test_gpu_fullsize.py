@@ -13,6 +13,10 @@ times: autotuned launch shapes and a HIP-graph plan over resident buffers.
   image against the oracle (which still builds every tile's histogram).
 - uneven batch of 256 images (half 8-bit, half binary16, 64..4096 per side),
   one persistent launch: every pixel against the oracle.
+- the weight sweep of a 3840x2160 frame of the video batch under 20 (beta_R,
+  beta_k) pairs, as bench.py times it: every output bit-identical to a single
+  call, and every pixel of 4 of the outputs against the oracle's table of all
+  colours at that pair.
 - 8-bit frames of the video batch (8 x 1080p + 8 x 2160p) through the global
   tone map, 8-bit T and FP32 Lhat out (the serving mix's SDR request): every
   image's statistics, and every pixel of both outputs, against the oracle.
@@ -89,6 +93,25 @@ def test_video_batch_every_pixel(dev, lut):
            (total, worst, off, off / total))
     assert worst <= 1e-5
     assert off / total <= 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_weight_sweep_4k_every_pixel(dev):
+    frame = synth.video_frame(63)
+    x = to_dev(frame, dev)
+    betas = [(br, bk) for br in (0.0, 0.3, 0.55, 0.8, 1.0) for bk in (0.2, 0.5, 0.8, 1.0)]
+    sweep = P.beta_sweep(x, betas)
+    for i, (br, bk) in enumerate(betas):
+        assert torch.equal(sweep[i], P.decolorize(x, beta_r=br, beta_k=bk)), (br, bk)
+    codes = _codes(frame)
+    worst = 0.0
+    for i in (0, 6, 13, 19):
+        br, bk = betas[i]
+        want = oracle.all_colours(br, bk)[codes] / 255.0
+        err = np.abs(sweep[i].cpu().numpy().astype(np.float64) - want)
+        worst = max(worst, float(err.max()))
+    report("weight sweep 3840x2160 x 20 pairs: max |dL| %.3e over 4 checked pairs" % worst)
+    assert worst <= 1e-5
 
 
 @pytest.mark.timeout(600)
