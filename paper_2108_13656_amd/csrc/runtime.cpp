@@ -778,6 +778,27 @@ int release_slot(dc_ctx::Slot *s, hipStream_t stream)
     return DC_OK;
 }
 
+// Holds a staged slot until the call's work is enqueued: finish() records the
+// slot's completion event after the last kernel; an early return after a
+// failure records it too (in the destructor), because the upload, and maybe
+// some kernels, are already queued and still read the slot, so the next call
+// that takes the slot must wait for them.
+struct SlotHold {
+    dc_ctx::Slot *slot;
+    hipStream_t st;
+    int finish()
+    {
+        dc_ctx::Slot *s = slot;
+        slot = nullptr;
+        return release_slot(s, st);
+    }
+    ~SlotHold()
+    {
+        if (slot)
+            (void)release_slot(slot, st);
+    }
+};
+
 // Stages a table in the next ring slot and copies it to the device on `st`.
 int stage(dc_ctx *ctx, const HostTable &h, hipStream_t st, dc_ctx::Slot **slot, DevBufs *b)
 {
@@ -1165,10 +1186,11 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
         rc = stage(ctx, h, st, &slot, &b);
         if (rc != DC_OK)
             return rc;
+        SlotHold hold{slot, st};
         rc = enqueue_decolor(ctx, h, b, ctx->tune, st, true);
         if (rc != DC_OK)
             return rc;
-        return release_slot(slot, st);
+        return hold.finish();
     });
 }
 
@@ -1196,6 +1218,7 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
         rc = stage(ctx, h, st, &slot, &b);
         if (rc != DC_OK)
             return rc;
+        SlotHold hold{slot, st};
         const int per = sweep_per(ctx, h);
         if (per > 0) {
             mark(ctx, true, 0, st);
@@ -1210,7 +1233,7 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
             if (rc != DC_OK)
                 return rc;
         }
-        return release_slot(slot, st);
+        return hold.finish();
     });
 }
 
@@ -1234,10 +1257,11 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
         rc = stage(ctx, h, st, &slot, &b);
         if (rc != DC_OK)
             return rc;
+        SlotHold hold{slot, st};
         rc = enqueue_tonemap(ctx, h, b, ctx->tune, tm_of(tm), (dc::StatsOut *)stats, st, true);
         if (rc != DC_OK)
             return rc;
-        return release_slot(slot, st);
+        return hold.finish();
     });
 }
 
@@ -1261,10 +1285,11 @@ int dc_tonemap_local(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_para
         rc = stage(ctx, h, st, &slot, &b);
         if (rc != DC_OK)
             return rc;
+        SlotHold hold{slot, st};
         rc = enqueue_local(ctx, h, b, tm_of(tm), (dc::StatsOut *)stats, st, true);
         if (rc != DC_OK)
             return rc;
-        return release_slot(slot, st);
+        return hold.finish();
     });
 }
 
@@ -1289,6 +1314,7 @@ int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t chann
         rc = stage(ctx, h, st, &slot, &b);
         if (rc != DC_OK)
             return rc;
+        SlotHold hold{slot, st};
         mark(ctx, true, 0, st);
         hipError_t e = hipSuccess;
         for (const auto &r : h.runs) {
@@ -1300,7 +1326,7 @@ int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t chann
         if (e != hipSuccess)
             return hip_fail(e, "channel launch");
         mark(ctx, true, 1, st);
-        return release_slot(slot, st);
+        return hold.finish();
     });
 }
 
@@ -1678,11 +1704,12 @@ int server_step(dc_server *sv)
         dc_ctx::Slot *slot = nullptr;
         DevBufs b;
         int rc = stage(sv->ctx, h, ln.s, &slot, &b);
+        if (rc != DC_OK)
+            return fail_lane(sv, ln, rc);
+        SlotHold hold{slot, ln.s};
+        rc = enqueue_tonemap(sv->ctx, h, b, sv->ctx->tune, tm_of(&sv->cfg.tm), nullptr, ln.s, false);
         if (rc == DC_OK)
-            rc = enqueue_tonemap(sv->ctx, h, b, sv->ctx->tune, tm_of(&sv->cfg.tm), nullptr, ln.s,
-                                 false);
-        if (rc == DC_OK)
-            rc = release_slot(slot, ln.s);
+            rc = hold.finish();
         if (rc != DC_OK)
             return fail_lane(sv, ln, rc);
         const hipError_t e = hipEventRecord(ln.done, ln.s);
