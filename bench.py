@@ -9,8 +9,8 @@ before timing starts. The same run also times the plain decolorization of the
 64-frame video batch (32 x 1920x1080 + 32 x 3840x2160, 8-bit in, 8-bit + FP32
 out) in one batched launch, reported in the same JSON line.
 
-Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused: this
-build measures one GPU.
+Prints one JSON line (see the keys below). ``--gpus`` above 1 is refused: the
+benchmark measures one GPU.
 """
 import argparse
 import json

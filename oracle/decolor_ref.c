@@ -253,7 +253,7 @@ void ref_decode_f16_array(const uint16_t *h, int64_t n, double *out)
         out[i] = ref_half_to_double(h[i]);
 }
 
-/* ------------------------------------------------------------ image driver */
+/* ------------------------------------------------------------ whole images */
 
 static double load_channel(const unsigned char *p, int dtype, int c)
 {
