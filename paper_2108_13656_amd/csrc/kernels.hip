@@ -183,9 +183,10 @@ __device__ __forceinline__ float chan(const unsigned (&w)[3], int e)
 // input that a later pass reads again (the tone map's curve pass) is, at the
 // batch sizes that matter, far larger than the caches. Streaming loads leave
 // L2 to the small shared data (descriptors, partials, curves) and made the
-// tone map's curve pass about 6 % faster on MI355X. A decolorization call
-// that reads one input for several images (the weight sweep) keeps plain
-// loads for it, so the repeats hit in cache.
+// tone map's curve pass about 6 % faster on MI355X. A tile-table
+// decolorization that reads one input for several images (weights per image
+// on outputs of differing layouts) keeps plain loads for it, so the repeats
+// hit in cache; the weight-sweep kernel reads its shared input once.
 template <bool NT = true>
 __device__ __forceinline__ void load_unit(const uint8_t *p, unsigned (&w)[3])
 {
