@@ -89,7 +89,7 @@ def parse():
     ap.add_argument("--skip-colour", action="store_true")
     ap.add_argument("--skip-local", action="store_true")
     ap.add_argument("--only", choices=["tonemap", "colour", "local", "video", "uneven", "serve",
-                                       "sweep"],
+                                       "sweep", "channels"],
                     default=None,
                     help="time one workload only (for profiler runs)")
     ap.add_argument("--tuning", default=None,
@@ -137,6 +137,29 @@ def kernel_times(fn, reps, P, dev):
     P.set_profiling(False, dev)
     torch.cuda.synchronize()
     return [a / reps for a in acc]
+
+
+def channels_leg(P, dev, stream, frames, o32, reps):
+    """Same-GPU comparison with the gray channels the paper compares its L
+    against: the video frames, u8 in, f32 out, Gpx/s from the kernel time of
+    the library's events."""
+    import torch
+    vpx = sum(f.shape[0] * f.shape[1] for f in frames)
+    comp = {}
+    with torch.cuda.stream(stream):
+        cplan = P.Plan(P.PLAN_DECOLORIZE, frames, o32)
+        cplan.run(stream)  # warm-up
+        comp["decolor_L"] = vpx / (kernel_times(lambda: cplan.run(stream), reps, P, dev)[0]
+                                   * 1e-3) / 1e9
+        cplan.close()
+        for ch in ("y601", "hsv_v", "cielab_l"):
+            P.channel_batch(frames, ch, outs=o32, stream=stream)  # warm-up
+            t = kernel_times(lambda: P.channel_batch(frames, ch, outs=o32, stream=stream), reps,
+                             P, dev)[0]
+            comp[ch] = vpx / (t * 1e-3) / 1e9
+    comp = {k: round(v, 1) for k, v in comp.items()}
+    log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
+    return comp
 
 
 def sweep_leg(P, dev, stream, frame, reps, traffic):
@@ -568,20 +591,7 @@ def main():
                 sp.close()
             comp = sweep = None
             if not args.no_per_image:
-                # Same-GPU comparison with the gray channels the paper compares
-                # its L against (u8 in, f32 out, kernel time from the library's
-                # events).
-                comp = {}
-                cplan = P.Plan(P.PLAN_DECOLORIZE, frames, o32)
-                comp["decolor_L"] = vpx / (kernel_times(lambda: cplan.run(stream), 10, P, dev)[0]
-                                           * 1e-3) / 1e9
-                cplan.close()
-                for ch in ("y601", "hsv_v", "cielab_l"):
-                    t = kernel_times(lambda: P.channel_batch(frames, ch, outs=o32, stream=stream),
-                                     10, P, dev)[0]
-                    comp[ch] = vpx / (t * 1e-3) / 1e9
-                comp = {k: round(v, 1) for k, v in comp.items()}
-                log("same-GPU gray channels, u8 -> f32, Gpx/s: %s" % comp)
+                comp = channels_leg(P, dev, stream, frames, o32, 10)
                 sweep = sweep_leg(P, dev, stream, frames[-1], 10, traffic)
         # 8-bit and FP32 parity on 4 of the frames against the oracle's value of
         # every 24-bit colour (the LSB-mismatch fraction of the u8 output)
@@ -633,6 +643,19 @@ def main():
                            "roofline": video["roofline"]})
         else:
             result["video_decolorize"] = video
+    # ---------------------------------------------------- gray channels alone
+    if args.only == "channels":
+        import synth
+        frames = [torch.from_numpy(f).to(dev) for f in synth.video_frames(workers=WORKERS)]
+        o32 = [torch.empty(f.shape[:2], dtype=torch.float32, device=dev) for f in frames]
+        comp = channels_leg(P, dev, stream, frames, o32, max(args.steps, 1))
+        result.update({"metric": METRIC, "value": comp["decolor_L"], "unit": "Gpixels/s",
+                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                       "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+                       "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                       "config": {"workload": "video_gray_channels_u8_to_f32"},
+                       "gray_channels_u8_to_f32_gpx": comp})
+        del frames, o32
     # ---------------------------------------------------- weight sweep alone
     if args.only == "sweep":
         import synth
