@@ -821,6 +821,10 @@ int check_ctx(dc_ctx *ctx)
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return hip_fail(e, "hipSetDevice");
+    // The launch checks read the thread's last HIP error: drop one that an
+    // earlier call left behind (a failed allocation, say), so that this call
+    // reports only its own.
+    (void)hipGetLastError();
     return DC_OK;
 }
 

@@ -76,3 +76,22 @@ def test_unknown_channel_and_plan_kind(dev):
     assert P.lib().dc_plan_create(ctx, 7, arr, 1, None, None, None, 0, ctypes.byref(h)) == \
         P.DC_ERR_INVALID_ARG
     assert not h.value
+
+
+def test_failed_allocation_reported_and_recovered(dev):
+    """A server whose budget the device cannot hold (1 TiB): creation fails with
+    DC_ERR_NO_MEMORY, nothing is left half-built, and the next calls on the
+    context run and report DC_OK (the failed allocation's error does not leak
+    into their launch checks)."""
+    x = to_dev(synth.sdr_pixels(np.random.default_rng(5), 64, 80), dev)
+    want = P.decolorize(x)
+    with pytest.raises(P.DecolorError) as e:
+        P.Server(budget_bytes=1 << 40)
+    assert e.value.status == P.DC_ERR_NO_MEMORY
+    assert "arena" in P.last_error()
+    assert torch.equal(P.decolorize(x), want)
+    outs, _, _ = P.tonemap_global([x])
+    srv = P.Server(budget_bytes=1 << 24)
+    srv.close()
+    torch.cuda.synchronize()
+    assert outs[0].shape == (64, 80)
