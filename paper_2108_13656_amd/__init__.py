@@ -231,7 +231,9 @@ _contexts_lock = threading.Lock()
 
 
 def context(device=None):
-    """The shared context of a device (created on first use)."""
+    """The shared context of a device (created on first use; a new context
+    takes the launch shapes of the tuning file named by ``DC_AUTOTUNE_CACHE``
+    when that file was written for this device and library build)."""
     if device is None:
         idx = None
     elif isinstance(device, int):
@@ -240,10 +242,15 @@ def context(device=None):
         idx = torch.device(device).index
     if idx is None:
         idx = torch.cuda.current_device()
+    created = False
     with _contexts_lock:
         if idx not in _contexts:
             _contexts[idx] = Context(idx)
-        return _contexts[idx]
+            created = True
+        ctx = _contexts[idx]
+    if created:
+        apply_tuning_cache(idx)
+    return ctx
 
 
 # ------------------------------------------------------------- marshalling
@@ -714,11 +721,22 @@ def load_tuning(path, device=None):
     return True
 
 
+TUNING_CACHE_ENV = "DC_AUTOTUNE_CACHE"
+
+
+def apply_tuning_cache(device=None):
+    """Applies the tuning file named by ``DC_AUTOTUNE_CACHE``, if set and made
+    for this device and library build; returns whether it did."""
+    path = os.environ.get(TUNING_CACHE_ENV)
+    return bool(path) and load_tuning(path, device)
+
+
 def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EPS,
              contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, stream=None,
              saturation=TM_SATURATION):
     """Runs the library's launch-shape search on these buffers and returns the
-    tuning it kept (a dict, see ``get_tuning``)."""
+    tuning it kept (a dict, see ``get_tuning``). With ``DC_AUTOTUNE_CACHE``
+    set, the context's shapes are then written to that file."""
     xs = list(xs)
     dev = xs[0].device
     arr = _image_array(xs, list(outs), None if outs2 is None else list(outs2))
@@ -727,6 +745,9 @@ def autotune(kind, xs, outs, outs2=None, beta_r=BETA_R, beta_k=BETA_K, eps=TM_EP
     t = DcTuning()
     context(dev).call(lib().dc_autotune, kind, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
                       _stream_ptr(stream, dev), ctypes.byref(t))
+    path = os.environ.get(TUNING_CACHE_ENV)
+    if path:
+        save_tuning(path, dev)
     return t.as_dict()
 
 

@@ -241,6 +241,27 @@ def test_tuning_roundtrip_and_autotune(dev):
         P.set_tuning(t0)
 
 
+def test_tuning_env_cache(dev, tmp_path, monkeypatch):
+    """DC_AUTOTUNE_CACHE: autotune writes the context's shapes to the named
+    file, and apply_tuning_cache (which a new context runs) applies it."""
+    import json
+    t0 = P.get_tuning()
+    try:
+        path = str(tmp_path / "cache.json")
+        monkeypatch.setenv(P.TUNING_CACHE_ENV, path)
+        x = to_dev(synth.sdr_pixels(np.random.default_rng(3), 256, 256), dev)
+        o = torch.empty((256, 256), device=dev)
+        P.autotune(P.PLAN_DECOLORIZE, [x], [o])
+        saved = json.load(open(path))["tuning"]
+        assert saved == P.get_tuning()
+        P.set_tuning(dict(t0, groups=[4, 4, 4], pass2_grid_per_cu=2))
+        assert P.apply_tuning_cache() and P.get_tuning() == saved
+        monkeypatch.delenv(P.TUNING_CACHE_ENV)
+        assert not P.apply_tuning_cache()
+    finally:
+        P.set_tuning(t0)
+
+
 def test_tuning_file(dev, tmp_path):
     """save_tuning / load_tuning: a file written on this device and build is
     applied; one naming another device is not, and leaves the tuning alone."""
