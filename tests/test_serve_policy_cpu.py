@@ -25,6 +25,28 @@ def sim(tmp_path_factory):
     return exe
 
 
+@pytest.fixture(scope="module")
+def sim_sanitized(tmp_path_factory):
+    """The same simulation built with AddressSanitizer and UBSan (host code)."""
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no g++")
+    exe = str(tmp_path_factory.mktemp("serve_asan") / "serve_sim")
+    res = subprocess.run([cxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+                          "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-o", exe,
+                          os.path.join(HERE, "serve_sim.cpp")], capture_output=True, text=True)
+    if res.returncode != 0:
+        pytest.skip("sanitizer runtime not available: " + res.stderr[-200:])
+    return exe
+
+
+@pytest.mark.parametrize("seed", [1, 5, 9])
+def test_policy_under_sanitizers(sim_sanitized, seed):
+    out = subprocess.run([sim_sanitized, str(seed)], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.startswith("ok ")
+
+
 @pytest.mark.parametrize("seed", range(1, 13))
 def test_policy_invariants(sim, seed):
     out = subprocess.run([sim, str(seed)], capture_output=True, text=True, timeout=120)
