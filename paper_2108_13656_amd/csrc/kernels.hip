@@ -1249,13 +1249,21 @@ __device__ __forceinline__ void ltm_slot(int i, int q, int &row, int &col)
     col = (t % UPR) * PPU + q;
 }
 
-// Bin position u in [0, kLtmBins - 1] of x2 = log2(Lhat + eps): 2 bins per
-// stop, bin centres at integers, bin 0 centred half a bin above log2(eps).
-__device__ __forceinline__ float ltm_u(float x2, float lo2)
+// Bin position u of x2 = log2(Lhat + eps): 2 bins per stop, bin centres at
+// integers, bin 0 centred half a bin above log2(eps), so u = 2 (x2 - lo2) -
+// 0.5 with lo2 = log2(eps); u0 = -(2 lo2 + 0.5) is the per-tile constant of
+// ltm_u0. u is clamped to [0, kLtmBins - 1), just below the last centre, so
+// its bin k = floor(u) <= kLtmBins - 2 and fraction f = u - k come from one
+// conversion and one fract; the clamp moves a pixel past the last centre by
+// less than 2^-18 of a bin.
+__device__ __forceinline__ float ltm_u0(float lo2) { return -fmaf(2.0f, lo2, 0.5f); }
+__device__ __forceinline__ float ltm_u(float x2, float u0)
 {
-    const float u = fmaf(2.0f, x2 - lo2, -0.5f);
-    return fminf(fmaxf(u, 0.0f), (float)(kLtmBins - 1));
+    const float u = fmaf(2.0f, x2, u0);
+    return fminf(fmaxf(u, 0.0f), 0x1.f7fffcp+5f); // 63 - 2^-18
 }
+__device__ __forceinline__ int ltm_bin(float u) { return (int)u; }
+__device__ __forceinline__ float ltm_frac(float u) { return __builtin_amdgcn_fractf(u); }
 
 // Statistics pass of the local tone map over one tile: the global statistics
 // partial of each wave (as tm_pass1_tile) and the tile's soft histogram of u
@@ -1274,7 +1282,7 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
     constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
     const LtmRef r = ltm_ref(im, tile);
     const Enc e{im.unit, 255.0f};
-    const float lo2 = hw_log2(tm.eps);
+    const float u0 = ltm_u0(hw_log2(tm.eps));
     if (threadIdx.x < kLtmBins)
         lds_hist[threadIdx.x] = 0u;
     __syncthreads();
@@ -1289,6 +1297,7 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
             float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, xlog2(l0, im.unit, tm.eps))));
     }
     const bool staged = im.staged != 0;
+    // one pixel into the statistics and the histogram (the caller counts it)
     auto add = [&](float l) {
         const float x2 = xlog2(l, im.unit, tm.eps);
         const float d = x2 - K;
@@ -1296,10 +1305,9 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
         q = fmaf(d, d, q);
         lo = fminf(lo, l);
         hi = fmaxf(hi, l);
-        cnt += 1.0f;
-        const float u = ltm_u(x2, lo2);
-        const int k = min((int)u, kLtmBins - 2);
-        const unsigned whi = (unsigned)fmaf(u - (float)k, (float)kLtmOne, 0.5f);
+        const float u = ltm_u(x2, u0);
+        const int k = ltm_bin(u);
+        const unsigned whi = (unsigned)fmaf(ltm_frac(u), (float)kLtmOne, 0.5f);
         atomicAdd(&lds_hist[k], kLtmOne - whi);
         atomicAdd(&lds_hist[k + 1], whi);
         return x2;
@@ -1327,6 +1335,7 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
                                     chan<SRC>(w[i], 3 * j + 2), im.k);
                     x[j] = add(v[j]);
                 }
+                cnt += (float)PPU;
                 if (r.dst2)
                     store_unit<PPU, SF, SU>(r.dst2 + row * r.d2p, im.dst2_dtype, col, v, e);
                 if (staged)
@@ -1342,6 +1351,7 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
                 float l;
                 lum_at_px<SRC>(r.src + row * r.sp + col * 3 * ES, im.k, l);
                 const float x2 = add(l);
+                cnt += 1.0f;
                 if (r.dst2)
                     store_px<SF, SU>(r.dst2 + row * r.d2p, im.dst2_dtype, col, l, e);
                 if (staged)
@@ -1478,13 +1488,13 @@ __device__ __forceinline__ void ltm_stage(const DevImage &im, const LtmRef &r,
 // bilinear blend T_l of the four corner tiles' curves at u, and
 // T = T_g + strength (T_l - T_g). cy0/wy: the row's axis; cx0/wx: the
 // column's.
-__device__ __forceinline__ float ltm_value(float x2, float lo2, TmArgs tm, Curve cv,
+__device__ __forceinline__ float ltm_value(float x2, float u0, TmArgs tm, Curve cv,
                                            const LtmLds *lds, int cx0, float wx, int cy0, float wy)
 {
     const float tg = hw_rcp(1.0f + hw_exp2(cv.a * (x2 - cv.mu2)));
-    const float u = ltm_u(x2, lo2);
-    const int k = min((int)u, kLtmBins - 2);
-    const float f = u - (float)k;
+    const float u = ltm_u(x2, u0);
+    const int k = ltm_bin(u);
+    const float f = ltm_frac(u);
     // the four corners' entries for bin k sit at fixed distances from the
     // first one, so a single address serves all four LDS reads
     const LtmLds *c = lds + (cy0 * 3 + cx0) * kLtmBins + k;
@@ -1510,7 +1520,7 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
     constexpr int ES = elem_size(SRC);
     const LtmRef r = ltm_ref(im, tile);
     const Enc e{1.0f, 255.0f};
-    const float lo2 = hw_log2(tm.eps);
+    const float u0 = ltm_u0(hw_log2(tm.eps));
     if (r.vec) {
         // rows past the image's end (bottom tiles) load the last row again, so
         // every load is unconditional and all of them are in flight together,
@@ -1543,7 +1553,7 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
                 for (int j = 0; j < PPU; ++j) {
                     const float l = lum<SRC>(chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
                                              chan<SRC>(w[i], 3 * j + 2), im.k);
-                    v[j] = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j], wx[j],
+                    v[j] = ltm_value(xlog2(l, im.unit, tm.eps), u0, tm, cv, lds, cx0[j], wx[j],
                                      cy0, wy);
                 }
                 store_unit<PPU, false, true>(r.dst + row * r.dp, im.dst_dtype, col, v, e);
@@ -1563,7 +1573,7 @@ __device__ __forceinline__ void ltm_pass2_tile(const DevImage &im, int64_t tile,
                 ltm_axis(col, r.tx, r.nx, cx0, wx);
                 ltm_axis(row, r.ty, r.ny, cy0, wy);
                 store_px<false, true>(r.dst + row * r.dp, im.dst_dtype, col,
-                                      ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0,
+                                      ltm_value(xlog2(l, im.unit, tm.eps), u0, tm, cv, lds, cx0,
                                                 wx, cy0, wy),
                                       e);
             }
@@ -1582,7 +1592,7 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
     constexpr int PPU = 4;
     constexpr int U = kStatsPxPerThread / PPU;
     const LtmRef r = ltm_ref(im, tile);
-    const float lo2 = hw_log2(tm.eps);
+    const float u0 = ltm_u0(hw_log2(tm.eps));
     if (r.vec) {
         float w[U][PPU];
 #pragma unroll
@@ -1617,7 +1627,7 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
                 unsigned o[PPU];
 #pragma unroll
                 for (int j = 0; j < PPU; ++j)
-                    o[j] = __builtin_bit_cast(unsigned, ltm_value(w[i][j], lo2, tm, cv, lds, cx0[j],
+                    o[j] = __builtin_bit_cast(unsigned, ltm_value(w[i][j], u0, tm, cv, lds, cx0[j],
                                                                   wx[j], cy0, wy));
                 put(gpw<u32x4>(r.dst + row * r.dp + col * 4), u32x4{o[0], o[1], o[2], o[3]});
             }
@@ -1634,7 +1644,7 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
                 float wx, wy;
                 ltm_axis(col, r.tx, r.nx, cx0, wx);
                 ltm_axis(row, r.ty, r.ny, cy0, wy);
-                *p = ltm_value(*p, lo2, tm, cv, lds, cx0, wx, cy0, wy);
+                *p = ltm_value(*p, u0, tm, cv, lds, cx0, wx, cy0, wy);
             }
         }
     }
@@ -1688,7 +1698,7 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
     constexpr int ES = elem_size(SRC);
     const LtmRef r = ltm_ref(im, tile);
     const Enc e{1.0f, 1.0f};
-    const float lo2 = hw_log2(tm.eps);
+    const float u0 = ltm_u0(hw_log2(tm.eps));
     const int dt = U8 ? 0 : im.dst_dtype;
     uint8_t *dst = im.dst + (int64_t)r.ty * kLtmTile * r.dp +
                    (int64_t)r.tx * kLtmTile * 3 * elem_size(im.dst_dtype);
@@ -1722,7 +1732,7 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
                     const float R = chan<SRC>(w[i], 3 * j), G = chan<SRC>(w[i], 3 * j + 1),
                                 B = chan<SRC>(w[i], 3 * j + 2);
                     const float l = lum<SRC>(R, G, B, im.k);
-                    const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0[j],
+                    const float T = ltm_value(xlog2(l, im.unit, tm.eps), u0, tm, cv, lds, cx0[j],
                                               wx[j], cy0, wy);
                     colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, &o[3 * j]);
                 }
@@ -1743,7 +1753,7 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
                 float wx, wy;
                 ltm_axis(col, r.tx, r.nx, cx0, wx);
                 ltm_axis(row, r.ty, r.ny, cy0, wy);
-                const float T = ltm_value(xlog2(l, im.unit, tm.eps), lo2, tm, cv, lds, cx0, wx,
+                const float T = ltm_value(xlog2(l, im.unit, tm.eps), u0, tm, cv, lds, cx0, wx,
                                           cy0, wy);
                 float o[3];
                 colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, o);
