@@ -65,12 +65,13 @@ def test_sweep_equals_single_calls(dev, kind, h, w, odt):
                   rel=kind != "u8")
 
 
+@pytest.mark.parametrize("kind", ["u8", "f16"])
 @pytest.mark.parametrize("npairs", [2, 7, 20, 45])
-def test_sweep_pair_chunks(dev, npairs):
+def test_sweep_pair_chunks(dev, npairs, kind):
     """More pairs than the image has tiles to spread over: the pairs split into
     chunks (the last one short) and every output still equals a single call."""
     rng = np.random.default_rng(40 + npairs)
-    img = synth.sdr_pixels(rng, 300, 400)
+    img = synth.sdr_pixels(rng, 300, 400) if kind == "u8" else synth.hdr_pixels(rng, 300, 400)
     betas = [(float(a), float(b)) for a, b in rng.uniform(0.0, 1.0, (npairs, 2))]
     x = to_dev(img, dev)
     sweep = P.beta_sweep(x, betas)
@@ -78,7 +79,8 @@ def test_sweep_pair_chunks(dev, npairs):
         assert torch.equal(sweep[i], P.decolorize(x, beta_r=br, beta_k=bk)), (i, br, bk)
     got = sweep.cpu().numpy()
     for i in (0, npairs - 1):
-        check_f32(got[i], oracle.decolorize(img, *betas[i]), "pair %d of %d" % (i, npairs))
+        check_f32(got[i], oracle.decolorize(img, *betas[i]), "pair %d of %d" % (i, npairs),
+                  rel=kind != "u8")
 
 
 def test_sweep_row_walk(dev):
@@ -92,3 +94,21 @@ def test_sweep_row_walk(dev):
         for buf, (br, bk) in zip(bufs, BETAS[:6]):
             assert torch.equal(buf[:, :208], P.decolorize(x, beta_r=br, beta_k=bk)), (pad, br, bk)
             assert bool((buf[:, 208:] == -1.0).all())
+
+
+def test_mixed_images_and_weights(dev):
+    imgs = [synth.sdr_pixels(np.random.default_rng(34), 50, 60),
+            synth.hdr_pixels(np.random.default_rng(35), 30, 700),
+            synth.random_image(36, 3, 5, np.float32)]
+    betas = [(0.9, 0.6), (0.55, 0.8), (0.1, 0.95)]
+    xs = [to_dev(a, dev) for a in imgs]
+    outs = P.decolorize_betas(xs, betas, torch.float16)
+    for x, o, (br, bk) in zip(xs, outs, betas):
+        assert torch.equal(o, P.decolorize(x, torch.float16, beta_r=br, beta_k=bk))
+
+
+def test_rejects_bad_weights(dev):
+    x = to_dev(synth.random_image(37, 4, 4, np.uint8), dev)
+    with pytest.raises(P.DecolorError) as e:
+        P.decolorize_betas([x, x], [(0.5, 0.5), (1.5, 0.5)])
+    assert e.value.status == P.DC_ERR_INVALID_ARG
