@@ -65,6 +65,8 @@ def _load():
     lib.ref_comparator_image.argtypes = [vp, i32, i32, i32, i64, i32, vp]
     lib.ref_tonemap_stats.restype = None
     lib.ref_tonemap_stats.argtypes = [vp, i64, d, vp]
+    lib.ref_tonemap_stats_counted.restype = None
+    lib.ref_tonemap_stats_counted.argtypes = [vp, vp, i64, d, vp]
     lib.ref_tonemap_curve.restype = d
     lib.ref_tonemap_curve.argtypes = [d, d, d, d, d, d]
     lib.ref_tonemap_curve_array.restype = None
@@ -182,6 +184,18 @@ def tonemap_stats(lhat, eps=1e-4):
     st = np.zeros(4, np.float64)
     _load().ref_tonemap_stats(_ptr(a), a.size, eps, _ptr(st))
     return {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": a.size}
+
+
+def tonemap_stats_counted(lhat, counts, eps=1e-4):
+    """tonemap_stats of the multiset in which value lhat[i] occurs counts[i]
+    times (an image given as the histogram of its colours)."""
+    a = np.ascontiguousarray(lhat, np.float64).ravel()
+    c = np.ascontiguousarray(counts, np.int64).ravel()
+    if a.size != c.size:
+        raise ValueError("lhat and counts differ in size")
+    st = np.zeros(4, np.float64)
+    _load().ref_tonemap_stats_counted(_ptr(a), _ptr(c), a.size, eps, _ptr(st))
+    return {"mu": st[0], "sigma": st[1], "l_min": st[2], "l_max": st[3], "count": int(c.sum())}
 
 
 def tonemap_curve(lhat, mu, sigma, eps=1e-4, contrast=2.0, sigma_floor=1e-3):

@@ -26,7 +26,10 @@
  *     input and Lhat = L for float input (L is degree-1 homogeneous, so the
  *     scale only fixes the unit of the output).
  *   - A black pixel (R + G + B == 0) has L = 0, the limit of Eqs. (4)-(6).
- *   - NaN and negative channel values are read as 0.
+ *   - NaN and negative channel values are read as 0. A binary16 channel of
+ *     +Inf reads as 65504, the format's largest finite value; a binary32
+ *     channel above 1e18 (+Inf included) reads as 1e18, the top of the range
+ *     the library accepts for linear input.
  *   - beta_R and beta_k may be anywhere in the closed interval [0, 1].
  *   - u8 encode rounds half up and clamps: min(255, floor(255 Lhat + 0.5)).
  *   - f16 encode is IEEE binary16 round-to-nearest-even.
@@ -186,6 +189,8 @@ double ref_comparator_px(double r, double g, double b, int kind)
     return (116.0 * f - 16.0) / 100.0;
 }
 
+static double load_channel(const unsigned char *p, int dtype, int c);
+
 /* A comparator channel of every pixel of an interleaved HWC image, in
  * normalised units (row-major, packed out). Returns 0, or -1 on a bad
  * argument. */
@@ -202,24 +207,9 @@ int ref_comparator_image(const void *src, int dtype, int W, int H, int64_t pitch
         const unsigned char *row = (const unsigned char *)src + (int64_t)y * pitch_bytes;
         for (int x = 0; x < W; ++x) {
             const unsigned char *p = row + (int64_t)3 * es * x;
-            double r = 0, g = 0, b = 0;
-            if (dtype == REF_U8) {
-                r = p[0];
-                g = p[1];
-                b = p[2];
-            } else if (dtype == REF_F16) {
-                uint16_t h[3];
-                memcpy(h, p, 6);
-                r = ref_half_to_double(h[0]);
-                g = ref_half_to_double(h[1]);
-                b = ref_half_to_double(h[2]);
-            } else {
-                float f[3];
-                memcpy(f, p, 12);
-                r = f[0];
-                g = f[1];
-                b = f[2];
-            }
+            double r = load_channel(p, dtype, 0);
+            double g = load_channel(p, dtype, 1);
+            double b = load_channel(p, dtype, 2);
             out[(int64_t)y * W + x] = ref_comparator_px(r / unit, g / unit, b / unit, kind);
         }
     }
@@ -255,6 +245,15 @@ void ref_decode_f16_array(const uint16_t *h, int64_t n, double *out)
 
 /* ------------------------------------------------------------ whole images */
 
+/* Upper end of a float channel: +Inf in binary16 reads as 65504 (the largest
+ * finite binary16), anything above 1e18 in binary32 as 1e18 (the top of the
+ * supported range). NaN passes through (sanitise reads it as 0). */
+static double cap_channel(double v, int dtype)
+{
+    const double hi = dtype == REF_F16 ? 65504.0 : 1e18;
+    return v > hi ? hi : v;
+}
+
 static double load_channel(const unsigned char *p, int dtype, int c)
 {
     switch (dtype) {
@@ -263,12 +262,12 @@ static double load_channel(const unsigned char *p, int dtype, int c)
     case REF_F16: {
         uint16_t h;
         memcpy(&h, p + 2 * c, 2);
-        return ref_half_to_double(h);
+        return cap_channel(ref_half_to_double(h), REF_F16);
     }
     default: {
         float f;
         memcpy(&f, p + 4 * c, 4);
-        return (double)f;
+        return cap_channel((double)f, REF_F32);
     }
     }
 }
@@ -382,6 +381,42 @@ void ref_tonemap_stats(const double *lhat, int64_t n, double eps, double *stats)
     }
     stats[0] = mu;
     stats[1] = sqrt(ss / (double)n);
+    stats[2] = mn;
+    stats[3] = mx;
+}
+
+/* The same statistics over a multiset of values: value lhat[i] occurs count[i]
+ * times (count[i] >= 0), so an image can be given as the histogram of its
+ * colours. The total count is the number of pixels; values with count 0 take
+ * no part, also not in the extremes. */
+void ref_tonemap_stats_counted(const double *lhat, const int64_t *count, int64_t n, double eps,
+                               double *stats)
+{
+    double total = 0.0, sum = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (count[i] <= 0)
+            continue;
+        total += (double)count[i];
+        sum += (double)count[i] * log(lhat[i] + eps);
+        if (lhat[i] < mn)
+            mn = lhat[i];
+        if (lhat[i] > mx)
+            mx = lhat[i];
+    }
+    if (total == 0.0) {
+        stats[0] = stats[1] = stats[2] = stats[3] = 0.0;
+        return;
+    }
+    double mu = sum / total;
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (count[i] <= 0)
+            continue;
+        double d = log(lhat[i] + eps) - mu;
+        ss += (double)count[i] * d * d;
+    }
+    stats[0] = mu;
+    stats[1] = sqrt(ss / total);
     stats[2] = mn;
     stats[3] = mx;
 }

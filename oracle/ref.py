@@ -65,6 +65,18 @@ def half_bits_to_float(bits):
     return sign * (1.0 + fraction / 1024.0) * 2.0 ** (exponent - 15)
 
 
+def decode(px, dtype):
+    """The three channel values of a pixel as the method reads them: binary16
+    bit patterns decoded, +Inf in binary16 read as 65504 (its largest finite
+    value), binary32 values above 1e18 (the top of the supported range, +Inf
+    included) read as 1e18; NaN and negatives are left to _clean."""
+    if dtype == "f16":
+        return [min(half_bits_to_float(int(v)), 65504.0) for v in px]
+    if dtype == "f32":
+        return [min(float(v), 1e18) if v == v else float(v) for v in px]
+    return [float(v) for v in px]
+
+
 def decolorize_image(pixels, dtype, beta_r=BETA_R, beta_k=BETA_K):
     """Normalised luminance of a nested-list image [[(r, g, b), ...], ...].
 
@@ -75,8 +87,7 @@ def decolorize_image(pixels, dtype, beta_r=BETA_R, beta_k=BETA_K):
     for row in pixels:
         out_row = []
         for px in row:
-            if dtype == "f16":
-                px = [half_bits_to_float(int(v)) for v in px]
+            px = decode(px, dtype)
             lum = luminance(px[0], px[1], px[2], beta_r, beta_k)
             out_row.append(lum / 255.0 if dtype == "u8" else lum)
         out.append(out_row)
@@ -144,8 +155,7 @@ def tonemap_colour(pixels, dtype, eps, contrast, sigma_floor, saturation,
     for row, lrow in zip(pixels, lhat):
         out_row, t_row = [], []
         for px, lh in zip(row, lrow):
-            if dtype == "f16":
-                px = [half_bits_to_float(int(v)) for v in px]
+            px = decode(px, dtype)
             t = tonemap_curve(lh, eps, contrast, mu, sigma, sigma_floor)
             out_row.append(tuple(colour_channel(float(v) / unit, lh, t, saturation) for v in px))
             t_row.append(t)

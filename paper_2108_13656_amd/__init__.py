@@ -422,6 +422,25 @@ def channel_batch(xs, channel, out_dtype=torch.float32, out2_dtype=None, outs=No
     return outs if outs2 is None else list(zip(outs, outs2))
 
 
+def _stats_ptr(stats, n, dev):
+    """Device address of a caller's statistics tensor, after checking that the
+    kernels can write n entries of STATS_BYTES there: a contiguous tensor on
+    the images' device holding at least n * STATS_BYTES bytes. None gives 0
+    (no statistics)."""
+    if stats is None:
+        return ctypes.c_void_p(0)
+    if not isinstance(stats, torch.Tensor):
+        raise ValueError("stats must be a torch tensor")
+    if stats.device != dev:
+        raise ValueError("stats must be on %s (the images' device), not %s" % (dev, stats.device))
+    if not stats.is_contiguous():
+        raise ValueError("stats must be contiguous")
+    have = stats.numel() * stats.element_size()
+    if have < n * STATS_BYTES:
+        raise ValueError("stats holds %d bytes; %d images need %d" % (have, n, n * STATS_BYTES))
+    return ctypes.c_void_p(stats.data_ptr())
+
+
 def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, beta_k=BETA_K,
                    eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR, outs=None,
                    lhats=None, stats=None, want_stats=True, stream=None, colour=False,
@@ -445,8 +464,7 @@ def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, 
     p = _params(beta_r, beta_k)
     tm = DcTmParams(eps, contrast, sigma_floor, saturation, TM_LOCAL_STRENGTH)
     context(dev).call(lib().dc_tonemap_global, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
-                      ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
-                      _stream_ptr(stream, dev))
+                      _stats_ptr(stats, len(xs), dev), _stream_ptr(stream, dev))
     return outs, lhats, stats
 
 
@@ -472,8 +490,7 @@ def tonemap_local(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, b
     p = _params(beta_r, beta_k)
     tm = DcTmParams(eps, contrast, sigma_floor, saturation, strength)
     context(dev).call(lib().dc_tonemap_local, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
-                      ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
-                      _stream_ptr(stream, dev))
+                      _stats_ptr(stats, len(xs), dev), _stream_ptr(stream, dev))
     return outs, lhats, stats
 
 
@@ -517,7 +534,7 @@ class Plan:
         self._ctx = context(self.device)
         self._ctx.call(lib().dc_plan_create, kind, arr, len(xs), ctypes.byref(p),
                        ctypes.byref(tm) if tm is not None else None,
-                       ctypes.c_void_p(stats.data_ptr() if stats is not None else 0),
+                       _stats_ptr(stats, len(xs), self.device),
                        PLAN_GRAPH if graph else 0, ctypes.byref(self._h))
 
     def run(self, stream=None):

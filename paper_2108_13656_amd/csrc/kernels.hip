@@ -53,20 +53,34 @@ __device__ __forceinline__ float lum_code(float R, float G, float B, Coef k)
     return Y * hw_rsq(Y * fmaf(S, S, 1e-6f));
 }
 
+// A float channel as every kernel reads it: NaN and negatives as lo, values
+// above hi as hi. hi is the input format's ceiling: 65504, the largest finite
+// binary16 (so +Inf reads as 65504), or 1e18, the top of the supported binary32
+// range (+Inf included). NaN goes to lo because max returns its non-NaN operand.
+__device__ __forceinline__ float chan_clamp(float v, float lo, float hi)
+{
+    return fminf(fmaxf(v, lo), hi);
+}
+template <int SRC>
+__host__ __device__ constexpr float chan_max()
+{
+    return SRC == 1 ? 65504.0f : 1e18f;
+}
+
 // L for binary16 input: the division-free form of lum_code on the decoded
 // values (the same four constants), finished as sqrt(Y) / S. Binary16 spans
 // 6e-8 .. 65504, so Y stays between about 1e-30 and 5e20 and no intermediate
-// leaves the FP32 normal range; NaN and negative channels read as 0 (max
-// returns the non-NaN operand). Blue reads as at least 1e-30, which keeps
+// leaves the FP32 normal range; NaN and negative channels read as 0 and +Inf
+// as 65504 (chan_clamp). Blue reads as at least 1e-30, which keeps
 // S > 0 without a clamp of its own and changes no result: binary16 has no
 // value below 6e-8 but 0, and every term of 1e-30 either underflows to 0
 // (B^2, C^2) or is absorbed (in S, G + B), so a black pixel still gives
 // sqrt(0) * (1 / 1e-30) = 0.
 __device__ __forceinline__ float lum_half(float R, float G, float B, Coef k)
 {
-    R = fmaxf(R, 0.0f);
-    G = fmaxf(G, 0.0f);
-    B = fmaxf(B, 1e-30f);
+    R = chan_clamp(R, 0.0f, chan_max<1>());
+    G = chan_clamp(G, 0.0f, chan_max<1>());
+    B = chan_clamp(B, 1e-30f, chan_max<1>());
     const float rr = R * R, gg = G * G;
     const float Q = hw_sqrt(fmaf(B, B, fmaf(R, R, gg)));          // sqrt(3) * Eq. (1)
     const float Lgr3 = hw_sqrt(fmaf(k.cr, rr, k.cg * gg));        // sqrt(3) * Eq. (3)
@@ -81,12 +95,12 @@ __device__ __forceinline__ float lum_half(float R, float G, float B, Coef k)
 // L for linear float input. The pixel is first normalised by S, so every
 // intermediate lies in [0, 1] whatever the radiance scale (binary16 spans
 // 6e-8 .. 65504), and L = S * L(r, g, b) by degree-1 homogeneity. NaN and
-// negative channels read as 0 (max returns the non-NaN operand).
+// negative channels read as 0, values above 1e18 as 1e18 (chan_clamp).
 __device__ __forceinline__ float lum_linear(float R, float G, float B, Coef k)
 {
-    R = fmaxf(R, 0.0f);
-    G = fmaxf(G, 0.0f);
-    B = fmaxf(B, 0.0f);
+    R = chan_clamp(R, 0.0f, chan_max<2>());
+    G = chan_clamp(G, 0.0f, chan_max<2>());
+    B = chan_clamp(B, 0.0f, chan_max<2>());
     const float S = (R + G) + B;
     const float inv = hw_rcp(fmaxf(S, 1e-30f));
     const float r = R * inv, g = G * inv, b = B * inv;
@@ -609,13 +623,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const DevImage *__restrict__ t
 // path (Table I's same-machine comparison, on the GPU): CH 1 = the rgb2gray
 // weighted sum quoted in Sec. I, CH 2 = V of HSV, CH 3 = CIE 1976 L* / 100
 // built on that Y with white Y_n = 1 (cube root as exp2(log2(y) / 3)).
-// Inputs are scaled to normalised units first; NaN and negatives read as 0.
-template <int CH>
+// Inputs are scaled to normalised units first; float channels read as
+// chan_clamp leaves them (NaN and negatives 0, past the format's ceiling the
+// ceiling).
+template <int SRC, int CH>
 __device__ __forceinline__ float comparator_px(float R, float G, float B, float unit)
 {
-    R = fmaxf(R, 0.0f) * unit;
-    G = fmaxf(G, 0.0f) * unit;
-    B = fmaxf(B, 0.0f) * unit;
+    if constexpr (SRC != 0) {
+        R = chan_clamp(R, 0.0f, chan_max<SRC>());
+        G = chan_clamp(G, 0.0f, chan_max<SRC>());
+        B = chan_clamp(B, 0.0f, chan_max<SRC>());
+    }
+    R *= unit;
+    G *= unit;
+    B *= unit;
     if constexpr (CH == 2) {
         return fmaxf(R, fmaxf(G, B));
     } else {
@@ -651,7 +672,7 @@ __device__ __forceinline__ void channel_tile(const DevImage &im, int64_t tile)
             float v[PPU];
 #pragma unroll
             for (int j = 0; j < PPU; ++j)
-                v[j] = comparator_px<CH>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
+                v[j] = comparator_px<SRC, CH>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
                                          chan<SRC>(w[u], 3 * j + 2), im.unit);
             const uint32_t lp = slot_lp<PPU>(true, u, 0);
             store_unit<PPU, false, true>(t.dst, im.dst_dtype, lp, v, e);
@@ -667,7 +688,7 @@ __device__ __forceinline__ void channel_tile(const DevImage &im, int64_t tile)
         if (p < rem) {
             float R, G_, B;
             load_px<SRC>(t.src + p * (3 * ES), R, G_, B);
-            const float v = comparator_px<CH>(R, G_, B, im.unit);
+            const float v = comparator_px<SRC, CH>(R, G_, B, im.unit);
             store_px<false, true>(t.dst, im.dst_dtype, p, v, e);
             if (t.dst2)
                 store_px<false, true>(t.dst2, im.dst2_dtype, p, v, e);
@@ -866,9 +887,30 @@ __device__ __forceinline__ Part part_of(const WavePart &w, float unit)
     return Part{w.n, w.K + m, fmaxf(fmaf(-w.s, m, w.q), 0.0f), w.lo * unit, w.hi * unit};
 }
 
-// Level 1 of the statistics combine: block g merges the fixed group of up to
-// kBlock consecutive wave partials g - grp_begin of its image (one per thread,
-// loaded in parallel) with a fixed LDS tree, and writes one group partial.
+// Level 1 of the statistics combine for group g (global numbering) of image
+// im: the workgroup merges the fixed group of up to kBlock consecutive wave
+// partials g - grp_begin of the image (one per thread, loaded in parallel) with
+// a fixed LDS tree, and thread 0 writes one group partial. Every thread of the
+// workgroup takes part; sh is kBlock entries of LDS.
+__device__ __forceinline__ void combine_group(const DevImage &im, int64_t g,
+                                              const WavePart *__restrict__ parts,
+                                              Part *__restrict__ parts2, Part *sh)
+{
+    const int64_t nparts = im.ntiles * kWavesPerBlock;
+    const int64_t c = (g - im.grp_begin) * kBlock + threadIdx.x;
+    const int tid = threadIdx.x;
+    sh[tid] = c < nparts ? part_of(parts[im.chunk_begin + c], im.unit) : part_empty();
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] = merge(sh[tid], sh[tid + s]);
+        __syncthreads();
+    }
+    if (tid == 0)
+        parts2[g] = sh[0];
+}
+
+// Level 1 as a kernel: block g merges group g0 + g.
 __global__ __launch_bounds__(kBlock) void k_tm_combine(const DevImage *__restrict__ table,
                                                        const int64_t *__restrict__ grp_end,
                                                        int img0, int nimg, int64_t g0,
@@ -886,32 +928,18 @@ __global__ __launch_bounds__(kBlock) void k_tm_combine(const DevImage *__restric
             lo = mid + 1;
     }
     const DevImage im = table[lo];
-    const int64_t nparts = im.ntiles * kWavesPerBlock;
-    const int64_t c = (g - im.grp_begin) * kBlock + threadIdx.x;
-    const int tid = threadIdx.x;
-    sh[tid] = c < nparts ? part_of(parts[im.chunk_begin + c], im.unit) : part_empty();
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (tid < s)
-            sh[tid] = merge(sh[tid], sh[tid + s]);
-        __syncthreads();
-    }
-    if (tid == 0)
-        parts2[g] = sh[0];
+    combine_group(im, g, parts, parts2, sh);
 }
 
-// Level 2: one workgroup per image merges the image's group partials in a
-// fixed order, then writes the curve coefficients (and, when asked, the
-// statistics for the caller).
-__global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restrict__ table,
-                                                        int img0, TmArgs tm,
-                                                        const Part *__restrict__ parts2,
-                                                        Curve *__restrict__ curves,
-                                                        StatsOut *__restrict__ stats)
+// Level 2 for image number img of the table: the workgroup merges the image's
+// group partials in a fixed order, then thread 0 writes the curve
+// coefficients (and, when asked, the statistics for the caller). Every thread
+// takes part; sh is kBlock entries of LDS.
+__device__ __forceinline__ void finalize_image(const DevImage &im, int img, TmArgs tm,
+                                              const Part *__restrict__ parts2,
+                                              Curve *__restrict__ curves,
+                                              StatsOut *__restrict__ stats, Part *sh)
 {
-    __shared__ Part sh[kBlock];
-    const int img = img0 + blockIdx.x;
-    const DevImage im = table[img];
     const int tid = threadIdx.x;
     Part a = part_empty();
     for (int64_t c = tid; c < im.ngrp; c += kBlock)
@@ -943,6 +971,19 @@ __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restri
             stats[im.image] = o;
         }
     }
+}
+
+// Level 2 as a kernel: one workgroup per image, images img0 + blockIdx.x.
+__global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restrict__ table,
+                                                        int img0, TmArgs tm,
+                                                        const Part *__restrict__ parts2,
+                                                        Curve *__restrict__ curves,
+                                                        StatsOut *__restrict__ stats)
+{
+    __shared__ Part sh[kBlock];
+    const int img = img0 + blockIdx.x;
+    const DevImage im = table[img];
+    finalize_image(im, img, tm, parts2, curves, stats, sh);
 }
 
 // T = 1 / (1 + exp2(a (x2 - mu2))) of one pixel.
@@ -1024,9 +1065,9 @@ __device__ __forceinline__ void colour_px(float R, float G, float B, float l, fl
 {
     constexpr float kOut = U8 ? 255.0f : 1.0f;
     if constexpr (SRC != 0) {
-        R = fmaxf(R, 0.0f);
-        G = fmaxf(G, 0.0f);
-        B = fmaxf(B, 0.0f);
+        R = chan_clamp(R, 0.0f, chan_max<SRC>());
+        G = chan_clamp(G, 0.0f, chan_max<SRC>());
+        B = chan_clamp(B, 0.0f, chan_max<SRC>());
     }
     if constexpr (MODE == kColourGrey) {
         o[0] = o[1] = o[2] = hw_rcp(1.0f + E) * kOut;
@@ -1661,9 +1702,9 @@ __device__ __forceinline__ void colour_of_t(float R, float G, float B, float l, 
 {
     constexpr float kOut = U8 ? 255.0f : 1.0f;
     if constexpr (SRC != 0) {
-        R = fmaxf(R, 0.0f);
-        G = fmaxf(G, 0.0f);
-        B = fmaxf(B, 0.0f);
+        R = chan_clamp(R, 0.0f, chan_max<SRC>());
+        G = chan_clamp(G, 0.0f, chan_max<SRC>());
+        B = chan_clamp(B, 0.0f, chan_max<SRC>());
     }
     if constexpr (MODE == kColourGrey) {
         o[0] = o[1] = o[2] = T * kOut;

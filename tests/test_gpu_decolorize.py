@@ -48,9 +48,13 @@ def test_gradient_rects_512(dev):
 
 
 def test_f16_channel_sweep(dev):
-    """Every non-negative finite binary16 value in each channel, crossed with a
-    grid of values of the other two channels."""
-    halves = np.arange(0, 0x7C00, dtype=np.uint16).view(np.float16)  # 0 .. 65504
+    """Every non-negative binary16 value in each channel (0 .. 65504 and +Inf,
+    which reads as 65504), plus NaN, -Inf, -0 and a negative subnormal (which
+    read as 0), crossed with a grid of values of the other two channels; true
+    relative error 1e-5 everywhere (the flush floor 1e-30 lies below every
+    nonzero binary16 result)."""
+    extra = np.array([0x7E00, 0xFC00, 0x8000, 0x8001], np.uint16)
+    halves = np.concatenate([np.arange(0, 0x7C01, dtype=np.uint16), extra]).view(np.float16)
     grid = np.array([0.0, 6e-8, 1e-3, 0.5, 1.0, 7.25, 100.0, 65504.0], np.float16)
     for ch in range(3):
         others = [c for c in range(3) if c != ch]
@@ -69,18 +73,19 @@ def test_f16_channel_sweep(dev):
 
 
 def test_f32_special_values(dev):
-    vals = np.array([0.0, -1.0, np.nan, 1e-40, 1e-20, 1e-6, 0.3, 1.0, 255.0, 1e6, 1e18],
-                    np.float32)
+    """Zero, negatives, NaN, +-Inf, subnormals and values up to and past the
+    1e18 ceiling in every combination of channels: relative 1e-5, with values
+    below 1e-30 allowed to flush (absolute error < 1e-30); +Inf and 3e18 read as
+    1e18."""
+    vals = np.array([0.0, -1.0, np.nan, -np.inf, np.inf, 1e-40, 1e-20, 1e-6, 0.3, 1.0, 255.0,
+                     1e6, 1e18, 3e18], np.float32)
     r, g, b = np.meshgrid(vals, vals, vals, indexing="ij")
-    img = np.stack([r.ravel(), g.ravel(), b.ravel()], -1).reshape(-1, 11, 3).astype(np.float32)
+    img = np.stack([r.ravel(), g.ravel(), b.ravel()], -1).reshape(-1, vals.size, 3)
+    img = img.astype(np.float32)
     got = P.decolorize(to_dev(img, dev)).cpu().numpy()
     want = oracle.decolorize(img)
     assert np.all(np.isfinite(got))
-    err = np.abs(got - want) / np.maximum(np.abs(want), 1.0)
-    # values below 1e-30 may be flushed: the absolute error there is < 1e-30
-    err[want < 1e-30] = np.abs(got - want)[want < 1e-30] * 1e25
-    report("f32 special values: max scaled error %.3e" % err.max())
-    assert err.max() <= 1e-5
+    check_f32(got, want, "f32 special values", rel=True)
 
 
 def test_hdr_distribution(dev):

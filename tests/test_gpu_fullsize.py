@@ -235,8 +235,9 @@ def test_uneven_batch_every_pixel(dev, lut):
             worst8 = max(worst8, float(np.max(np.abs(got - lut[_codes(img)] / 255.0))))
         else:
             want = oracle.decolorize(img, nthreads=WORKERS)
-            worst16 = max(worst16, float(np.max(np.abs(got - want) / np.maximum(1.0, want))))
-    report("uneven batch: %d px, max |dL| u8 %.3e, f16 scaled %.3e" %
+            worst16 = max(worst16, check_f32(got, want, "uneven f16 %dx%d" % img.shape[:2],
+                                             rel=True))
+    report("uneven batch: %d px, max |dL| u8 %.3e, f16 relative %.3e" %
            (sum(a.shape[0] * a.shape[1] for a in imgs), worst8, worst16))
     assert worst8 <= 1e-5 and worst16 <= 1e-5
 
@@ -256,9 +257,7 @@ def test_image_larger_than_2gib(dev):
     got = out.view(-1)[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
     flat = img.reshape(-1, 3)[idx].astype(np.float64)
     want = np.array([oracle.luminance(*p) for p in flat])
-    err = float(np.max(np.abs(got - want) / np.maximum(1.0, want)))
-    report("14000^2 binary32 decolorize: max scaled error %.3e over %d px" % (err, idx.size))
-    assert err <= 1e-5
+    check_f32(got, want, "14000^2 binary32 decolorize", rel=True)
     del out
     _, _, stats = P.tonemap_global([x], torch.float16, **TM)
     st = P.stats_to_host(stats)[0]
@@ -275,10 +274,10 @@ def test_more_than_2_31_pixels(dev, lut):
     """One 8-bit image of 46400 x 46400 = 2.15e9 pixels (pixel indices past
     2^31, 6.5 GB of input made on the device): decolorization to 8-bit codes at
     a million sampled pixels and along the last row against the oracle's table
-    of all colours; the global tone map's pixel count, and its T at the same
-    pixels against the oracle curve evaluated with the statistics the GPU
-    found (the statistics themselves are checked against the oracle on the
-    smaller images above)."""
+    of all colours; the global tone map's statistics over every pixel against
+    the oracle's, computed in FP64 from the image's colour histogram (counted
+    on the device) and the oracle's value of each colour, and T at the sampled
+    pixels against the oracle curve with the oracle's statistics."""
     h = w = 46400
     assert h * w > 2 ** 31
     gen = torch.Generator(device=dev)
@@ -296,12 +295,28 @@ def test_more_than_2_31_pixels(dev, lut):
     assert d.max() <= 1
     u8_mismatches_at_ties(got, lhat)
     del out
+    # colour histogram on the device, in slabs of rows (int32 codes)
+    counts = torch.zeros(1 << 24, dtype=torch.int64, device=dev)
+    for r0 in range(0, h, 4096):
+        c = x[r0:r0 + 4096].reshape(-1, 3).to(torch.int32)
+        code = (c[:, 0] << 16) | (c[:, 1] << 8) | c[:, 2]
+        counts += torch.bincount(code, minlength=1 << 24)
+        del c, code
+    counts = counts.cpu().numpy()
+    assert int(counts.sum()) == h * w
+    ref = oracle.tonemap_stats_counted(lut / 255.0, counts, TM["eps"])
     t, _, stats = P.tonemap_global([x], torch.float32, **TM)
     st = P.stats_to_host(stats)[0]
     assert st["count"] == h * w
-    t_ref = oracle.tonemap_curve(lhat, st["mu"], st["sigma"], **TM)
+    report("46400^2 tone map: mu %.7f / %.7f, sigma %.7f / %.7f, min %.4g / %.4g, max %.4g / %.4g"
+           % (st["mu"], ref["mu"], st["sigma"], ref["sigma"], st["l_min"], ref["l_min"],
+              st["l_max"], ref["l_max"]))
+    assert abs(st["mu"] - ref["mu"]) <= 2e-5 * (1 + abs(ref["mu"]))
+    assert abs(st["sigma"] - ref["sigma"]) <= 2e-5 * ref["sigma"]
+    assert st["l_min"] == pytest.approx(ref["l_min"], rel=1e-5, abs=1e-6)
+    assert st["l_max"] == pytest.approx(ref["l_max"], rel=1e-5)
+    t_ref = oracle.tonemap_curve(lhat, ref["mu"], ref["sigma"], **TM)
     err = float(np.max(np.abs(t[0].view(-1)[tidx].cpu().numpy() - t_ref)))
-    report("46400^2 u8: %d px, codes off by one %d, tone map mu %.6f sigma %.6f, max |dT| %.2e "
-           "at %d sampled px" % (h * w, int(np.count_nonzero(d)), st["mu"], st["sigma"], err,
-                                 idx.size))
+    report("46400^2 u8: %d px, codes off by one %d, max |dT| %.2e at %d sampled px" %
+           (h * w, int(np.count_nonzero(d)), err, idx.size))
     assert err <= 1e-5

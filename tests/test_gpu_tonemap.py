@@ -220,6 +220,59 @@ def test_low_variance_image_within_derived_bound(dev):
     assert err <= bound
 
 
+def _t_fp32_bound(st_ref, lhat_ref):
+    """The FP32 conditioning term of T: c / (4 s) times 4e-7 (1 + |x|max), with
+    s = max(sigma, sigma_floor) (T's slope in x is at most c / (4 s); x and the
+    statistics carry log2, rcp and sqrt rounding of about 4e-7 (1 + |x|))."""
+    s = max(st_ref["sigma"], TM["sigma_floor"])
+    xmax = float(np.max(np.abs(np.log(lhat_ref + TM["eps"]))))
+    return TM["contrast"] / (4 * s) * 4e-7 * (1 + xmax), xmax
+
+
+@pytest.mark.parametrize("sigma", [0.5, 0.2, 0.1, 0.06, 0.04, 0.02, 0.01, 3e-3, 1e-3, 3e-4])
+def test_t_tolerance_over_sigma(dev, sigma):
+    """Where |dT| <= 1e-5 holds: images whose x = ln(Lhat + eps) has standard
+    deviation sigma (a fixed colour scaled by exp(sigma n), n standard normal).
+    With sigma_star = c 4e-7 (1 + |x|max) / (4e-5), the sigma at which the FP32
+    term of _t_fp32_bound reaches 1e-5 (about 0.045 for c = 2 and |x| <= 1.3),
+    T must be within 1e-5 for sigma >= sigma_star and within 1e-5 plus that
+    term below it."""
+    rng = np.random.default_rng(int(sigma * 1e6))
+    base = np.array([0.4, 0.35, 0.3])
+    scale = np.exp(sigma * rng.standard_normal((64, 96, 1)))
+    img = (base * scale).astype(np.float32)
+    t_ref, lhat_ref, st_ref = oracle.tonemap(img, **TM)
+    outs, _, _ = P.tonemap_global([to_dev(img, dev)], **TM)
+    term, xmax = _t_fp32_bound(st_ref, lhat_ref)
+    sigma_star = TM["contrast"] * 4e-7 * (1 + xmax) / (4 * 1e-5)
+    err = float(np.max(np.abs(outs[0].cpu().numpy() - t_ref)))
+    bound = 1e-5 if st_ref["sigma"] >= sigma_star else 1e-5 + term
+    report("sigma %.2e (sigma_star %.3f): |dT| %.2e, bound %.2e" % (st_ref["sigma"], sigma_star,
+                                                                    err, bound))
+    assert err <= bound
+
+
+def test_infinite_channels(dev):
+    """+Inf channels of a binary16 image read as 65504 and of a binary32 image
+    as 1e18 (NaN and -Inf as 0): the tone map stays finite and matches the
+    oracle, L-hat included."""
+    rng = np.random.default_rng(16)
+    for dtype, special in ((np.float16, [np.inf, -np.inf, np.nan]),
+                           (np.float32, [np.inf, -np.inf, np.nan, 5e18])):
+        img = synth.hdr_pixels(rng, 40, 70).astype(dtype)
+        for i, v in enumerate(special):
+            img[3 + i, 5:9, i % 3] = v
+        img[0, 0, :] = np.inf
+        t_ref, lhat_ref, st_ref = oracle.tonemap(img, **TM)
+        outs, lhats, stats = P.tonemap_global([to_dev(img, dev)], torch.float32, torch.float32,
+                                              **TM)
+        name = "inf %s" % np.dtype(dtype).name
+        assert np.all(np.isfinite(outs[0].cpu().numpy()))
+        _check_stats(P.stats_to_host(stats)[0], st_ref, name)
+        check_f32(outs[0].cpu().numpy(), t_ref, name + " T")
+        check_f32(lhats[0].cpu().numpy(), lhat_ref, name + " Lhat", rel=True)
+
+
 def test_hdr_storage_error_against_exact_radiance(dev):
     """The HDR error stated a second way: the GPU result from the binary16
     image against the FP64 oracle on the radiance it stores before rounding

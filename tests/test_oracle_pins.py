@@ -241,6 +241,27 @@ def test_tonemap_stats_vs_statistics_module(oracle_mod):
     assert (mu, sigma) == pytest.approx((st["mu"], st["sigma"]), rel=1e-13)
 
 
+def test_tonemap_stats_counted_vs_statistics_module(oracle_mod):
+    """Statistics of an image given as a histogram of its values: equal to the
+    statistics module's mean and population deviation of the expanded list of
+    x = ln(Lhat + eps), and to the per-pixel oracle on that list; zero counts
+    take no part, also not in the extremes."""
+    rng = np.random.default_rng(81)
+    vals = rng.random(40) * 3.0
+    counts = rng.integers(0, 6, 40)
+    counts[[0, 7]] = 0
+    vals[0], vals[7] = 100.0, 1e-9  # extremes that must not count
+    st = oracle_mod.tonemap_stats_counted(vals, counts, 1e-4)
+    expanded = np.repeat(vals, counts)
+    xs = [math.log(v + 1e-4) for v in expanded]
+    assert st["count"] == len(xs)
+    assert st["mu"] == pytest.approx(statistics.fmean(xs), rel=1e-13, abs=1e-15)
+    assert st["sigma"] == pytest.approx(statistics.pstdev(xs), rel=1e-12)
+    assert st["l_min"] == expanded.min() and st["l_max"] == expanded.max()
+    ref = oracle_mod.tonemap_stats(expanded, 1e-4)
+    assert (st["mu"], st["sigma"]) == pytest.approx((ref["mu"], ref["sigma"]), rel=1e-13)
+
+
 def test_tonemap_symmetry_monotone_exposure(oracle_mod):
     img = synth.random_image(9, 16, 16, np.float32, scale=5.0) + np.float32(0.01)
     t, lhat, st = oracle_mod.tonemap(img, eps=0.0, contrast=2.0, sigma_floor=1e-3)
@@ -275,3 +296,64 @@ def test_hdr_generator_exact_and_stored_agree():
     b = synth.hdr_pixels(np.random.default_rng(5), 7, 9, exact=True)
     assert a.dtype == np.float16 and b.dtype == np.float64
     np.testing.assert_array_equal(a, b.astype(np.float16))
+
+
+def _hand_table():
+    rows = []
+    with open(os.path.join(GOLDEN, "hand_table.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            cols = [c.strip() for c in line.split("|")]
+            rgb = tuple(eval(v, {"__builtins__": {}}) for v in cols[0].split())
+            rows.append((rgb, [float(c) for c in cols[1:7]], int(cols[7])))
+    return rows
+
+
+@pytest.mark.parametrize("row", _hand_table(), ids=lambda r: "%.4g,%.4g,%.4g" % r[0])
+def test_hand_table(oracle_mod, row):
+    """Pixels evaluated by hand from Eqs. (1)-(6) at beta_R = 0.55, beta_k = 0.8
+    (tests/golden/hand_table.txt): the four intermediate terms to their 8
+    printed digits, L to its 10, the Sec. I rgb2gray value to 4, and the 8-bit
+    code exactly; for the C oracle and the Python twin."""
+    rgb, want, code = row
+    c_terms = oracle_mod.luminance_terms(*rgb, 0.55, 0.8)
+    t = twin.luminance_terms(*rgb, 0.55, 0.8)
+    py_terms = (t[0], t[2], t[3], t[4], t[5])
+    for got in (c_terms, py_terms):
+        for g, w in zip(got[:4], want[:4]):
+            assert abs(g - w) <= 5e-9
+        assert abs(got[4] - want[4]) <= 1e-10
+    assert abs(0.2989 * rgb[0] + 0.5870 * rgb[1] + 0.1140 * rgb[2] - want[5]) <= 5e-5
+    assert int(oracle_mod.encode_u8(np.array([c_terms[4]]))[0]) == code
+    assert twin.encode_u8(py_terms[4]) == code
+
+
+def test_infinite_channels_read_as_format_maximum(oracle_mod):
+    """+Inf in a binary16 channel reads as 65504 and a binary32 channel above
+    1e18 as 1e18 (the reading for values past the input's range): a pure-red
+    +Inf pixel gives sqrt(beta_R beta_k) times that value (the red closed form,
+    scaled by degree-1 homogeneity), and every pixel with an infinite channel
+    equals the same pixel with the cap in its place, in the C oracle and the
+    Python twin."""
+    inf_h, cap_h = np.float16(np.inf), np.float16(65504.0)
+    img = np.array([[[inf_h, 0, 0], [inf_h, 1, 2], [0.5, inf_h, inf_h], [np.nan, -1, inf_h]]],
+                   np.float16)
+    capped = np.where(np.isinf(img), cap_h, img).astype(np.float16)
+    got = oracle_mod.decolorize(img)
+    assert got[0, 0] == pytest.approx(math.sqrt(0.55 * 0.8) * 65504.0, rel=1e-14)
+    np.testing.assert_array_equal(got, oracle_mod.decolorize(capped))
+    bits = img.view(np.uint16)
+    tw = twin.decolorize_image([[tuple(int(v) for v in px) for px in bits[0]]], "f16")
+    np.testing.assert_allclose(np.array(tw), got, rtol=1e-13)
+    f = np.array([[[np.inf, 0, 0], [3e18, 0, 0], [0.25, np.inf, 7.0], [0, 0, 2e20]]], np.float32)
+    gf = oracle_mod.decolorize(f)
+    red = math.sqrt(0.55 * 0.8) * 1e18  # the red closed form at the cap
+    assert gf[0, 0] == pytest.approx(red, rel=1e-14)
+    assert gf[0, 1] == gf[0, 0]
+    assert gf[0, 3] == pytest.approx(1e18 / math.sqrt(3.0), rel=1e-14)  # blue closed form
+    twf = twin.decolorize_image([[tuple(float(v) for v in px) for px in f[0]]], "f32")
+    np.testing.assert_allclose(np.array(twf), gf, rtol=1e-13)
+    # the tone map of an image with an infinite channel stays finite
+    t, _, st = oracle_mod.tonemap(np.concatenate([img, capped], 1))
+    assert np.all(np.isfinite(t)) and math.isfinite(st["mu"])
