@@ -196,6 +196,28 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
 int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_params *params,
                       const dc_tm_params *tm, dc_stats *stats, void *stream);
 
+/* For callers that cannot allocate (code that must not call hipMalloc or
+ * allocate host memory per call: tight serving loops, harnesses that forbid
+ * it): dc_tonemap_global with the same arguments and bit-identical results,
+ * but the call allocates nothing, on the device or the host. Its workspace
+ * (descriptor table, statistics partials, curves) is one fixed device array of
+ * DC_NOALLOC_SCRATCH_BYTES per device, held until the process ends and shared
+ * by every call of this entry point on that device: it keeps the last call's
+ * contents (every call rewrites what it reads), and calls that overlap on one
+ * device (on other streams, contexts or threads) race on it, so serialise
+ * them. The descriptor table goes up from pinned staging that dc_create sets
+ * aside; a call first waits for the previous call's upload (not its kernels).
+ * Limits: n <= DC_NOALLOC_MAX_IMAGES and about 340 Mpx per call (24 bytes of
+ * partials per 1024 pixels plus the table must fit the array); a larger call
+ * returns DC_ERR_INVALID_ARG before any work. It always runs the batch
+ * schedule (statistics pass over every image, combine, curve pass). Errors
+ * otherwise as dc_tonemap_global. */
+#define DC_NOALLOC_SCRATCH_BYTES (8 << 20)
+#define DC_NOALLOC_MAX_IMAGES 1024
+int dc_tonemap_global_noalloc(dc_ctx *ctx, const dc_image *imgs, int32_t n,
+                              const dc_params *params, const dc_tm_params *tm, dc_stats *stats,
+                              void *stream);
+
 /* Local tone map (Sec. III-B.2: tone curves from smoothed local cumulative
  * histograms, the paper's choice for its local operator; it defers the
  * algorithm to its cited O(1) design). Reading, per image:

@@ -139,6 +139,7 @@ def lib():
     L.dc_decolorize_batch.argtypes = [vp, img_p, i32, par_p, vp]
     L.dc_tonemap_global.argtypes = [vp, img_p, i32, par_p, tm_p, vp, vp]
     L.dc_tonemap_local.argtypes = [vp, img_p, i32, par_p, tm_p, vp, vp]
+    L.dc_tonemap_global_noalloc.argtypes = [vp, img_p, i32, par_p, tm_p, vp, vp]
     L.dc_status_string.argtypes = [ctypes.c_int]
     L.dc_status_string.restype = ctypes.c_char_p
     L.dc_last_error_message.argtypes = []
@@ -450,6 +451,31 @@ def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, 
     is a uint8 device tensor of n x 24 bytes (see ``stats_to_host``). Outputs
     are HxW T, or HxWx3 re-coloured RGB min(1, T (C / Lhat)^saturation) with
     colour=True (given ``outs`` may mix both shapes)."""
+    return _tonemap_global(lib().dc_tonemap_global, xs, out_dtype, lhat_dtype, beta_r, beta_k,
+                           eps, contrast, sigma_floor, outs, lhats, stats, want_stats, stream,
+                           colour, saturation)
+
+
+def tonemap_global_noalloc(xs, outs, lhats=None, stats=None, beta_r=BETA_R, beta_k=BETA_K,
+                           eps=TM_EPS, contrast=TM_CONTRAST, sigma_floor=TM_SIGMA_FLOOR,
+                           stream=None, saturation=TM_SATURATION):
+    """``tonemap_global`` through dc_tonemap_global_noalloc, the entry point
+    that allocates nothing (its workspace is the library's fixed per-device
+    scratch array). The caller passes every output (``outs``, optional
+    ``lhats`` and ``stats``); nothing is allocated here either. Returns
+    (outs, lhats, stats)."""
+    xs = list(xs)
+    if outs is None or len(outs) != len(xs):
+        raise ValueError("tonemap_global_noalloc needs one given output per image")
+    if not xs:
+        return [], lhats, stats
+    return _tonemap_global(lib().dc_tonemap_global_noalloc, xs, None, None, beta_r, beta_k, eps,
+                           contrast, sigma_floor, outs, lhats, stats, False, stream, False,
+                           saturation)
+
+
+def _tonemap_global(fn, xs, out_dtype, lhat_dtype, beta_r, beta_k, eps, contrast, sigma_floor,
+                    outs, lhats, stats, want_stats, stream, colour, saturation):
     xs = list(xs)
     if not xs:
         return [], None, None
@@ -463,7 +489,7 @@ def tonemap_global(xs, out_dtype=torch.float32, lhat_dtype=None, beta_r=BETA_R, 
     arr = _image_array(xs, outs, lhats)
     p = _params(beta_r, beta_k)
     tm = DcTmParams(eps, contrast, sigma_floor, saturation, TM_LOCAL_STRENGTH)
-    context(dev).call(lib().dc_tonemap_global, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
+    context(dev).call(fn, arr, len(xs), ctypes.byref(p), ctypes.byref(tm),
                       _stats_ptr(stats, len(xs), dev), _stream_ptr(stream, dev))
     return outs, lhats, stats
 

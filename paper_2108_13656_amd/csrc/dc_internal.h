@@ -121,6 +121,18 @@ struct StatsOut {
     int64_t count;
 };
 
+// The tone map's fixed device scratch (kernels.hip), used by the entry point
+// that allocates nothing: descriptor table, tile and group prefixes, wave and
+// group partials and curves of one call, laid out as a ring slot would hold
+// them. kScratchBytes bounds one call: at most kScratchMaxImages images and
+// about 340 Mpx (24 B of wave partials per 1024 px).
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr int kScratchMaxImages = 1024;
+constexpr int kMaxDevices = 64;
+// Device address of the scratch array on the current device (looked up once
+// per device with hipGetSymbolAddress, then cached).
+hipError_t scratch_address(void **p);
+
 // Kernel launchers (kernels.hip). All return the hipError_t of the launch.
 hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, hipStream_t s);
 // n images sharing the input and geometry of table[0] (ntiles tiles each):

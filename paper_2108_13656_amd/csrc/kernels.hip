@@ -14,6 +14,8 @@
 // instructions, and writes its outputs with 1-16 byte stores.
 #include "dc_internal.h"
 
+#include <mutex>
+
 namespace dc {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -1840,6 +1842,37 @@ __global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict
         else
             ltm_pass2_tile<SRC>(im, tile - im.tile_begin, tm, curves[i], coef, lds);
     });
+}
+
+// ------------------------------------------------------------ scratch
+
+// Workspace of dc_tonemap_global_noalloc: one per device, held until the
+// process ends, shared by every such call on the device (calls that overlap on
+// one device race on it). Host code never passes this name to a kernel: in
+// host code it is a stand-in, not a device address; scratch_address gives the
+// real one.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **p)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[dev] = a;
+    }
+    *p = addr[dev];
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------ launchers

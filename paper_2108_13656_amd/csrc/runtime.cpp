@@ -118,61 +118,74 @@ int validate_tm(const dc_tm_params *tm)
     return DC_OK;
 }
 
-// Checks of the input half of a descriptor; fills its byte extent.
-int check_src(const dc_image &m, const std::string &at, Range &r)
+// Checks of the input half of a descriptor; fills its byte extent. at is the
+// descriptor's label for messages (anything convertible to std::string).
+template <class Label>
+int check_src(const dc_image &m, const Label &at, Range &r)
 {
     if (!m.src)
-        return fail(DC_ERR_INVALID_ARG, "src must not be NULL" + at);
+        return fail(DC_ERR_INVALID_ARG, "src must not be NULL" + std::string(at));
     if (m.width < 1 || m.height < 1)
-        return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + at);
+        return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + std::string(at));
     if (!dtype_ok(m.src_dtype))
-        return fail(DC_ERR_INVALID_ARG, "src_dtype must be DC_U8, DC_F16 or DC_F32" + at);
+        return fail(DC_ERR_INVALID_ARG, "src_dtype must be DC_U8, DC_F16 or DC_F32" + std::string(at));
     const int64_t es = dc::elem_size(m.src_dtype);
     const int64_t row_in = 3 * es * (int64_t)m.width;
     if (m.src_pitch < row_in)
-        return fail(DC_ERR_INVALID_ARG, "src_pitch is smaller than 3 * width * element size" + at);
+        return fail(DC_ERR_INVALID_ARG, "src_pitch is smaller than 3 * width * element size" + std::string(at));
     if ((uintptr_t)m.src % es || m.src_pitch % es)
-        return fail(DC_ERR_INVALID_ARG, "src and src_pitch must be multiples of the element size" + at);
+        return fail(DC_ERR_INVALID_ARG, "src and src_pitch must be multiples of the element size" + std::string(at));
     if (!extent(m.src, m.src_pitch, row_in, m.height, r))
-        return fail(DC_ERR_INVALID_ARG, "src extent overflows" + at);
+        return fail(DC_ERR_INVALID_ARG, "src extent overflows" + std::string(at));
     return DC_OK;
 }
 
 // allowed: the dc_image flags this call accepts (DC_IMG_RGB_OUT for the tone
 // map, DC_IMG_HOST_SRC for server requests); other known flags are
 // DC_ERR_UNSUPPORTED, unknown bits DC_ERR_INVALID_ARG.
-int validate_images(const dc_image *imgs, int32_t n, int32_t allowed)
+// outs_buf and ins_buf, when given, are the work lists (cleared here; with
+// enough capacity reserved the check makes no host allocation on success).
+int validate_images(const dc_image *imgs, int32_t n, int32_t allowed,
+                    std::vector<Range> *outs_buf = nullptr, std::vector<Range> *ins_buf = nullptr)
 {
     if (n < 0)
         return fail(DC_ERR_INVALID_ARG, "n must be >= 0");
     if (n > 0 && !imgs)
         return fail(DC_ERR_INVALID_ARG, "image list is NULL");
-    std::vector<Range> outs, ins;
+    std::vector<Range> outs_own, ins_own;
+    std::vector<Range> &outs = outs_buf ? *outs_buf : outs_own;
+    std::vector<Range> &ins = ins_buf ? *ins_buf : ins_own;
+    outs.clear();
+    ins.clear();
     outs.reserve((size_t)n * 2);
     ins.reserve((size_t)n);
     for (int32_t i = 0; i < n; ++i) {
         const dc_image &m = imgs[i];
-        const std::string at = " (image " + std::to_string(i) + ")";
+        // The image's label, built only for a message.
+        struct At {
+            int32_t i;
+            operator std::string() const { return " (image " + std::to_string(i) + ")"; }
+        } const at{i};
         if (!m.src || !m.dst)
-            return fail(DC_ERR_INVALID_ARG, "src and dst must not be NULL" + at);
+            return fail(DC_ERR_INVALID_ARG, "src and dst must not be NULL" + std::string(at));
         if (m.width < 1 || m.height < 1)
-            return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + at);
+            return fail(DC_ERR_INVALID_ARG, "width and height must be >= 1" + std::string(at));
         if (m.flags & ~(DC_IMG_RGB_OUT | DC_IMG_HOST_SRC))
-            return fail(DC_ERR_INVALID_ARG, "unknown flags" + at);
+            return fail(DC_ERR_INVALID_ARG, "unknown flags" + std::string(at));
         if ((m.flags & DC_IMG_RGB_OUT) && !(allowed & DC_IMG_RGB_OUT))
-            return fail(DC_ERR_UNSUPPORTED, "DC_IMG_RGB_OUT applies to the tone map only" + at);
+            return fail(DC_ERR_UNSUPPORTED, "DC_IMG_RGB_OUT applies to the tone map only" + std::string(at));
         if ((m.flags & DC_IMG_HOST_SRC) && !(allowed & DC_IMG_HOST_SRC))
-            return fail(DC_ERR_UNSUPPORTED, "DC_IMG_HOST_SRC applies to server requests only" + at);
+            return fail(DC_ERR_UNSUPPORTED, "DC_IMG_HOST_SRC applies to server requests only" + std::string(at));
         if (!dtype_ok(m.src_dtype) || !dtype_ok(m.dst_dtype))
-            return fail(DC_ERR_INVALID_ARG, "src_dtype and dst_dtype must be DC_U8, DC_F16 or DC_F32" + at);
+            return fail(DC_ERR_INVALID_ARG, "src_dtype and dst_dtype must be DC_U8, DC_F16 or DC_F32" + std::string(at));
         if (m.dst2_dtype == DC_NONE) {
             if (m.dst2)
-                return fail(DC_ERR_INVALID_ARG, "dst2 must be NULL when dst2_dtype is DC_NONE" + at);
+                return fail(DC_ERR_INVALID_ARG, "dst2 must be NULL when dst2_dtype is DC_NONE" + std::string(at));
         } else {
             if (!dtype_ok(m.dst2_dtype))
-                return fail(DC_ERR_INVALID_ARG, "dst2_dtype must be DC_NONE, DC_U8, DC_F16 or DC_F32" + at);
+                return fail(DC_ERR_INVALID_ARG, "dst2_dtype must be DC_NONE, DC_U8, DC_F16 or DC_F32" + std::string(at));
             if (!m.dst2)
-                return fail(DC_ERR_INVALID_ARG, "dst2 is NULL but dst2_dtype is set" + at);
+                return fail(DC_ERR_INVALID_ARG, "dst2 is NULL but dst2_dtype is set" + std::string(at));
         }
         Range r;
         const int src_rc = check_src(m, at, r);
@@ -192,12 +205,12 @@ int validate_images(const dc_image *imgs, int32_t n, int32_t allowed)
             const int64_t row = ch * eo * (int64_t)m.width;
             if (pitch[o] < row)
                 return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) +
-                                                    "_pitch is smaller than its row bytes" + at);
+                                                    "_pitch is smaller than its row bytes" + std::string(at));
             if ((uintptr_t)op[o] % eo || pitch[o] % eo)
                 return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) +
-                                                    " and its pitch must be multiples of the element size" + at);
+                                                    " and its pitch must be multiples of the element size" + std::string(at));
             if (!extent(op[o], pitch[o], row, m.height, r))
-                return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) + " extent overflows" + at);
+                return fail(DC_ERR_INVALID_ARG, std::string(kind_name(o + 1)) + " extent overflows" + std::string(at));
             r.image = i;
             r.kind = o + 1;
             outs.push_back(r);
@@ -338,6 +351,10 @@ struct Tune {
     int tm_pipeline = 0; // 1 = per-image tone map on two streams
 };
 
+namespace {
+struct NoAlloc;
+}
+
 struct dc_ctx {
     static constexpr int kSlots = 16;
     struct Slot {
@@ -361,6 +378,10 @@ struct dc_ctx {
     bool profiling = false;
     hipEvent_t prof[kMaxEvents] = {};
     int prof_used = 0;
+    // dc_tonemap_global_noalloc: the device address of the fixed scratch array
+    // on this context's device, and the host state set up for it here.
+    void *scratch = nullptr;
+    NoAlloc *na = nullptr;
 };
 
 namespace {
@@ -418,6 +439,17 @@ struct HostTable {
         int img0, img1, src, rgb, staged;
     };
     std::vector<Run> runs;
+    std::vector<int32_t> order; // build_table's sort permutation (kept for its capacity)
+    // Reserves room for n images, so that build_table makes no host
+    // allocation for a call of up to n images.
+    void reserve(size_t n)
+    {
+        d.reserve(n);
+        tile_end.reserve(n);
+        grp_end.reserve(n);
+        runs.reserve(n);
+        order.reserve(n);
+    }
 };
 
 // kind of table: decolorization (tiles of the tuned group count), tone map
@@ -441,19 +473,23 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
     for (int32_t i = 0; i < n; ++i)
         h.mixed |= imgs[i].src_dtype != h.src0;
     h.groups = h.mixed ? tune.mixed_groups : tune.groups[h.src0];
-    std::vector<int32_t> order((size_t)n);
+    std::vector<int32_t> &order = h.order;
+    order.resize((size_t)n);
     for (int32_t i = 0; i < n; ++i)
         order[i] = i;
+    // A stable order by (input type, output kind): the caller's index breaks
+    // ties, so std::sort (which needs no temporary buffer) gives it.
     if (kind != kTabDecolor)
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
             // second key: colour output, then (local tone map) FP32 staging
             auto key = [&](const dc_image &m) {
                 const int rgb = (m.flags & DC_IMG_RGB_OUT) ? 2 : 0;
                 return kind == kTabLocal ? (rgb ? rgb : (m.dst_dtype == DC_F32 ? 1 : 0)) : rgb;
             };
             const int ra = key(imgs[a]), rb = key(imgs[b]);
-            return imgs[a].src_dtype != imgs[b].src_dtype ? imgs[a].src_dtype < imgs[b].src_dtype
-                                                          : ra < rb;
+            if (imgs[a].src_dtype != imgs[b].src_dtype)
+                return imgs[a].src_dtype < imgs[b].src_dtype;
+            return ra != rb ? ra < rb : a < b;
         });
     h.runs.clear();
     int64_t total = 0;
@@ -529,6 +565,29 @@ void write_upload(const HostTable &h, const Layout &l, char *dst)
     std::memcpy(dst + l.table, h.d.data(), sizeof(dc::DevImage) * h.d.size());
     std::memcpy(dst + l.ends, h.tile_end.data(), sizeof(int64_t) * h.tile_end.size());
     std::memcpy(dst + l.gends, h.grp_end.data(), sizeof(int64_t) * h.grp_end.size());
+}
+
+static_assert(DC_NOALLOC_SCRATCH_BYTES == dc::kScratchBytes, "scratch size in the ABI header");
+static_assert(DC_NOALLOC_MAX_IMAGES == dc::kScratchMaxImages, "scratch image limit in the ABI header");
+
+// Host state of dc_tonemap_global_noalloc, set up by dc_create so that the
+// entry point allocates nothing: the argument check's work lists and the table
+// builder's arrays reserved for kScratchMaxImages images, and pinned staging
+// for the descriptor upload with the event of its last copy.
+struct NoAlloc {
+    HostTable h;
+    std::vector<Range> outs, ins;
+    void *host = nullptr;
+    size_t host_cap = 0;
+    hipEvent_t copied = nullptr;
+    bool pending = false;
+};
+
+// Bytes of the largest upload (table, tile ends, group ends) of a call.
+size_t noalloc_upload_cap()
+{
+    const size_t n = dc::kScratchMaxImages;
+    return align_up(sizeof(dc::DevImage) * n, 256) + 2 * align_up(sizeof(int64_t) * n, 256);
 }
 
 struct DevBufs {
@@ -1048,6 +1107,33 @@ int dc_create(dc_ctx **out, int device)
                 return hip_fail(e, "hipEventCreate");
             }
         }
+        // Set-up of dc_tonemap_global_noalloc: the scratch array's address on
+        // this device, reserved host lists, pinned staging and its event.
+        e = dc::scratch_address(&ctx->scratch);
+        if (e != hipSuccess) {
+            dc_destroy(ctx);
+            return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+        }
+        ctx->na = new (std::nothrow) NoAlloc();
+        if (!ctx->na) {
+            dc_destroy(ctx);
+            return fail(DC_ERR_NO_MEMORY, "context allocation failed");
+        }
+        ctx->na->h.reserve(dc::kScratchMaxImages);
+        ctx->na->outs.reserve(2 * (size_t)dc::kScratchMaxImages);
+        ctx->na->ins.reserve(dc::kScratchMaxImages);
+        const size_t cap = noalloc_upload_cap();
+        if (hipHostMalloc(&ctx->na->host, cap, hipHostMallocDefault) != hipSuccess) {
+            ctx->na->host = nullptr;
+            dc_destroy(ctx);
+            return fail(DC_ERR_NO_MEMORY, "pinned staging allocation failed");
+        }
+        ctx->na->host_cap = cap;
+        e = hipEventCreateWithFlags(&ctx->na->copied, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            dc_destroy(ctx);
+            return hip_fail(e, "hipEventCreate");
+        }
         *out = ctx;
         return DC_OK;
     });
@@ -1075,6 +1161,13 @@ int dc_destroy(dc_ctx *ctx)
             (void)hipEventDestroy(e);
         if (ctx->side)
             (void)hipStreamDestroy(ctx->side);
+        if (ctx->na) {
+            if (ctx->na->host)
+                (void)hipHostFree(ctx->na->host);
+            if (ctx->na->copied)
+                (void)hipEventDestroy(ctx->na->copied);
+            delete ctx->na;
+        }
         delete ctx;
         return DC_OK;
     });
@@ -1266,6 +1359,60 @@ int dc_tonemap_global(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_par
         if (rc != DC_OK)
             return rc;
         return hold.finish();
+    });
+}
+
+int dc_tonemap_global_noalloc(dc_ctx *ctx, const dc_image *imgs, int32_t n,
+                              const dc_params *params, const dc_tm_params *tm, dc_stats *stats,
+                              void *stream)
+{
+    return guarded([&]() -> int {
+        TraceRange trace("dc_tonemap_global_noalloc");
+        g_last_error.clear();
+        int rc = check_ctx(ctx);
+        if (rc != DC_OK)
+            return rc;
+        if (n > dc::kScratchMaxImages)
+            return fail(DC_ERR_INVALID_ARG, "dc_tonemap_global_noalloc takes at most " +
+                                                std::to_string(dc::kScratchMaxImages) +
+                                                " images per call");
+        NoAlloc &na = *ctx->na;
+        rc = validate_params(params);
+        if (rc == DC_OK)
+            rc = validate_tm(tm);
+        if (rc == DC_OK)
+            rc = validate_images(imgs, n, DC_IMG_RGB_OUT, &na.outs, &na.ins);
+        if (rc != DC_OK || n == 0)
+            return rc;
+        const hipStream_t st = (hipStream_t)stream;
+        // The per-image pipeline would need a second stream and events made
+        // on first use, so this entry point always takes the batch schedule.
+        Tune tune = ctx->tune;
+        tune.tm_pipeline = 0;
+        build_table(imgs, n, params, kTabTonemap, tune, na.h);
+        const Layout l = layout_of(na.h);
+        if (l.total > dc::kScratchBytes)
+            return fail(DC_ERR_INVALID_ARG,
+                        "the call needs " + std::to_string(l.total) +
+                            " bytes of workspace; dc_tonemap_global_noalloc has a fixed " +
+                            std::to_string(dc::kScratchBytes) +
+                            "-byte scratch (about 340 Mpx per call)");
+        if (na.pending) {
+            // The previous call's upload still reads the staging.
+            if (hipEventSynchronize(na.copied) != hipSuccess)
+                return fail(DC_ERR_HIP, "hipEventSynchronize failed on the scratch upload");
+            na.pending = false;
+        }
+        write_upload(na.h, l, (char *)na.host);
+        hipError_t e = hipMemcpyAsync(ctx->scratch, na.host, l.upload, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "descriptor upload to the scratch");
+        e = hipEventRecord(na.copied, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipEventRecord");
+        na.pending = true;
+        return enqueue_tonemap(ctx, na.h, bufs_of(ctx->scratch, l), tune, tm_of(tm),
+                               (dc::StatsOut *)stats, st, true);
     });
 }
 

@@ -186,6 +186,8 @@ def test_compute_calls_reject_null_context(lib):
         P.DC_ERR_INVALID_ARG
     assert lib.dc_tonemap_local(None, ctypes.byref(d), 1, ctypes.byref(p), None, None, None) == \
         P.DC_ERR_INVALID_ARG
+    assert lib.dc_tonemap_global_noalloc(None, ctypes.byref(d), 1, ctypes.byref(p), None, None,
+                                         None) == P.DC_ERR_INVALID_ARG
 
 
 def test_binding_refuses_cpu_tensors():
