@@ -89,7 +89,7 @@ def parse():
     ap.add_argument("--skip-colour", action="store_true")
     ap.add_argument("--skip-local", action="store_true")
     ap.add_argument("--only", choices=["tonemap", "colour", "local", "video", "uneven", "serve",
-                                       "sweep", "channels"],
+                                       "sweep", "channels", "ceilings"],
                     default=None,
                     help="time one workload only (for profiler runs)")
     ap.add_argument("--tuning", default=None,
@@ -103,6 +103,9 @@ def parse():
 
 
 WORKERS = min(16, os.cpu_count() or 1)
+# Host cores the CPU legs may use: the affinity mask, at most 16 (one GPU's
+# share of a shared host).
+HOST_CORES = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def gen_hdr(n, size):
@@ -189,6 +192,122 @@ def sweep_leg(P, dev, stream, frame, reps, traffic):
     return sweep
 
 
+# Streams whose ceilings are measured: (name, 16-B reads : writes per trip,
+# read bytes, written bytes). Read:write ratios of the passes: statistics pass
+# read-only, curve pass 6:4 (binary16 in, FP32 T out), video 3:5 (8-bit in,
+# 8-bit + FP32 out), a copy 1:1, and a pure write.
+CEILING_STREAMS = [("read", 8, 0, 1610612736, 0),
+                   ("write", 0, 8, 0, 1073741824),
+                   ("read6_write4", 6, 4, 1610612736, 1073741824),
+                   ("read3_write5", 3, 5, 995328000, 1658880000),
+                   ("copy", 4, 4, 1073741824, 1073741824)]
+
+
+def ceilings_leg(dev, reps=7, grids=(0, 4, 8, 16, 32)):
+    """What HBM sustains for plain streams (libdc_ceilings.so: no arithmetic,
+    nontemporal 16-byte loads and stores): per stream, the best grid's median
+    pass time over `reps` passes, as bytes moved / time. Grids are workgroups
+    per CU, 0 = one workgroup per tile."""
+    import ctypes
+    import torch
+    from paper_2108_13656_amd import build as B
+    if not os.path.exists(B.CEIL_LIB):
+        return None
+    L = ctypes.CDLL(B.CEIL_LIB)
+    L.dcx_stream.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                             ctypes.c_void_p]
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    big = max(r for _, _, _, r, _ in CEILING_STREAMS)
+    bigw = max(w for _, _, _, _, w in CEILING_STREAMS)
+    src = torch.ones(big, dtype=torch.uint8, device=dev)
+    dst = torch.empty(bigw, dtype=torch.uint8, device=dev)
+    sink = torch.zeros(4, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for name, vr, vw, rb, wb in CEILING_STREAMS:
+        best = None
+        for gpc in grids:
+            ts = []
+            for _ in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rc = L.dcx_stream(src.data_ptr(), rb, dst.data_ptr(), wb, vr, vw, gpc * ncu,
+                                  sink.data_ptr(), stream.cuda_stream)
+                e1.record(stream)
+                if rc != 0:
+                    raise RuntimeError("dcx_stream failed: %d" % rc)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts[1:]))
+            if best is None or ms < best[0]:
+                best = (ms, gpc)
+        gbs = (rb + wb) / (best[0] * 1e-3) / 1e9
+        out[name] = {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "ms": round(best[0], 4), "grid_per_cu": best[1], "read_bytes": rb,
+                     "write_bytes": wb}
+        log("ceiling %-13s %7.1f GB/s (%.1f %% of peak) at %d workgroups/CU" %
+            (name, gbs, 100 * gbs / HBM_PEAK_GBS, best[1]))
+    del src, dst
+    torch.cuda.empty_cache()
+    # The tone map's two-pass traffic with no arithmetic, 16 x 4096^2 binary16
+    # -> FP32 (24 KiB in / 16 KiB out per 4096-px tile): batch order (read all,
+    # then re-read all and write) and the lagged order (image s read beside
+    # image s - 1's re-read and write, one launch per stage).
+    L.dcx_stage.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    nimg, tpi = 16, 4096
+    inb, outb = nimg * tpi * 24576, nimg * tpi * 16384
+    src = torch.ones(inb, dtype=torch.uint8, device=dev)
+    dst = torch.empty(outb, dtype=torch.uint8, device=dev)
+    px = nimg * tpi * 4096
+
+    def batch(gpc):
+        rc = L.dcx_stream(src.data_ptr(), inb, 0, 0, 8, 0, gpc * ncu, sink.data_ptr(),
+                          stream.cuda_stream)
+        rc = rc or L.dcx_stream(src.data_ptr(), inb, dst.data_ptr(), outb, 6, 4, gpc * ncu,
+                                sink.data_ptr(), stream.cuda_stream)
+        return rc
+
+    def lagged(gpc):
+        rc = 0
+        for s in range(nimg + 1):
+            rc = rc or L.dcx_stage(src.data_ptr(), dst.data_ptr(), s, nimg, tpi, gpc * ncu,
+                                   sink.data_ptr(), stream.cuda_stream)
+        return rc
+
+    for name, fn in (("tonemap_two_pass_batch", batch), ("tonemap_two_pass_lagged", lagged)):
+        best = None
+        for gpc in grids:
+            ts = []
+            for _ in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rc = fn(gpc)
+                e1.record(stream)
+                if rc != 0:
+                    raise RuntimeError("%s failed: %d" % (name, rc))
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts[1:]))
+            if best is None or ms < best[0]:
+                best = (ms, gpc)
+        out[name] = {"ms": round(best[0], 4), "grid_per_cu": best[1],
+                     "gbs_at_16_bytes_per_px": round(px * 16 / (best[0] * 1e-3) / 1e9, 1),
+                     "frac_of_peak_at_10_bytes_per_px":
+                         round(px * 10 / (best[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("%s: %.3f ms (%.1f GB/s of 16 B/px traffic; %.1f %% of peak at 10 B/px)" %
+            (name, best[0], px * 16 / (best[0] * 1e-3) / 1e9,
+             100 * px * 10 / (best[0] * 1e-3) / 1e9 / HBM_PEAK_GBS))
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+POOL_W = 8192          # serving: source pools read as images this many pixels wide
+UNALIGNED_EVERY = 10   # serving: one request in this many starts at any pixel
+
+
 def serve_leg(args, P, dev):
     """Poisson trace through the native continuous-batching server: saturated
     throughput first, then arrivals at 0.7 of it; FIFO one-image-per-launch
@@ -206,14 +325,25 @@ def serve_leg(args, P, dev):
         pool = flat.repeat(reps)
         pools[fmt] = (pool, dt, 3 * pool.element_size(), pool.numel() // 3)
     trace = synth.serving_trace(n_requests=args.requests, rate_per_s=1.0)
-    reqs, px = [], []
+    # Each pool is read as a POOL_W-pixel-wide image (row pitch POOL_W * bpp
+    # bytes) and every request is a crop of it: its rows lie POOL_W pixels
+    # apart, wider than the crop, so the kernels walk pitched rows. Crops start
+    # at a multiple of 16 pixels except one in UNALIGNED_EVERY, which starts
+    # anywhere (a row start that is not 16-byte aligned takes the per-pixel walk).
+    reqs, px, unaligned = [], [], 0
     for r in trace:
         pool, dt, bpp, npx = pools[r["fmt"]]
-        n = r["w"] * r["h"]
-        off = int(rng.integers(0, (npx - n) // 16)) * 16
+        rows = npx // POOL_W
+        y0 = int(rng.integers(0, rows - r["h"] + 1))
+        if r["id"] % UNALIGNED_EVERY == UNALIGNED_EVERY - 1:
+            x0 = int(rng.integers(0, POOL_W - r["w"] + 1))
+        else:
+            x0 = int(rng.integers(0, (POOL_W - r["w"]) // 16 + 1)) * 16
+        unaligned += (x0 * bpp) % 16 != 0
+        off = y0 * POOL_W + x0
         reqs.append(P.make_request(r["id"], pool.data_ptr() + off * bpp, dt, r["w"], r["h"],
-                                   r["w"] * bpp, P.DC_U8 if r["fmt"] == "u8" else P.DC_F32))
-        px.append(n)
+                                   POOL_W * bpp, P.DC_U8 if r["fmt"] == "u8" else P.DC_F32))
+        px.append(r["w"] * r["h"])
     px = np.array(px, np.float64)
     unit_arrivals = np.array([r["arrival"] for r in trace])
     budget = int(args.budget_gib * (1 << 30))
@@ -270,7 +400,7 @@ def serve_leg(args, P, dev):
             pool, dt, bpp, _ = pools[r["fmt"]]
             off = q.img.src - pool.data_ptr()
             reqs.append(P.make_request(r["id"], hpools[r["fmt"]].data_ptr() + off, dt, r["w"],
-                                       r["h"], r["w"] * bpp, q.img.dst_dtype,
+                                       r["h"], POOL_W * bpp, q.img.dst_dtype,
                                        flags=P.DC_IMG_HOST_SRC))
         hsat = run(64, 4, np.zeros(len(reqs)), "host_saturated")
         hrate = 0.7 * hsat["gpx_s"] * 1e9 / px.mean()
@@ -290,6 +420,9 @@ def serve_leg(args, P, dev):
     out = {"workload": "serving_tonemap", "requests": len(reqs),
            "mix": "70% u8 SDR -> u8 T, 30% f16 HDR -> f32 T",
            "sizes": "w log-uniform 256..7680, h log-uniform 256..4320",
+           "sources": "crops of %d-px-wide device pools (row pitch > row bytes); %d of %d "
+                      "start at a row offset that is not 16-byte aligned" %
+                      (POOL_W, unaligned, len(reqs)),
            "mean_mpx": round(px.mean() / 1e6, 3), "budget_gib": args.budget_gib,
            "saturated_gpx_s": sat["gpx_s"], "rate_req_s": round(rate, 1),
            "gpx_s": served["gpx_s"], "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
@@ -329,6 +462,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": n, "copies": 3}), flush=True)
         return
+    ceilings = None
+    if args.only in (None, "ceilings"):
+        ceilings = ceilings_leg(dev)
+        if args.only == "ceilings":
+            print(json.dumps({"ceilings": ceilings, "peak_gbs": HBM_PEAK_GBS}), flush=True)
+            return
     fixed = None
     if args.tuning:
         with open(args.tuning) as f:
@@ -432,16 +571,17 @@ def main():
             # before binary16 rounding (the storage error, bounded in the tests)
             import synth
             exact = synth.hdr_image(0, shape=(size, size), exact=True).astype(np.float32)
-            t_exact, _, _ = oracle.tonemap(exact, nthreads=min(WORKERS, 16))
+            t_exact, _, _ = oracle.tonemap(exact, nthreads=HOST_CORES)
             err_exact = float(np.max(np.abs(outs[0].cpu().numpy() - t_exact)))
             del exact, t_exact
             result["parity_sample"] = {"images": k, "max_abs_err_T": worst,
                                        "max_abs_err_T_vs_unrounded_radiance": err_exact}
             log("cpu baseline %.4f Gpx/s; GPU vs oracle max |dT| %.2e" % (cpu_gpx, worst))
             # Eqs. (1)-(6) alone, as in the paper's run-time table: one thread,
-            # and the oracle's row split over the host cores that go with one
-            # GPU (16).
-            ncores = min(WORKERS, 16)
+            # and the oracle's row split over every host core this process may
+            # use, at most 16: the CPU share that goes with one GPU on a shared
+            # host (nproc and the affinity mask are reported beside it).
+            ncores = HOST_CORES
             t0 = time.time()
             oracle.decolorize(imgs[0], nthreads=1)
             one = size * size / (time.time() - t0) / 1e9
@@ -458,8 +598,11 @@ def main():
                 pass
             result["cpu_baseline"]["decolorize_only"] = {
                 "one_thread_gpx": round(one, 6), "all_cores_gpx": round(allc, 6),
-                "cores": ncores, "cpu_model": model,
-                "sample": "Eqs. (1)-(6) in FP64 on 1 and %d of the images" % k}
+                "cores": ncores, "sample": "Eqs. (1)-(6) in FP64 on 1 and %d of the images" % k}
+            result["cpu_baseline"]["host"] = {"cpu_model": model, "nproc": os.cpu_count(),
+                                              "affinity_cores": len(os.sched_getaffinity(0)),
+                                              "cores_used_all_cores_leg": ncores,
+                                              "cap": "16 threads, one GPU's share of the host"}
             log("cpu oracle, decolorization only: %.4f Gpx/s on 1 thread, %.4f on %d (%s)" %
                 (one, allc, ncores, model))
         plan.close()

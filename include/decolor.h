@@ -301,7 +301,9 @@ typedef struct dc_tuning {
     int32_t mixed_grid_per_cu;    /* batches mixing input types */
     int32_t pass1_grid_per_cu;
     int32_t pass2_grid_per_cu;
-    int32_t tonemap_pipeline; /* 0: each pass over all images; 1: image by image on two streams */
+    int32_t tonemap_pipeline; /* 0: each pass over all images; m >= 1: groups of m images,
+                                 a group's curve pass beside the next group's statistics pass
+                                 on a second stream */
 } dc_tuning;
 
 int dc_get_tuning(dc_ctx *ctx, dc_tuning *out);

@@ -31,10 +31,22 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+# Memory-ceiling kernels of the benchmark (no part of libdecolor.so).
+CEIL_LIB = os.path.join(HERE, "libdc_ceilings.so")
+CEIL_SOURCES = [os.path.join(CSRC, "ceilings.hip")]
+
+
 def build(verbose=False):
-    """Compiles every source into libdecolor.so (always recompiles)."""
-    out_tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-o", out_tmp] + SOURCES + LIBS
+    """Compiles every source into libdecolor.so, and the benchmark's
+    memory-ceiling kernels into libdc_ceilings.so (always recompiles)."""
+    _compile(SOURCES, LIB, LIBS, verbose)
+    _compile(CEIL_SOURCES, CEIL_LIB, [], verbose)
+    return LIB
+
+
+def _compile(sources, lib, libs, verbose):
+    out_tmp = lib + ".tmp"
+    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-o", out_tmp] + sources + libs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -45,8 +57,7 @@ def build(verbose=False):
         raise RuntimeError("hipcc failed:\n" + log)
     if verbose and log.strip():
         print(log)
-    os.replace(out_tmp, LIB)
-    return LIB
+    os.replace(out_tmp, lib)
 
 
 if __name__ == "__main__":

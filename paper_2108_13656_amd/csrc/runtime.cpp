@@ -686,13 +686,15 @@ hipError_t launch_curve(const DevBufs &b, int img0, int nimg, int64_t t0, int64_
                                 colour_mode(a.saturation), a, b.curves, grid, st);
 }
 
-// Kernel sequence of a tone map over a staged table. Mode 0: the statistics
-// pass over every image, the two-level combine, then the curve pass over every
-// image. Mode 1 (t.tm_pipeline): image by image, the statistics pass runs on
-// the caller's stream and the combine and curve pass of that image on a second
-// stream, so the curve pass of image i overlaps the statistics pass of image
-// i + 1 (and re-reads image i while it is still in the last-level cache).
-// Both modes compute the same values: every kernel's per-image work is fixed.
+// Kernel sequence of a tone map over a staged table. t.tm_pipeline = 0: the
+// statistics pass over every image, the two-level combine, then the curve pass
+// over every image. t.tm_pipeline = m >= 1: the images go in groups of m (runs
+// of one input type and output kind split into chunks of m); a group's
+// statistics pass runs on the caller's stream and its combine and curve pass
+// on a second stream, so the curve pass of one group overlaps the statistics
+// pass of the next (the VALU-bound statistics pass beside the memory-bound
+// curve pass). Every schedule computes the same values: each kernel's
+// per-image work is fixed.
 int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tune &t,
                     dc::TmArgs a, dc::StatsOut *stats, hipStream_t st, bool marks)
 {
@@ -724,30 +726,38 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
             return hip_fail(e, "tonemap launch");
         return DC_OK;
     }
-    int rc = ensure_fork(ctx, (size_t)n);
+    const int m = t.tm_pipeline;
+    size_t chunks = 0;
+    for (const auto &r : h.runs)
+        chunks += (size_t)((r.img1 - r.img0 + m - 1) / m);
+    int rc = ensure_fork(ctx, chunks);
     if (rc != DC_OK)
         return rc;
     mark(ctx, marks, 0, st);
-    for (int i = 0; i < n && e == hipSuccess; ++i) {
-        const int64_t t0 = h.d[i].tile_begin, t1 = h.tile_end[i];
-        const int src = h.d[i].src_dtype;
-        e = dc::launch_tm_pass1(b.table, b.tile_end, i, 1, t0, t1, 0, src, a, b.parts, g1, st);
-        if (e == hipSuccess)
-            e = hipEventRecord(ctx->fork[i], st);
-        if (e == hipSuccess)
-            e = hipStreamWaitEvent(ctx->side, ctx->fork[i], 0);
-        if (e == hipSuccess)
-            e = dc::launch_tm_combine(b.table, b.grp_end, i, 1, h.d[i].grp_begin, h.grp_end[i],
-                                      b.parts, b.parts2, ctx->side);
-        if (e == hipSuccess)
-            e = dc::launch_tm_finalize(b.table, i, 1, a, b.parts2, b.curves, stats, ctx->side);
-        if (e == hipSuccess)
-            e = launch_curve(b, i, 1, t0, t1, src, h.d[i].rgb_out, a, g2, ctx->side);
+    size_t c = 0;
+    for (const auto &r : h.runs) {
+        for (int i0 = r.img0; i0 < r.img1 && e == hipSuccess; i0 += m, ++c) {
+            const int k = std::min(m, r.img1 - i0);
+            const int64_t t0 = h.d[i0].tile_begin, t1 = h.tile_end[i0 + k - 1];
+            e = dc::launch_tm_pass1(b.table, b.tile_end, i0, k, t0, t1, 0, r.src, a, b.parts, g1,
+                                    st);
+            if (e == hipSuccess)
+                e = hipEventRecord(ctx->fork[c], st);
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(ctx->side, ctx->fork[c], 0);
+            if (e == hipSuccess)
+                e = dc::launch_tm_combine(b.table, b.grp_end, i0, k, h.d[i0].grp_begin,
+                                          h.grp_end[i0 + k - 1], b.parts, b.parts2, ctx->side);
+            if (e == hipSuccess)
+                e = dc::launch_tm_finalize(b.table, i0, k, a, b.parts2, b.curves, stats, ctx->side);
+            if (e == hipSuccess)
+                e = launch_curve(b, i0, k, t0, t1, r.src, r.rgb, a, g2, ctx->side);
+        }
     }
     if (e == hipSuccess)
-        e = hipEventRecord(ctx->fork[n], ctx->side);
+        e = hipEventRecord(ctx->fork[chunks], ctx->side);
     if (e == hipSuccess)
-        e = hipStreamWaitEvent(st, ctx->fork[n], 0);
+        e = hipStreamWaitEvent(st, ctx->fork[chunks], 0);
     mark(ctx, marks, 1, st);
     if (e != hipSuccess)
         return hip_fail(e, "tonemap pipeline launch");
@@ -893,8 +903,7 @@ bool tune_ok(const dc_tuning &t)
     auto c_ok = [](int c) { return c >= 0 && c <= 64; };
     return g_ok(t.groups[0]) && g_ok(t.groups[1]) && g_ok(t.groups[2]) && g_ok(t.mixed_groups) &&
            c_ok(t.decolor_grid_per_cu) && c_ok(t.mixed_grid_per_cu) && c_ok(t.pass1_grid_per_cu) &&
-           c_ok(t.pass2_grid_per_cu) &&
-           (t.tonemap_pipeline == 0 || t.tonemap_pipeline == 1);
+           c_ok(t.pass2_grid_per_cu) && t.tonemap_pipeline >= 0 && t.tonemap_pipeline <= 1024;
 }
 
 dc_tuning to_public(const Tune &t)

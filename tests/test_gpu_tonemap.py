@@ -161,20 +161,24 @@ def test_autotune_tonemap_keeps_results(dev):
         P.set_tuning(t0)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_two_stream_pipeline_matches_batch_schedule(dev, graph):
-    """The per-image two-stream schedule gives the batch schedule's bits, also
-    when captured into a graph and replayed."""
+@pytest.mark.parametrize("graph,group", [(False, 1), (True, 1), (False, 2), (True, 3),
+                                         (False, 64)])
+def test_two_stream_pipeline_matches_batch_schedule(dev, graph, group):
+    """The two-stream schedule (groups of `group` images; runs of one input
+    type split into chunks) gives the batch schedule's bits, also when captured
+    into a graph and replayed."""
     rng = np.random.default_rng(14)
     imgs = [synth.hdr_pixels(rng, 700, 513), synth.sdr_pixels(rng, 64, 64),
-            synth.hdr_pixels(rng, 1, 4097), synth.sdr_pixels(rng, 333, 1000)]
+            synth.hdr_pixels(rng, 1, 4097), synth.sdr_pixels(rng, 333, 1000),
+            synth.hdr_pixels(rng, 90, 91), synth.sdr_pixels(rng, 5, 3000),
+            synth.hdr_pixels(rng, 256, 256)]
     xs = [to_dev(a, dev) for a in imgs]
     t0 = P.get_tuning()
     try:
         P.set_tuning(dict(t0, tonemap_pipeline=0))
         want, _, want_st = P.tonemap_global(xs, torch.float32, **TM)
         torch.cuda.synchronize()
-        P.set_tuning(dict(t0, tonemap_pipeline=1, pass1_grid_per_cu=2, pass2_grid_per_cu=4))
+        P.set_tuning(dict(t0, tonemap_pipeline=group, pass1_grid_per_cu=2, pass2_grid_per_cu=4))
         got, _, got_st = P.tonemap_global(xs, torch.float32, **TM)
         torch.cuda.synchronize()
         for a, b in zip(got, want):
