@@ -33,10 +33,18 @@ __host__ __device__ constexpr int elem_size(int dtype)
 
 // How an image is walked.
 enum Walk : int32_t {
-    kWalkPacked = 0, // one segment of W*H pixels, vector groups
-    kWalkRows = 1,   // H segments of W pixels (16-B aligned pitches), vector groups
+    kWalkPacked = 0, // one segment of W*H pixels, vector units
+    kWalkRows = 1,   // pitched rows: tiled as one segment of W*H pixels in row-major
+                     // order, vector units placed across the row breaks (magic, gaps)
     kWalkScalar = 2, // H segments of W pixels, one pixel at a time
 };
+
+// The row walk needs q = floor(x / W) = mulhi(x, ceil(2^32 / W)) to be exact
+// for x < W + the largest tile (16384 px), i.e. W (W + 16384) < 2^32, and the
+// rows' padding to fit the 32-bit offsets within a tile; wider images or
+// wider padding take the per-pixel walk.
+constexpr int32_t kRowWalkMaxWidth = 46000;
+constexpr int64_t kRowWalkMaxGap = (int64_t)1 << 18;
 
 // Per-pixel coefficients of Eqs. (3) and (6), in the scaling the input's
 // per-pixel form expects (see lum_code / lum_half / lum_linear).
@@ -75,6 +83,12 @@ struct DevImage {
     int32_t shared_src;     // decolorization: another image of the call reads the same input
     float unit;             // Lhat = L * unit (1/255 for 8-bit input)
     Coef k;                 // per-pixel constants for this image's input type
+    // Row walk: ceil(2^32 / width), and each buffer's row padding in bytes
+    // (pitch minus the row's bytes).
+    uint32_t magic;
+    uint32_t gap_src;
+    uint32_t gap_dst;
+    uint32_t gap_dst2;
 };
 
 // Statistics partial of one chunk, in log2 units: count, mean and sum of
@@ -134,27 +148,29 @@ constexpr int kMaxDevices = 64;
 hipError_t scratch_address(void **p);
 
 // Kernel launchers (kernels.hip). All return the hipError_t of the launch.
+// `rows` = every image of the launch is on the row walk (kWalkRows); a launch
+// never mixes row-walk images with others.
 hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, hipStream_t s);
 // n images sharing the input and geometry of table[0] (ntiles tiles each):
 // each workgroup reads a tile once for up to `per` of the images.
 hipError_t launch_sweep(const DevImage *table, int n, int per, int64_t ntiles, int src_dtype,
-                        int groups, int64_t grid, hipStream_t s);
-hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
-                                int64_t total_tiles, int mixed_src, int src_dtype, int groups,
-                                int64_t grid, hipStream_t s);
+                        int groups, int rows, int64_t grid, hipStream_t s);
+hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int img0,
+                                int nimg, int64_t t0, int64_t t1, int mixed_src, int src_dtype,
+                                int groups, int rows, int64_t grid, hipStream_t s);
 hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                          int64_t t0, int64_t t1, int src_dtype, int channel, int64_t grid,
-                          hipStream_t s);
+                          int64_t t0, int64_t t1, int src_dtype, int channel, int rows,
+                          int64_t grid, hipStream_t s);
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
-                           WavePart *parts, int64_t grid, hipStream_t s);
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, int rows,
+                           TmArgs tm, WavePart *parts, int64_t grid, hipStream_t s);
 hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int img0, int nimg,
                              int64_t g0, int64_t g1, const WavePart *parts, Part *parts2,
                              hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
                               const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s);
 hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                            int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
+                            int64_t t0, int64_t t1, int src_dtype, int mode, int rows, TmArgs tm,
                             const Curve *curves, int64_t grid, hipStream_t s);
 hipError_t launch_ltm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                             int64_t t0, int64_t t1, int src_dtype, TmArgs tm, WavePart *parts,
@@ -170,7 +186,7 @@ hipError_t launch_ltm_colour(const DevImage *table, const int64_t *tile_end, int
                              int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
                              const Curve *curves, const LtmCoef *coef, hipStream_t s);
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
-                           const Curve *curves, int64_t grid, hipStream_t s);
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, int rows,
+                           TmArgs tm, const Curve *curves, int64_t grid, hipStream_t s);
 
 } // namespace dc

@@ -130,16 +130,24 @@ __device__ __forceinline__ float lum(float R, float G, float B, Coef k)
 
 // Image pointers come from descriptors in memory, so the compiler cannot tell
 // they are global; these casts give global_load/global_store instead of flat.
+// The pointee types carry 1-byte alignment: on the row walk a unit's address
+// follows the image's pitch and offset, not the unit's size, and the target's
+// unaligned access mode (which the compiler assumes for gfx950 under ROCm)
+// serves such accesses with the same dwordx3 / dwordx4 instructions.
 #define DC_GLOBAL __attribute__((address_space(1)))
 template <typename T>
-__device__ __forceinline__ const DC_GLOBAL T *gp(const void *p)
+struct Unaligned {
+    typedef T type __attribute__((aligned(1)));
+};
+template <typename T>
+__device__ __forceinline__ const DC_GLOBAL typename Unaligned<T>::type *gp(const void *p)
 {
-    return (const DC_GLOBAL T *)p;
+    return (const DC_GLOBAL typename Unaligned<T>::type *)p;
 }
 template <typename T>
-__device__ __forceinline__ DC_GLOBAL T *gpw(void *p)
+__device__ __forceinline__ DC_GLOBAL typename Unaligned<T>::type *gpw(void *p)
 {
-    return (DC_GLOBAL T *)p;
+    return (DC_GLOBAL typename Unaligned<T>::type *)p;
 }
 
 // Unit stores of the outputs are nontemporal: every output byte is written
@@ -149,7 +157,7 @@ __device__ __forceinline__ DC_GLOBAL T *gpw(void *p)
 // faster per pass on MI355X, measured on the 16 x 4096^2 tone map and the
 // 64-frame video batch).
 template <typename T>
-__device__ __forceinline__ void put(DC_GLOBAL T *p, T v)
+__device__ __forceinline__ void put(DC_GLOBAL typename Unaligned<T>::type *p, T v)
 {
     __builtin_nontemporal_store(v, p);
 }
@@ -206,7 +214,7 @@ __device__ __forceinline__ float chan(const unsigned (&w)[3], int e)
 template <bool NT = true>
 __device__ __forceinline__ void load_unit(const uint8_t *p, unsigned (&w)[3])
 {
-    const DC_GLOBAL unsigned *q = gp<unsigned>(p);
+    const auto *q = gp<unsigned>(p);
     if constexpr (NT) {
         w[0] = __builtin_nontemporal_load(&q[0]);
         w[1] = __builtin_nontemporal_load(&q[1]);
@@ -222,17 +230,17 @@ template <int SRC>
 __device__ __forceinline__ void load_px(const uint8_t *p, float &R, float &G, float &B)
 {
     if constexpr (SRC == 0) {
-        const DC_GLOBAL uint8_t *b = gp<uint8_t>(p);
+        const auto *b = gp<uint8_t>(p);
         R = b[0];
         G = b[1];
         B = b[2];
     } else if constexpr (SRC == 1) {
-        const DC_GLOBAL _Float16 *h = gp<_Float16>(p);
+        const auto *h = gp<_Float16>(p);
         R = (float)h[0];
         G = (float)h[1];
         B = (float)h[2];
     } else {
-        const DC_GLOBAL float *f = gp<float>(p);
+        const auto *f = gp<float>(p);
         R = f[0];
         G = f[1];
         B = f[2];
@@ -330,28 +338,54 @@ struct LumEnc {
 
 // ------------------------------------------------------------ tile walk
 
-// One tile: its segment's base pointers advanced to the tile's first pixel
-// (uniform across the workgroup), and how many of the segment's pixels remain
-// from there. Offsets within a tile fit in 32 bits.
+// One tile: base pointers at the tile's first pixel (uniform across the
+// workgroup) and how many pixels of its segment remain from there. A packed
+// image is one segment of W * H pixels. A pitched image on the row walk is
+// tiled the same way, over its W * H pixels in row-major order: tile-local
+// pixel p lies q(p) rows below the tile's first pixel, at byte offset
+// p * bpp + q(p) * gap from it (gap = pitch - W * bpp, the row's padding),
+// q(p) = floor((col0 + p) / W) = mulhi(col0 + p, magic) with col0 the first
+// pixel's column and magic = ceil(2^32 / W), exact for the widths the runtime
+// gives this walk. Offsets within a tile fit in 32 bits.
 struct TileRef {
     const uint8_t *src;
     uint8_t *dst;
     uint8_t *dst2;
     int64_t rem;
+    uint32_t col0, magic, width, gs, gd, gd2;
 };
 
 // DST_CH = channels per pixel of dst (3 for the re-coloured tone map).
 template <int DST_CH = 1>
 __device__ __forceinline__ TileRef tile_ref(const DevImage &im, int64_t tile, int64_t tile_px)
 {
+    TileRef t;
+    const int64_t es = 3 * elem_size(im.src_dtype), ed = DST_CH * elem_size(im.dst_dtype);
+    const int64_t e2 = im.dst2 ? elem_size(im.dst2_dtype) : 0;
+    t.col0 = 0;
+    t.magic = im.magic;
+    t.width = (uint32_t)im.width;
+    t.gs = im.gap_src;
+    t.gd = im.gap_dst;
+    t.gd2 = im.gap_dst2;
+    if (im.walk == kWalkRows) {
+        const int64_t px0 = tile * tile_px;
+        const int64_t row0 = (int64_t)((uint64_t)px0 / (uint64_t)t.width);
+        const int64_t col0 = px0 - row0 * (int64_t)t.width;
+        t.col0 = (uint32_t)col0;
+        t.src = im.src + row0 * im.src_seg_stride + col0 * es;
+        t.dst = im.dst + row0 * im.dst_seg_stride + col0 * ed;
+        t.dst2 = im.dst2 ? im.dst2 + row0 * im.dst2_seg_stride + col0 * e2 : nullptr;
+        t.rem = im.seg_len - px0;
+        return t;
+    }
     const int64_t seg = tile / im.tiles_per_seg;
     const int64_t ts = tile - seg * im.tiles_per_seg;
     const int64_t px0 = ts * tile_px;
-    TileRef t;
-    t.src = im.src + seg * im.src_seg_stride + px0 * 3 * elem_size(im.src_dtype);
-    t.dst = im.dst + seg * im.dst_seg_stride + px0 * DST_CH * elem_size(im.dst_dtype);
-    t.dst2 = im.dst2 ? im.dst2 + seg * im.dst2_seg_stride + px0 * elem_size(im.dst2_dtype)
-                     : nullptr;
+    const int64_t segs = im.walk == kWalkScalar ? seg : 0; // packed: one segment
+    t.src = im.src + segs * im.src_seg_stride + px0 * es;
+    t.dst = im.dst + segs * im.dst_seg_stride + px0 * ed;
+    t.dst2 = im.dst2 ? im.dst2 + segs * im.dst2_seg_stride + px0 * e2 : nullptr;
     t.rem = im.seg_len - px0;
     return t;
 }
@@ -368,32 +402,145 @@ __device__ __forceinline__ uint32_t slot_lp(bool vec, int u, int j)
     return vec ? (uint32_t)(u * kBlock + tid) * PPU + j : (uint32_t)(u * PPU + j) * kBlock + tid;
 }
 
-// Luminance of all U * PPU pixels a thread owns in a FULL tile on a vector
-// walk (every slot inside the segment): all U loads are issued first. lv holds
-// L in input units.
-template <int SRC, int U>
-__device__ __forceinline__ void tile_lum_full(const TileRef &t, Coef k,
-                                              float (&lv)[U * unit_px(SRC)])
+// Rows below the tile's first pixel of tile-local pixel p (0 off the row walk).
+template <bool ROWS>
+__device__ __forceinline__ uint32_t row_q(const TileRef &t, uint32_t p)
+{
+    if constexpr (ROWS)
+        return __umulhi(t.col0 + p, t.magic);
+    else
+        return 0u;
+}
+
+// Where the unit of PPU pixels from tile-local pixel lp lies: q of its first
+// pixel, and whether a row break falls inside it (its pixels are then not
+// contiguous; only when W is not a multiple of PPU).
+struct UnitPos {
+    uint32_t q;
+    bool split;
+};
+template <int PPU, bool ROWS>
+__device__ __forceinline__ UnitPos unit_pos(const TileRef &t, uint32_t lp)
+{
+    UnitPos u{row_q<ROWS>(t, lp), false};
+    if constexpr (ROWS && PPU > 1)
+        u.split = (t.width & (PPU - 1)) != 0 && row_q<ROWS>(t, lp + PPU - 1) != u.q;
+    return u;
+}
+
+// Element e (channel value number e) of a unit held as 3 dwords, set to the
+// element's bits.
+template <int SRC>
+__device__ __forceinline__ void set_elem(unsigned (&w)[3], int e, unsigned bits)
+{
+    if constexpr (SRC == 0) {
+        const int sh = 8 * (e & 3);
+        w[e >> 2] = (w[e >> 2] & ~(0xffu << sh)) | (bits << sh);
+    } else if constexpr (SRC == 1) {
+        const int sh = 16 * (e & 1);
+        w[e >> 1] = (w[e >> 1] & ~(0xffffu << sh)) | (bits << sh);
+    } else {
+        w[e] = bits;
+    }
+}
+
+// Loads the unit from tile-local pixel lp: one dwordx3 at its first pixel.
+// A unit that a row break splits gets the same load first (its 12 bytes run
+// from that pixel through the row's end and padding into the next row, all
+// inside the image: a next row exists, and the row walk has W >= 4), then
+// patch_unit reads each pixel past the break from the next row.
+template <int SRC, bool ROWS, bool NT = true>
+__device__ __forceinline__ void load_unit_at(const TileRef &t, uint32_t lp, UnitPos up,
+                                             unsigned (&w)[3])
+{
+    load_unit<NT>(t.src + lp * (3 * elem_size(SRC)) + __umul24(up.q, t.gs), w);
+}
+
+template <int SRC, bool ROWS>
+__device__ __forceinline__ void patch_unit(const TileRef &t, uint32_t lp, UnitPos up,
+                                           unsigned (&w)[3])
 {
     constexpr int PPU = unit_px(SRC);
     constexpr int ES = elem_size(SRC);
+    if constexpr (ROWS && PPU > 1) {
+        if (up.split) {
+#pragma unroll
+            for (int j = 1; j < PPU; ++j) {
+                const uint32_t qj = row_q<ROWS>(t, lp + j);
+                if (qj != up.q) {
+                    const uint8_t *p = t.src + (lp + j) * (3 * ES) + __umul24(qj, t.gs);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if constexpr (SRC == 0)
+                            set_elem<SRC>(w, 3 * j + c, gp<uint8_t>(p)[c]);
+                        else
+                            set_elem<SRC>(w, 3 * j + c, gp<unsigned short>(p)[c]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Positions and loads of a thread's U units of a full tile, all issued before
+// any arithmetic; each unit is patched (patch_unit) where it is consumed, so
+// the rare reloads of split units do not hold registers across the others.
+template <int SRC, int U, bool ROWS, bool NT = true>
+__device__ __forceinline__ void load_units(const TileRef &t, unsigned (&w)[U][3],
+                                           UnitPos (&up)[U])
+{
+    constexpr int PPU = unit_px(SRC);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        up[u] = unit_pos<PPU, ROWS>(t, slot_lp<PPU>(true, u, 0));
+        load_unit_at<SRC, ROWS, NT>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
+    }
+}
+
+
+// Luminance of all U * PPU pixels a thread owns in a FULL tile on a vector
+// walk (every slot inside the segment): all U loads are issued first. lv holds
+// L in input units; up the units' positions (for the stores).
+template <int SRC, int U, bool ROWS>
+__device__ __forceinline__ void tile_lum_full(const TileRef &t, Coef k,
+                                              float (&lv)[U * unit_px(SRC)], UnitPos (&up)[U])
+{
+    constexpr int PPU = unit_px(SRC);
     unsigned w[U][3];
+    load_units<SRC, U, ROWS>(t, w, up);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
-#pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
+        patch_unit<SRC, ROWS>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
 #pragma unroll
         for (int j = 0; j < PPU; ++j)
             lv[u * PPU + j] = lum<SRC>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
                                        chan<SRC>(w[u], 3 * j + 2), k);
+    }
+}
+
+// Stores the PPU values of the unit from tile-local pixel lp to an output
+// whose tile base is `out` with row padding `gap`: one store, or pixel by
+// pixel for a unit split by a row break.
+template <int PPU, bool SF, bool SU, bool ROWS>
+__device__ __forceinline__ void store_unit_at(const TileRef &t, uint8_t *out, uint32_t gap,
+                                              int dtype, uint32_t lp, UnitPos up,
+                                              const float (&v)[PPU], Enc e)
+{
+    if (!up.split) {
+        store_unit<PPU, SF, SU>(out + __umul24(up.q, gap), dtype, lp, v, e);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < PPU; ++j)
+        store_px<SF, SU>(out + __umul24(row_q<ROWS>(t, lp + j), gap), dtype, lp + j, v[j], e);
 }
 
 // Writes the per-slot values of a full tile (laid out as tile_lum_full
 // produced them) to one output.
-template <int SRC, int U, bool SF, bool SU>
-__device__ __forceinline__ void tile_store_full(uint8_t *out, int dtype,
-                                                const float (&v)[U * unit_px(SRC)], Enc e)
+template <int SRC, int U, bool SF, bool SU, bool ROWS>
+__device__ __forceinline__ void tile_store_full(const TileRef &t, uint8_t *out, uint32_t gap,
+                                                int dtype, const float (&v)[U * unit_px(SRC)],
+                                                const UnitPos (&up)[U], Enc e)
 {
     constexpr int PPU = unit_px(SRC);
 #pragma unroll
@@ -402,16 +549,17 @@ __device__ __forceinline__ void tile_store_full(uint8_t *out, int dtype,
 #pragma unroll
         for (int j = 0; j < PPU; ++j)
             vv[j] = v[u * PPU + j];
-        store_unit<PPU, SF, SU>(out, dtype, slot_lp<PPU>(true, u, 0), vv, e);
+        store_unit_at<PPU, SF, SU, ROWS>(t, out, gap, dtype, slot_lp<PPU>(true, u, 0), up[u], vv,
+                                         e);
     }
 }
 
 // L (input units) of tile-local pixel p, loaded channel by channel.
-template <int SRC>
+template <int SRC, bool ROWS>
 __device__ __forceinline__ float lum_at(const TileRef &t, uint32_t p, Coef k)
 {
     float R, G_, B;
-    load_px<SRC>(t.src + p * (3 * elem_size(SRC)), R, G_, B);
+    load_px<SRC>(t.src + p * (3 * elem_size(SRC)) + __umul24(row_q<ROWS>(t, p), t.gs), R, G_, B);
     return lum<SRC>(R, G_, B, k);
 }
 
@@ -458,11 +606,10 @@ __device__ __forceinline__ void for_each_tile(const int64_t *__restrict__ tile_e
 // the thread's U units is issued first, then each unit is evaluated and stored
 // while later loads are still in flight; a partial tile (the segment's end) and
 // the per-pixel walk go pixel by pixel with bounds checks.
-template <int SRC, int U>
+template <int SRC, int U, bool ROWS>
 __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile)
 {
     constexpr int PPU = unit_px(SRC);
-    constexpr int ES = elem_size(SRC);
     constexpr int64_t TILE = (int64_t)kBlock * U * PPU;
     constexpr bool SF = LumEnc<SRC>::SF, SU = LumEnc<SRC>::SU;
     const TileRef t = tile_ref(im, tile, TILE);
@@ -471,26 +618,23 @@ __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile)
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= TILE) {
         unsigned w[U][3];
-        if (im.shared_src) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                load_unit<false>(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
-        } else {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
-        }
+        UnitPos up[U];
+        if (im.shared_src)
+            load_units<SRC, U, ROWS, false>(t, w, up);
+        else
+            load_units<SRC, U, ROWS>(t, w, up);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            patch_unit<SRC, ROWS>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
             float v[PPU];
 #pragma unroll
             for (int j = 0; j < PPU; ++j)
                 v[j] = lum<SRC>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
                                 chan<SRC>(w[u], 3 * j + 2), k);
             const uint32_t lp = slot_lp<PPU>(true, u, 0);
-            store_unit<PPU, SF, SU>(t.dst, im.dst_dtype, lp, v, e);
+            store_unit_at<PPU, SF, SU, ROWS>(t, t.dst, t.gd, im.dst_dtype, lp, up[u], v, e);
             if (t.dst2)
-                store_unit<PPU, SF, SU>(t.dst2, im.dst2_dtype, lp, v, e);
+                store_unit_at<PPU, SF, SU, ROWS>(t, t.dst2, t.gd2, im.dst2_dtype, lp, up[u], v, e);
         }
         return;
     }
@@ -499,42 +643,47 @@ __device__ __forceinline__ void decolor_tile(const DevImage &im, int64_t tile)
     for (int s = 0; s < U * PPU; ++s) {
         const uint32_t p = slot_lp<PPU>(vec, s / PPU, s % PPU);
         if (p < rem) {
-            const float v = lum_at<SRC>(t, p, k);
-            store_px<SF, SU>(t.dst, im.dst_dtype, p, v, e);
+            const float v = lum_at<SRC, ROWS>(t, p, k);
+            const uint32_t q = row_q<ROWS>(t, p);
+            store_px<SF, SU>(t.dst + __umul24(q, t.gd), im.dst_dtype, p, v, e);
             if (t.dst2)
-                store_px<SF, SU>(t.dst2, im.dst2_dtype, p, v, e);
+                store_px<SF, SU>(t.dst2 + __umul24(q, t.gd2), im.dst2_dtype, p, v, e);
         }
     }
 }
 
 // Kernel template argument G = 48-byte groups per thread = 4 units.
-template <int SRC, int G>
+// ROWS = the image is on the row walk (a launch covers images of one kind).
+template <int SRC, int G, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_decolor_single(DevImage im, int64_t ntiles)
 {
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        decolor_tile<SRC, 4 * G>(im, tile);
+        decolor_tile<SRC, 4 * G, ROWS>(im, tile);
 }
 
-// One launch over the tiles of many images. MIXED = the input element type
-// varies per image (a uniform branch per tile); otherwise it is SRC.
-template <int SRC, int G, bool MIXED>
+// One launch over the tiles [t0, t1) of images img0 .. img0 + nimg - 1.
+// MIXED = the input element type varies per image (a uniform branch per
+// tile); otherwise it is SRC. ROWS = every image of the range is on the row
+// walk (the runtime sorts a table so that row-walk images form one range).
+template <int SRC, int G, bool MIXED, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__restrict__ table,
                                                           const int64_t *__restrict__ tile_end,
-                                                          int nimg, int64_t total_tiles)
+                                                          int img0, int nimg, int64_t t0,
+                                                          int64_t t1)
 {
-    for_each_tile(tile_end, 0, nimg, 0, total_tiles, [&](int i, int64_t tile) {
+    for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
             // Tile sizes are per image: 4G units of its own unit width.
             if (im.src_dtype == 0)
-                decolor_tile<0, 4 * G>(im, lt);
+                decolor_tile<0, 4 * G, ROWS>(im, lt);
             else if (im.src_dtype == 1)
-                decolor_tile<1, 4 * G>(im, lt);
+                decolor_tile<1, 4 * G, ROWS>(im, lt);
             else
-                decolor_tile<2, 4 * G>(im, lt);
+                decolor_tile<2, 4 * G, ROWS>(im, lt);
         } else {
-            decolor_tile<SRC, 4 * G>(im, lt);
+            decolor_tile<SRC, 4 * G, ROWS>(im, lt);
         }
     });
 }
@@ -549,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_decolor_table(const DevImage *__rest
 // loop and leave it, so each further pair costs only the weight-dependent part.
 // Each output is the same expression of the same inputs as a single call, so
 // the results are bit-identical to dc_decolorize with that pair.
-template <int SRC, int U>
+template <int SRC, int U, bool ROWS>
 __device__ __forceinline__ void sweep_tile(const DevImage *__restrict__ table, int i0, int i1,
                                            int64_t tile)
 {
@@ -564,11 +713,11 @@ __device__ __forceinline__ void sweep_tile(const DevImage *__restrict__ table, i
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= TILE) {
         unsigned w[U][3];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+        UnitPos up[U];
+        load_units<SRC, U, ROWS>(t, w, up);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            patch_unit<SRC, ROWS>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
             float R[PPU], G[PPU], B[PPU];
 #pragma unroll
             for (int j = 0; j < PPU; ++j) {
@@ -584,7 +733,8 @@ __device__ __forceinline__ void sweep_tile(const DevImage *__restrict__ table, i
 #pragma unroll
                 for (int j = 0; j < PPU; ++j)
                     v[j] = lum<SRC>(R[j], G[j], B[j], k);
-                store_unit<PPU, SF, SU>(table[i].dst + dst_off, im.dst_dtype, lp, v, e);
+                store_unit_at<PPU, SF, SU, ROWS>(t, table[i].dst + dst_off, t.gd, im.dst_dtype, lp,
+                                                 up[u], v, e);
             }
         }
         return;
@@ -594,11 +744,12 @@ __device__ __forceinline__ void sweep_tile(const DevImage *__restrict__ table, i
     for (int sl = 0; sl < U * PPU; ++sl) {
         const uint32_t p = slot_lp<PPU>(vec, sl / PPU, sl % PPU);
         if (p < rem) {
+            const uint32_t q = row_q<ROWS>(t, p);
             float R, G, B;
-            load_px<SRC>(t.src + p * (3 * ES), R, G, B);
+            load_px<SRC>(t.src + p * (3 * ES) + __umul24(q, t.gs), R, G, B);
 #pragma unroll 1
             for (int i = i0; i < i1; ++i)
-                store_px<SF, SU>(table[i].dst + dst_off, im.dst_dtype, p,
+                store_px<SF, SU>(table[i].dst + dst_off + __umul24(q, t.gd), im.dst_dtype, p,
                                  lum<SRC>(R, G, B, table[i].k), e);
         }
     }
@@ -607,7 +758,7 @@ __device__ __forceinline__ void sweep_tile(const DevImage *__restrict__ table, i
 // Work item w = (chunk c, tile t) with w = c * ntiles + t: pairs
 // [c * per, min(n, (c + 1) * per)) of tile t. Splitting the pairs into chunks
 // keeps the launch wide on small images; each chunk reads the tile again.
-template <int SRC, int G>
+template <int SRC, int G, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_sweep(const DevImage *__restrict__ table, int n,
                                                   int per, int64_t ntiles, int64_t nwork)
 {
@@ -615,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const DevImage *__restrict__ t
         const int64_t c = w / ntiles;
         const int i0 = (int)c * per;
         const int i1 = n - i0 < per ? n : i0 + per;
-        sweep_tile<SRC, 4 * G>(table, i0, i1, w - c * ntiles);
+        sweep_tile<SRC, 4 * G, ROWS>(table, i0, i1, w - c * ntiles);
     }
 }
 
@@ -654,7 +805,7 @@ __device__ __forceinline__ float comparator_px(float R, float G, float B, float 
 
 // One tile of a comparator channel (4 units per thread), same walks and
 // encodings as the decolorization; values are already normalised.
-template <int SRC, int CH>
+template <int SRC, int CH, bool ROWS>
 __device__ __forceinline__ void channel_tile(const DevImage &im, int64_t tile)
 {
     constexpr int U = 4;
@@ -666,20 +817,21 @@ __device__ __forceinline__ void channel_tile(const DevImage &im, int64_t tile)
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= TILE) {
         unsigned w[U][3];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+        UnitPos up[U];
+        load_units<SRC, U, ROWS>(t, w, up);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            patch_unit<SRC, ROWS>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
             float v[PPU];
 #pragma unroll
             for (int j = 0; j < PPU; ++j)
                 v[j] = comparator_px<SRC, CH>(chan<SRC>(w[u], 3 * j), chan<SRC>(w[u], 3 * j + 1),
                                          chan<SRC>(w[u], 3 * j + 2), im.unit);
             const uint32_t lp = slot_lp<PPU>(true, u, 0);
-            store_unit<PPU, false, true>(t.dst, im.dst_dtype, lp, v, e);
+            store_unit_at<PPU, false, true, ROWS>(t, t.dst, t.gd, im.dst_dtype, lp, up[u], v, e);
             if (t.dst2)
-                store_unit<PPU, false, true>(t.dst2, im.dst2_dtype, lp, v, e);
+                store_unit_at<PPU, false, true, ROWS>(t, t.dst2, t.gd2, im.dst2_dtype, lp, up[u], v,
+                                                      e);
         }
         return;
     }
@@ -688,17 +840,18 @@ __device__ __forceinline__ void channel_tile(const DevImage &im, int64_t tile)
     for (int s = 0; s < U * PPU; ++s) {
         const uint32_t p = slot_lp<PPU>(vec, s / PPU, s % PPU);
         if (p < rem) {
+            const uint32_t q = row_q<ROWS>(t, p);
             float R, G_, B;
-            load_px<SRC>(t.src + p * (3 * ES), R, G_, B);
+            load_px<SRC>(t.src + p * (3 * ES) + __umul24(q, t.gs), R, G_, B);
             const float v = comparator_px<SRC, CH>(R, G_, B, im.unit);
-            store_px<false, true>(t.dst, im.dst_dtype, p, v, e);
+            store_px<false, true>(t.dst + __umul24(q, t.gd), im.dst_dtype, p, v, e);
             if (t.dst2)
-                store_px<false, true>(t.dst2, im.dst2_dtype, p, v, e);
+                store_px<false, true>(t.dst2 + __umul24(q, t.gd2), im.dst2_dtype, p, v, e);
         }
     }
 }
 
-template <int SRC, int CH>
+template <int SRC, int CH, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_channel_table(const DevImage *__restrict__ table,
                                                           const int64_t *__restrict__ tile_end,
                                                           int img0, int nimg, int64_t t0,
@@ -706,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_channel_table(const DevImage *__rest
 {
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
-        channel_tile<SRC, CH>(im, tile - im.tile_begin);
+        channel_tile<SRC, CH, ROWS>(im, tile - im.tile_begin);
     });
 }
 
@@ -772,7 +925,7 @@ __device__ __forceinline__ float wave_max(float v)
 // Chunks are fixed slices of each image, so the partials, and the statistics
 // merged from them in a fixed order, never depend on the other images of the
 // call or on the launch shape.
-template <int SRC>
+template <int SRC, bool ROWS>
 __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                               WavePart *__restrict__ parts)
 {
@@ -787,9 +940,10 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
     const bool full = vec && t.rem >= kStatsChunkPx;
     if (full) {
         float lv[NV];
-        tile_lum_full<SRC, U>(t, im.k, lv);
+        UnitPos up[U];
+        tile_lum_full<SRC, U, ROWS>(t, im.k, lv, up);
         if (t.dst2)
-            tile_store_full<SRC, U, SF, SU>(t.dst2, im.dst2_dtype, lv, e);
+            tile_store_full<SRC, U, SF, SU, ROWS>(t, t.dst2, t.gd2, im.dst2_dtype, lv, up, e);
         float x[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
@@ -809,7 +963,7 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
         // 0 is the wave's first pixel, valid whenever any pixel of the wave is.
         const uint32_t rem = (uint32_t)(t.rem < kStatsChunkPx ? t.rem : kStatsChunkPx);
         const uint32_t p0 = slot_lp<PPU>(vec, 0, 0);
-        const float l0 = p0 < rem ? lum_at<SRC>(t, p0, im.k) : 0.0f;
+        const float l0 = p0 < rem ? lum_at<SRC, ROWS>(t, p0, im.k) : 0.0f;
         K = __builtin_bit_cast(
             float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, xlog2(l0, im.unit, tm.eps))));
         cnt = 0.0f;
@@ -817,9 +971,9 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
         for (int i = 0; i < NV; ++i) {
             const uint32_t p = slot_lp<PPU>(vec, i / PPU, i % PPU);
             if (p < rem) {
-                const float l = lum_at<SRC>(t, p, im.k);
+                const float l = lum_at<SRC, ROWS>(t, p, im.k);
                 if (t.dst2)
-                    store_px<SF, SU>(t.dst2, im.dst2_dtype, p, l, e);
+                    store_px<SF, SU>(t.dst2 + __umul24(row_q<ROWS>(t, p), t.gd2), im.dst2_dtype, p, l, e);
                 const float d = xlog2(l, im.unit, tm.eps) - K;
                 s += d;
                 q = fmaf(d, d, q);
@@ -843,7 +997,7 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
 // one launch can span every image of a call or a single image. MIXED = the
 // input element type varies per image; otherwise it is SRC (one instantiation
 // per type keeps the register count of the uniform case low).
-template <int SRC, bool MIXED>
+template <int SRC, bool MIXED, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
                                                      int img0, int nimg, int64_t t0, int64_t t1,
@@ -854,18 +1008,18 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass1(const DevImage *__restrict_
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
             if (im.src_dtype == 0)
-                tm_pass1_tile<0>(im, lt, tm, parts);
+                tm_pass1_tile<0, ROWS>(im, lt, tm, parts);
             else if (im.src_dtype == 1)
-                tm_pass1_tile<1>(im, lt, tm, parts);
+                tm_pass1_tile<1, ROWS>(im, lt, tm, parts);
             else
-                tm_pass1_tile<2>(im, lt, tm, parts);
+                tm_pass1_tile<2, ROWS>(im, lt, tm, parts);
         } else {
-            tm_pass1_tile<SRC>(im, lt, tm, parts);
+            tm_pass1_tile<SRC, ROWS>(im, lt, tm, parts);
         }
     });
 }
 
-// The binary16 statistics pass of uniform batches, held to 80 VGPRs: its body
+// The binary16 statistics pass of uniform batches off the row walk, held to 80 VGPRs: its body
 // fits them without spilling, and the sixth wave per SIMD that this allows
 // hides more of the load latency (about 3 % faster on MI355X; the other
 // instantiations would spill under the same limit).
@@ -875,7 +1029,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 {
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
-        tm_pass1_tile<1>(im, tile - im.tile_begin, tm, parts);
+        tm_pass1_tile<1, false>(im, tile - im.tile_begin, tm, parts);
     });
 }
 
@@ -994,7 +1148,7 @@ __device__ __forceinline__ float curve(float l, float unit, TmArgs tm, Curve cv)
     return hw_rcp(1.0f + hw_exp2(cv.a * (xlog2(l, unit, tm.eps) - cv.mu2)));
 }
 
-template <int SRC>
+template <int SRC, bool ROWS>
 __device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, TmArgs tm, Curve cv)
 {
     constexpr int PPU = unit_px(SRC);
@@ -1005,11 +1159,12 @@ __device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, 
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= kStatsChunkPx) {
         float lv[NV];
-        tile_lum_full<SRC, U>(t, im.k, lv);
+        UnitPos up[U];
+        tile_lum_full<SRC, U, ROWS>(t, im.k, lv, up);
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             lv[i] = curve(lv[i], im.unit, tm, cv);
-        tile_store_full<SRC, U, false, true>(t.dst, im.dst_dtype, lv, e);
+        tile_store_full<SRC, U, false, true, ROWS>(t, t.dst, t.gd, im.dst_dtype, lv, up, e);
         return;
     }
     const uint32_t rem = (uint32_t)(t.rem < kStatsChunkPx ? t.rem : kStatsChunkPx);
@@ -1017,12 +1172,12 @@ __device__ __forceinline__ void tm_pass2_tile(const DevImage &im, int64_t tile, 
     for (int i = 0; i < NV; ++i) {
         const uint32_t p = slot_lp<PPU>(vec, i / PPU, i % PPU);
         if (p < rem)
-            store_px<false, true>(t.dst, im.dst_dtype, p,
-                                  curve(lum_at<SRC>(t, p, im.k), im.unit, tm, cv), e);
+            store_px<false, true>(t.dst + __umul24(row_q<ROWS>(t, p), t.gd), im.dst_dtype, p,
+                                  curve(lum_at<SRC, ROWS>(t, p, im.k), im.unit, tm, cv), e);
     }
 }
 
-template <int SRC, bool MIXED>
+template <int SRC, bool MIXED, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict__ table,
                                                      const int64_t *__restrict__ tile_end,
                                                      int img0, int nimg, int64_t t0, int64_t t1,
@@ -1034,13 +1189,13 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
         const int64_t lt = tile - im.tile_begin;
         if constexpr (MIXED) {
             if (im.src_dtype == 0)
-                tm_pass2_tile<0>(im, lt, tm, cv);
+                tm_pass2_tile<0, ROWS>(im, lt, tm, cv);
             else if (im.src_dtype == 1)
-                tm_pass2_tile<1>(im, lt, tm, cv);
+                tm_pass2_tile<1, ROWS>(im, lt, tm, cv);
             else
-                tm_pass2_tile<2>(im, lt, tm, cv);
+                tm_pass2_tile<2, ROWS>(im, lt, tm, cv);
         } else {
-            tm_pass2_tile<SRC>(im, lt, tm, cv);
+            tm_pass2_tile<SRC, ROWS>(im, lt, tm, cv);
         }
     });
 }
@@ -1116,18 +1271,18 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
                 for (int i = 0; i < 4; ++i)
                     w[j] = u8_of<false>(o[4 * j + i], 1.0f, i, w[j]);
             }
-            DC_GLOBAL unsigned *q = gpw<unsigned>(p);
+            auto *q = gpw<unsigned>(p);
             put(&q[0], w[0]);
             put(&q[1], w[1]);
             put(&q[2], w[2]);
         } else if constexpr (PPU == 2) {
-            DC_GLOBAL unsigned short *q = gpw<unsigned short>(p);
+            auto *q = gpw<unsigned short>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], (unsigned short)u8_of<false>(o[2 * j + 1], 1.0f, 1,
                                                         u8_of<false>(o[2 * j], 1.0f, 0, 0u)));
         } else {
-            DC_GLOBAL uint8_t *q = gpw<uint8_t>(p);
+            auto *q = gpw<uint8_t>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], (uint8_t)u8_of<false>(o[j], 1.0f, 0, 0u));
@@ -1135,18 +1290,18 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
     } else if (dtype == 1) {
         uint8_t *p = base + 6 * lp;
         if constexpr (PPU == 4) {
-            DC_GLOBAL u32x2 *q = gpw<u32x2>(p);
+            auto *q = gpw<u32x2>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], u32x2{pack_f16x2(o[4 * j], o[4 * j + 1]),
                                  pack_f16x2(o[4 * j + 2], o[4 * j + 3])});
         } else if constexpr (PPU == 2) {
-            DC_GLOBAL unsigned *q = gpw<unsigned>(p);
+            auto *q = gpw<unsigned>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], pack_f16x2(o[2 * j], o[2 * j + 1]));
         } else {
-            DC_GLOBAL _Float16 *q = gpw<_Float16>(p);
+            auto *q = gpw<_Float16>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], (_Float16)o[j]);
@@ -1158,17 +1313,17 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
         for (int i = 0; i < 3 * PPU; ++i)
             b[i] = __builtin_bit_cast(unsigned, o[i]);
         if constexpr (PPU == 4) {
-            DC_GLOBAL u32x4 *q = gpw<u32x4>(p);
+            auto *q = gpw<u32x4>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], u32x4{b[4 * j], b[4 * j + 1], b[4 * j + 2], b[4 * j + 3]});
         } else if constexpr (PPU == 2) {
-            DC_GLOBAL u32x2 *q = gpw<u32x2>(p);
+            auto *q = gpw<u32x2>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], u32x2{b[2 * j], b[2 * j + 1]});
         } else {
-            DC_GLOBAL unsigned *q = gpw<unsigned>(p);
+            auto *q = gpw<unsigned>(p);
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 put(&q[j], b[j]);
@@ -1179,7 +1334,7 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
 // Curve pass with colour output over one statistics tile: the same units,
 // tiles and curve as tm_pass2_tile, and 3 output channels per pixel. U8 =
 // the image's dst is 8-bit (a uniform choice per image).
-template <int SRC, int MODE, bool U8>
+template <int SRC, int MODE, bool U8, bool ROWS>
 __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile, TmArgs tm,
                                                Curve cv)
 {
@@ -1188,14 +1343,15 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
     constexpr int ES = elem_size(SRC);
     const TileRef t = tile_ref<3>(im, tile, kStatsChunkPx);
     const Enc e{1.0f, 1.0f};
+    const int dt = U8 ? 0 : im.dst_dtype;
     const bool vec = im.walk != kWalkScalar;
     if (vec && t.rem >= kStatsChunkPx) {
         unsigned w[U][3];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            load_unit(t.src + slot_lp<PPU>(true, u, 0) * (3 * ES), w[u]);
+        UnitPos up[U];
+        load_units<SRC, U, ROWS>(t, w, up);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            patch_unit<SRC, ROWS>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
             float o[3 * PPU];
 #pragma unroll
             for (int j = 0; j < PPU; ++j) {
@@ -1205,7 +1361,18 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
                 const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
                 colour_px<SRC, MODE, U8>(R, G, B, l, E, tm.saturation, &o[3 * j]);
             }
-            store_rgb_unit<PPU>(t.dst, U8 ? 0 : im.dst_dtype, slot_lp<PPU>(true, u, 0), o);
+            const uint32_t lp = slot_lp<PPU>(true, u, 0);
+            if (!up[u].split) {
+                store_rgb_unit<PPU>(t.dst + __umul24(up[u].q, t.gd), dt, lp, o);
+            } else {
+                // a unit split by a row break: each pixel into its own row
+#pragma unroll
+                for (int j = 0; j < PPU; ++j)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        store_px<false, false>(t.dst + __umul24(row_q<ROWS>(t, lp + j), t.gd), dt,
+                                               3 * (lp + j) + c, o[3 * j + c], e);
+            }
         }
         return;
     }
@@ -1214,20 +1381,21 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
     for (int i = 0; i < kStatsPxPerThread; ++i) {
         const uint32_t p = slot_lp<PPU>(vec, i / PPU, i % PPU);
         if (p < rem) {
+            const uint32_t q = row_q<ROWS>(t, p);
             float R, G, B;
-            load_px<SRC>(t.src + p * (3 * ES), R, G, B);
+            load_px<SRC>(t.src + p * (3 * ES) + __umul24(q, t.gs), R, G, B);
             const float l = lum<SRC>(R, G, B, im.k);
             const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
             float o[3];
             colour_px<SRC, MODE, U8>(R, G, B, l, E, tm.saturation, o);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                store_px<false, false>(t.dst, U8 ? 0 : im.dst_dtype, 3 * p + c, o[c], e);
+                store_px<false, false>(t.dst + __umul24(q, t.gd), dt, 3 * p + c, o[c], e);
         }
     }
 }
 
-template <int SRC, int MODE>
+template <int SRC, int MODE, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_tm_colour(const DevImage *__restrict__ table,
                                                       const int64_t *__restrict__ tile_end,
                                                       int img0, int nimg, int64_t t0, int64_t t1,
@@ -1236,9 +1404,9 @@ __global__ __launch_bounds__(kBlock) void k_tm_colour(const DevImage *__restrict
     for_each_tile(tile_end, img0, nimg, t0, t1, [&](int i, int64_t tile) {
         const DevImage im = table[i];
         if (im.dst_dtype == 0)
-            tm_colour_tile<SRC, MODE, true>(im, tile - im.tile_begin, tm, curves[i]);
+            tm_colour_tile<SRC, MODE, true, ROWS>(im, tile - im.tile_begin, tm, curves[i]);
         else
-            tm_colour_tile<SRC, MODE, false>(im, tile - im.tile_begin, tm, curves[i]);
+            tm_colour_tile<SRC, MODE, false, ROWS>(im, tile - im.tile_begin, tm, curves[i]);
     });
 }
 
@@ -1682,7 +1850,7 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
             int row, col;
             ltm_slot<PPU>(sl / PPU, sl % PPU, row, col);
             if (row < r.bh && col < r.bw) {
-                DC_GLOBAL float *p = gpw<float>(r.dst + row * r.dp) + col;
+                auto *p = gpw<float>(r.dst + row * r.dp) + col;
                 int cx0, cy0;
                 float wx, wy;
                 ltm_axis(col, r.tx, r.nx, cx0, wx);
@@ -1885,54 +2053,66 @@ static unsigned grid_of(int64_t ntiles, int64_t grid)
     return (unsigned)(g > 0 ? g : 1);
 }
 
+// Launches the row-walk or the other instantiation of a kernel template:
+// DC_BY_ROWS(M, args) expands M(args, true) or M(args, false) by the runtime
+// flag `rows`.
+#define DC_BY_ROWS(M, ...)                                                                        \
+    do {                                                                                          \
+        if (rows)                                                                                 \
+            M(__VA_ARGS__, true);                                                                 \
+        else                                                                                      \
+            M(__VA_ARGS__, false);                                                                \
+    } while (0)
+
 hipError_t launch_decolor_single(const DevImage &im, int groups, int64_t grid, hipStream_t s)
 {
     const int64_t ntiles = im.ntiles;
     const unsigned g = grid_of(ntiles, grid);
-#define DC_LAUNCH_SINGLE(S, GG)                                                                   \
-    hipLaunchKernelGGL((k_decolor_single<S, GG>), dim3(g), dim3(kBlock), 0, s, im, ntiles)
+    const bool rows = im.walk == kWalkRows;
+#define DC_LAUNCH_SINGLE(S, GG, R)                                                                \
+    hipLaunchKernelGGL((k_decolor_single<S, GG, R>), dim3(g), dim3(kBlock), 0, s, im, ntiles)
     switch (im.src_dtype * 8 + groups) {
-    case 0 * 8 + 1: DC_LAUNCH_SINGLE(0, 1); break;
-    case 0 * 8 + 2: DC_LAUNCH_SINGLE(0, 2); break;
-    case 0 * 8 + 4: DC_LAUNCH_SINGLE(0, 4); break;
-    case 1 * 8 + 1: DC_LAUNCH_SINGLE(1, 1); break;
-    case 1 * 8 + 2: DC_LAUNCH_SINGLE(1, 2); break;
-    case 1 * 8 + 4: DC_LAUNCH_SINGLE(1, 4); break;
-    case 2 * 8 + 1: DC_LAUNCH_SINGLE(2, 1); break;
-    case 2 * 8 + 2: DC_LAUNCH_SINGLE(2, 2); break;
-    case 2 * 8 + 4: DC_LAUNCH_SINGLE(2, 4); break;
+    case 0 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_SINGLE, 0, 1); break;
+    case 0 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_SINGLE, 0, 2); break;
+    case 0 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_SINGLE, 0, 4); break;
+    case 1 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_SINGLE, 1, 1); break;
+    case 1 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_SINGLE, 1, 2); break;
+    case 1 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_SINGLE, 1, 4); break;
+    case 2 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_SINGLE, 2, 1); break;
+    case 2 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_SINGLE, 2, 2); break;
+    case 2 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_SINGLE, 2, 4); break;
     default: return hipErrorInvalidValue;
     }
 #undef DC_LAUNCH_SINGLE
     return hipGetLastError();
 }
 
-hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int nimg,
-                                int64_t total_tiles, int mixed_src, int src_dtype, int groups,
-                                int64_t grid, hipStream_t s)
+hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, int img0,
+                                int nimg, int64_t t0, int64_t t1, int mixed_src, int src_dtype,
+                                int groups, int rows, int64_t grid, hipStream_t s)
 {
-    const unsigned g = grid_of(total_tiles, grid);
-#define DC_LAUNCH_TABLE(S, GG, M)                                                                 \
-    hipLaunchKernelGGL((k_decolor_table<S, GG, M>), dim3(g), dim3(kBlock), 0, s, table, tile_end,  \
-                       nimg, total_tiles)
+    const unsigned g = grid_of(t1 - t0, grid);
+#define DC_LAUNCH_TABLE(S, GG, M, R)                                                              \
+    hipLaunchKernelGGL((k_decolor_table<S, GG, M, R>), dim3(g), dim3(kBlock), 0, s, table,         \
+                       tile_end, img0, nimg, t0, t1)
     if (mixed_src) {
         switch (groups) {
-        case 1: DC_LAUNCH_TABLE(0, 1, true); break;
-        case 2: DC_LAUNCH_TABLE(0, 2, true); break;
-        case 4: DC_LAUNCH_TABLE(0, 4, true); break;
+        case 1: DC_BY_ROWS(DC_LAUNCH_TABLE, 0, 1, true); break;
+        case 2: DC_BY_ROWS(DC_LAUNCH_TABLE, 0, 2, true); break;
+        case 4: DC_BY_ROWS(DC_LAUNCH_TABLE, 0, 4, true); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (src_dtype * 8 + groups) {
-        case 0 * 8 + 1: DC_LAUNCH_TABLE(0, 1, false); break;
-        case 0 * 8 + 2: DC_LAUNCH_TABLE(0, 2, false); break;
-        case 0 * 8 + 4: DC_LAUNCH_TABLE(0, 4, false); break;
-        case 1 * 8 + 1: DC_LAUNCH_TABLE(1, 1, false); break;
-        case 1 * 8 + 2: DC_LAUNCH_TABLE(1, 2, false); break;
-        case 1 * 8 + 4: DC_LAUNCH_TABLE(1, 4, false); break;
-        case 2 * 8 + 1: DC_LAUNCH_TABLE(2, 1, false); break;
-        case 2 * 8 + 2: DC_LAUNCH_TABLE(2, 2, false); break;
-        case 2 * 8 + 4: DC_LAUNCH_TABLE(2, 4, false); break;
+        case 0 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_TABLE, 0, 1, false); break;
+        case 0 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_TABLE, 0, 2, false); break;
+        case 0 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_TABLE, 0, 4, false); break;
+        case 1 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_TABLE, 1, 1, false); break;
+        case 1 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_TABLE, 1, 2, false); break;
+        case 1 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_TABLE, 1, 4, false); break;
+        case 2 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_TABLE, 2, 1, false); break;
+        case 2 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_TABLE, 2, 2, false); break;
+        case 2 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_TABLE, 2, 4, false); break;
         default: return hipErrorInvalidValue;
         }
     }
@@ -1941,25 +2121,25 @@ hipError_t launch_decolor_table(const DevImage *table, const int64_t *tile_end, 
 }
 
 hipError_t launch_sweep(const DevImage *table, int n, int per, int64_t ntiles, int src_dtype,
-                        int groups, int64_t grid, hipStream_t s)
+                        int groups, int rows, int64_t grid, hipStream_t s)
 {
     if (n < 1 || per < 1 || ntiles < 1)
         return hipErrorInvalidValue;
     const int64_t nwork = ntiles * ((n + per - 1) / per);
     const unsigned g = grid_of(nwork, grid);
-#define DC_LAUNCH_SWEEP(S, GG)                                                                    \
-    hipLaunchKernelGGL((k_sweep<S, GG>), dim3(g), dim3(kBlock), 0, s, table, n, per, ntiles,     \
+#define DC_LAUNCH_SWEEP(S, GG, R)                                                                 \
+    hipLaunchKernelGGL((k_sweep<S, GG, R>), dim3(g), dim3(kBlock), 0, s, table, n, per, ntiles,  \
                        nwork)
     switch (src_dtype * 8 + groups) {
-    case 0 * 8 + 1: DC_LAUNCH_SWEEP(0, 1); break;
-    case 0 * 8 + 2: DC_LAUNCH_SWEEP(0, 2); break;
-    case 0 * 8 + 4: DC_LAUNCH_SWEEP(0, 4); break;
-    case 1 * 8 + 1: DC_LAUNCH_SWEEP(1, 1); break;
-    case 1 * 8 + 2: DC_LAUNCH_SWEEP(1, 2); break;
-    case 1 * 8 + 4: DC_LAUNCH_SWEEP(1, 4); break;
-    case 2 * 8 + 1: DC_LAUNCH_SWEEP(2, 1); break;
-    case 2 * 8 + 2: DC_LAUNCH_SWEEP(2, 2); break;
-    case 2 * 8 + 4: DC_LAUNCH_SWEEP(2, 4); break;
+    case 0 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_SWEEP, 0, 1); break;
+    case 0 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_SWEEP, 0, 2); break;
+    case 0 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_SWEEP, 0, 4); break;
+    case 1 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_SWEEP, 1, 1); break;
+    case 1 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_SWEEP, 1, 2); break;
+    case 1 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_SWEEP, 1, 4); break;
+    case 2 * 8 + 1: DC_BY_ROWS(DC_LAUNCH_SWEEP, 2, 1); break;
+    case 2 * 8 + 2: DC_BY_ROWS(DC_LAUNCH_SWEEP, 2, 2); break;
+    case 2 * 8 + 4: DC_BY_ROWS(DC_LAUNCH_SWEEP, 2, 4); break;
     default: return hipErrorInvalidValue;
     }
 #undef DC_LAUNCH_SWEEP
@@ -1967,23 +2147,23 @@ hipError_t launch_sweep(const DevImage *table, int n, int per, int64_t ntiles, i
 }
 
 hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                          int64_t t0, int64_t t1, int src_dtype, int channel, int64_t grid,
-                          hipStream_t s)
+                          int64_t t0, int64_t t1, int src_dtype, int channel, int rows,
+                          int64_t grid, hipStream_t s)
 {
     const dim3 g(grid_of(t1 - t0, grid));
-#define DC_LAUNCH_CH(S, C)                                                                        \
-    hipLaunchKernelGGL((k_channel_table<S, C>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg, \
-                       t0, t1)
+#define DC_LAUNCH_CH(S, C, R)                                                                     \
+    hipLaunchKernelGGL((k_channel_table<S, C, R>), g, dim3(kBlock), 0, s, table, tile_end, img0,   \
+                       nimg, t0, t1)
     switch (src_dtype * 4 + channel) {
-    case 0 * 4 + 1: DC_LAUNCH_CH(0, 1); break;
-    case 0 * 4 + 2: DC_LAUNCH_CH(0, 2); break;
-    case 0 * 4 + 3: DC_LAUNCH_CH(0, 3); break;
-    case 1 * 4 + 1: DC_LAUNCH_CH(1, 1); break;
-    case 1 * 4 + 2: DC_LAUNCH_CH(1, 2); break;
-    case 1 * 4 + 3: DC_LAUNCH_CH(1, 3); break;
-    case 2 * 4 + 1: DC_LAUNCH_CH(2, 1); break;
-    case 2 * 4 + 2: DC_LAUNCH_CH(2, 2); break;
-    case 2 * 4 + 3: DC_LAUNCH_CH(2, 3); break;
+    case 0 * 4 + 1: DC_BY_ROWS(DC_LAUNCH_CH, 0, 1); break;
+    case 0 * 4 + 2: DC_BY_ROWS(DC_LAUNCH_CH, 0, 2); break;
+    case 0 * 4 + 3: DC_BY_ROWS(DC_LAUNCH_CH, 0, 3); break;
+    case 1 * 4 + 1: DC_BY_ROWS(DC_LAUNCH_CH, 1, 1); break;
+    case 1 * 4 + 2: DC_BY_ROWS(DC_LAUNCH_CH, 1, 2); break;
+    case 1 * 4 + 3: DC_BY_ROWS(DC_LAUNCH_CH, 1, 3); break;
+    case 2 * 4 + 1: DC_BY_ROWS(DC_LAUNCH_CH, 2, 1); break;
+    case 2 * 4 + 2: DC_BY_ROWS(DC_LAUNCH_CH, 2, 2); break;
+    case 2 * 4 + 3: DC_BY_ROWS(DC_LAUNCH_CH, 2, 3); break;
     default: return hipErrorInvalidValue;
     }
 #undef DC_LAUNCH_CH
@@ -1991,22 +2171,24 @@ hipError_t launch_channel(const DevImage *table, const int64_t *tile_end, int im
 }
 
 hipError_t launch_tm_pass1(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
-                           WavePart *parts, int64_t grid, hipStream_t s)
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, int rows,
+                           TmArgs tm, WavePart *parts, int64_t grid, hipStream_t s)
 {
     const dim3 g(grid_of(t1 - t0, grid));
-#define DC_LAUNCH_P1(S, M)                                                                        \
-    hipLaunchKernelGGL((k_tm_pass1<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,     \
+#define DC_LAUNCH_P1(S, M, R)                                                                     \
+    hipLaunchKernelGGL((k_tm_pass1<S, M, R>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,  \
                        t0, t1, tm, parts)
     if (mixed_src)
-        DC_LAUNCH_P1(0, true);
+        DC_BY_ROWS(DC_LAUNCH_P1, 0, true);
     else if (src_dtype == 0)
-        DC_LAUNCH_P1(0, false);
-    else if (src_dtype == 1)
+        DC_BY_ROWS(DC_LAUNCH_P1, 0, false);
+    else if (src_dtype == 1 && !rows)
         hipLaunchKernelGGL(k_tm_pass1_f16, g, dim3(kBlock), 0, s, table, tile_end, img0, nimg, t0,
                            t1, tm, parts);
+    else if (src_dtype == 1)
+        DC_LAUNCH_P1(1, false, true);
     else
-        DC_LAUNCH_P1(2, false);
+        DC_BY_ROWS(DC_LAUNCH_P1, 2, false);
 #undef DC_LAUNCH_P1
     return hipGetLastError();
 }
@@ -2029,23 +2211,23 @@ hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs 
 }
 
 hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                            int64_t t0, int64_t t1, int src_dtype, int mode, TmArgs tm,
+                            int64_t t0, int64_t t1, int src_dtype, int mode, int rows, TmArgs tm,
                             const Curve *curves, int64_t grid, hipStream_t s)
 {
     const dim3 g(grid_of(t1 - t0, grid));
-#define DC_LAUNCH_COL(S, M)                                                                       \
-    hipLaunchKernelGGL((k_tm_colour<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,    \
-                       t0, t1, tm, curves)
+#define DC_LAUNCH_COL(S, M, R)                                                                    \
+    hipLaunchKernelGGL((k_tm_colour<S, M, R>), g, dim3(kBlock), 0, s, table, tile_end, img0,       \
+                       nimg, t0, t1, tm, curves)
     switch (src_dtype * 4 + mode) {
-    case 0 * 4 + kColourGrey: DC_LAUNCH_COL(0, kColourGrey); break;
-    case 0 * 4 + kColourRatio: DC_LAUNCH_COL(0, kColourRatio); break;
-    case 0 * 4 + kColourPow: DC_LAUNCH_COL(0, kColourPow); break;
-    case 1 * 4 + kColourGrey: DC_LAUNCH_COL(1, kColourGrey); break;
-    case 1 * 4 + kColourRatio: DC_LAUNCH_COL(1, kColourRatio); break;
-    case 1 * 4 + kColourPow: DC_LAUNCH_COL(1, kColourPow); break;
-    case 2 * 4 + kColourGrey: DC_LAUNCH_COL(2, kColourGrey); break;
-    case 2 * 4 + kColourRatio: DC_LAUNCH_COL(2, kColourRatio); break;
-    case 2 * 4 + kColourPow: DC_LAUNCH_COL(2, kColourPow); break;
+    case 0 * 4 + kColourGrey: DC_BY_ROWS(DC_LAUNCH_COL, 0, kColourGrey); break;
+    case 0 * 4 + kColourRatio: DC_BY_ROWS(DC_LAUNCH_COL, 0, kColourRatio); break;
+    case 0 * 4 + kColourPow: DC_BY_ROWS(DC_LAUNCH_COL, 0, kColourPow); break;
+    case 1 * 4 + kColourGrey: DC_BY_ROWS(DC_LAUNCH_COL, 1, kColourGrey); break;
+    case 1 * 4 + kColourRatio: DC_BY_ROWS(DC_LAUNCH_COL, 1, kColourRatio); break;
+    case 1 * 4 + kColourPow: DC_BY_ROWS(DC_LAUNCH_COL, 1, kColourPow); break;
+    case 2 * 4 + kColourGrey: DC_BY_ROWS(DC_LAUNCH_COL, 2, kColourGrey); break;
+    case 2 * 4 + kColourRatio: DC_BY_ROWS(DC_LAUNCH_COL, 2, kColourRatio); break;
+    case 2 * 4 + kColourPow: DC_BY_ROWS(DC_LAUNCH_COL, 2, kColourPow); break;
     default: return hipErrorInvalidValue;
     }
 #undef DC_LAUNCH_COL
@@ -2126,21 +2308,21 @@ hipError_t launch_ltm_colour(const DevImage *table, const int64_t *tile_end, int
 }
 
 hipError_t launch_tm_pass2(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
-                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, TmArgs tm,
-                           const Curve *curves, int64_t grid, hipStream_t s)
+                           int64_t t0, int64_t t1, int mixed_src, int src_dtype, int rows,
+                           TmArgs tm, const Curve *curves, int64_t grid, hipStream_t s)
 {
     const dim3 g(grid_of(t1 - t0, grid));
-#define DC_LAUNCH_P2(S, M)                                                                        \
-    hipLaunchKernelGGL((k_tm_pass2<S, M>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,     \
+#define DC_LAUNCH_P2(S, M, R)                                                                     \
+    hipLaunchKernelGGL((k_tm_pass2<S, M, R>), g, dim3(kBlock), 0, s, table, tile_end, img0, nimg,  \
                        t0, t1, tm, curves)
     if (mixed_src)
-        DC_LAUNCH_P2(0, true);
+        DC_BY_ROWS(DC_LAUNCH_P2, 0, true);
     else if (src_dtype == 0)
-        DC_LAUNCH_P2(0, false);
+        DC_BY_ROWS(DC_LAUNCH_P2, 0, false);
     else if (src_dtype == 1)
-        DC_LAUNCH_P2(1, false);
+        DC_BY_ROWS(DC_LAUNCH_P2, 1, false);
     else
-        DC_LAUNCH_P2(2, false);
+        DC_BY_ROWS(DC_LAUNCH_P2, 2, false);
 #undef DC_LAUNCH_P2
     return hipGetLastError();
 }

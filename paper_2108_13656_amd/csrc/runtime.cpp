@@ -260,6 +260,26 @@ dc::TmArgs tm_of(const dc_tm_params *tm)
               : dc::TmArgs{1e-4f, 2.0f, 1e-3f, 1.0f, 0.5f};
 }
 
+// Walk of an image for the tile-table kernels: packed rows are one segment;
+// pitched rows take the row walk unless the width or the padding is past what
+// its 32-bit arithmetic covers (or W < 4, where a unit split by a row break
+// could reach past the next row), then one segment per row, pixel by pixel.
+int walk_of(const dc_image &m)
+{
+    const int64_t W = m.width, H = m.height;
+    const int64_t es = dc::elem_size(m.src_dtype);
+    const int64_t e1 = dc::elem_size(m.dst_dtype) * ((m.flags & DC_IMG_RGB_OUT) ? 3 : 1);
+    const int64_t e2 = m.dst2 ? dc::elem_size(m.dst2_dtype) : 0;
+    const int64_t gs = m.src_pitch - 3 * es * W, gd = m.dst_pitch - e1 * W;
+    const int64_t g2 = m.dst2 ? m.dst2_pitch - e2 * W : 0;
+    if (H == 1 || (gs == 0 && gd == 0 && g2 == 0))
+        return dc::kWalkPacked;
+    if (W >= 4 && W <= dc::kRowWalkMaxWidth && gs < dc::kRowWalkMaxGap &&
+        gd < dc::kRowWalkMaxGap && g2 < dc::kRowWalkMaxGap)
+        return dc::kWalkRows;
+    return dc::kWalkScalar;
+}
+
 // Walk classification and tile count of one image for tiles of tile_px pixels.
 dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_params *params)
 {
@@ -283,23 +303,32 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
     const int64_t es = dc::elem_size(m.src_dtype);
     const int64_t e1 = dc::elem_size(m.dst_dtype) * (d.rgb_out ? 3 : 1); // dst bytes per pixel
     const int64_t e2 = m.dst2 ? dc::elem_size(m.dst2_dtype) : 0;
-    const bool aligned = ((uintptr_t)m.src % 16 == 0) && ((uintptr_t)m.dst % 16 == 0) &&
-                         (!m.dst2 || (uintptr_t)m.dst2 % 16 == 0);
-    const bool packed = H == 1 || (m.src_pitch == 3 * es * W && m.dst_pitch == e1 * W &&
-                                   (!m.dst2 || m.dst2_pitch == e2 * W));
-    const bool rows16 = m.src_pitch % 16 == 0 && m.dst_pitch % 16 == 0 &&
-                        (!m.dst2 || m.dst2_pitch % 16 == 0);
+    const int64_t gs = m.src_pitch - 3 * es * W, gd = m.dst_pitch - e1 * W;
+    const int64_t g2 = m.dst2 ? m.dst2_pitch - e2 * W : 0;
+    // Any element-aligned base takes the vector units (the target serves
+    // unaligned dword accesses). Packed rows are one segment; pitched rows are
+    // tiled the same way over W * H pixels, with the row breaks placed per unit
+    // (the row walk), or else one segment per row (walk_of).
+    const int walk = walk_of(m);
+    const bool packed = walk == dc::kWalkPacked, rows = walk == dc::kWalkRows;
+    d.src_seg_stride = m.src_pitch;
+    d.dst_seg_stride = m.dst_pitch;
+    d.dst2_seg_stride = m.dst2 ? m.dst2_pitch : 0;
     int64_t nseg;
-    if (aligned && packed) {
-        d.walk = dc::kWalkPacked;
+    if (packed || rows) {
+        d.walk = packed ? dc::kWalkPacked : dc::kWalkRows;
         d.seg_len = W * H;
         nseg = 1;
+        if (!packed) {
+            d.magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)W +
+                                 (((uint64_t)1 << 32) % (uint64_t)W != 0));
+            d.gap_src = (uint32_t)gs;
+            d.gap_dst = (uint32_t)gd;
+            d.gap_dst2 = (uint32_t)g2;
+        }
     } else {
-        d.walk = (aligned && rows16) ? dc::kWalkRows : dc::kWalkScalar;
+        d.walk = dc::kWalkScalar;
         d.seg_len = W;
-        d.src_seg_stride = m.src_pitch;
-        d.dst_seg_stride = m.dst_pitch;
-        d.dst2_seg_stride = m.dst2 ? m.dst2_pitch : 0;
         nseg = H;
     }
     d.tiles_per_seg = (d.seg_len + tile_px - 1) / tile_px;
@@ -435,8 +464,10 @@ struct HostTable {
     // gray before colour output); runs[k] = {first image, end image, type,
     // colour output} of each run, so each pass launches its per-type kernel
     // once per run.
+    // Every table is sorted so that images on the row walk form runs of their
+    // own (rows = 1): a launch covers images of one walk kind.
     struct Run {
-        int img0, img1, src, rgb, staged;
+        int img0, img1, src, rgb, staged, rows;
     };
     std::vector<Run> runs;
     std::vector<int32_t> order; // build_table's sort permutation (kept for its capacity)
@@ -477,20 +508,27 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
     order.resize((size_t)n);
     for (int32_t i = 0; i < n; ++i)
         order[i] = i;
-    // A stable order by (input type, output kind): the caller's index breaks
-    // ties, so std::sort (which needs no temporary buffer) gives it.
-    if (kind != kTabDecolor)
-        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            // second key: colour output, then (local tone map) FP32 staging
-            auto key = [&](const dc_image &m) {
-                const int rgb = (m.flags & DC_IMG_RGB_OUT) ? 2 : 0;
-                return kind == kTabLocal ? (rgb ? rgb : (m.dst_dtype == DC_F32 ? 1 : 0)) : rgb;
-            };
-            const int ra = key(imgs[a]), rb = key(imgs[b]);
-            if (imgs[a].src_dtype != imgs[b].src_dtype)
-                return imgs[a].src_dtype < imgs[b].src_dtype;
-            return ra != rb ? ra < rb : a < b;
-        });
+    // A stable order by (walk, input type, output kind) for the tone map and
+    // the channels, by walk alone for decolorization: the caller's index
+    // breaks ties, so std::sort (which needs no temporary buffer) gives it.
+    // The local tone map has its own 2-D walk and ignores the row walk.
+    auto rows_of = [&](int32_t i) { return kind != kTabLocal && walk_of(imgs[i]) == dc::kWalkRows; };
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const bool wa = rows_of(a), wb = rows_of(b);
+        if (wa != wb)
+            return wb;
+        if (kind == kTabDecolor)
+            return a < b;
+        // then input type, then colour output, then (local tone map) FP32 staging
+        auto key = [&](const dc_image &m) {
+            const int rgb = (m.flags & DC_IMG_RGB_OUT) ? 2 : 0;
+            return kind == kTabLocal ? (rgb ? rgb : (m.dst_dtype == DC_F32 ? 1 : 0)) : rgb;
+        };
+        const int ra = key(imgs[a]), rb = key(imgs[b]);
+        if (imgs[a].src_dtype != imgs[b].src_dtype)
+            return imgs[a].src_dtype < imgs[b].src_dtype;
+        return ra != rb ? ra < rb : a < b;
+    });
     h.runs.clear();
     int64_t total = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -503,9 +541,12 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
         h.d[i] = kind == kTabLocal ? describe_local(m, order[i], pp)
                                    : describe(m, order[i], tile_px, pp);
         const int rgb = h.d[i].rgb_out, staged = h.d[i].staged;
-        if (h.runs.empty() || h.runs.back().src != m.src_dtype || h.runs.back().rgb != rgb ||
-            h.runs.back().staged != staged)
-            h.runs.push_back(HostTable::Run{i, i + 1, m.src_dtype, rgb, staged});
+        const int rows = kind != kTabLocal && h.d[i].walk == dc::kWalkRows;
+        // decolorization runs split on the walk only (one launch handles mixed types)
+        const int src = kind == kTabDecolor ? -1 : m.src_dtype;
+        if (h.runs.empty() || h.runs.back().src != src || h.runs.back().rgb != rgb ||
+            h.runs.back().staged != staged || h.runs.back().rows != rows)
+            h.runs.push_back(HostTable::Run{i, i + 1, src, rgb, staged, rows});
         else
             h.runs.back().img1 = i + 1;
         h.d[i].tile_begin = total;
@@ -615,10 +656,15 @@ int enqueue_decolor(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
                     hipStream_t st, bool marks)
 {
     mark(ctx, marks, 0, st);
-    hipError_t e = dc::launch_decolor_table(b.table, b.tile_end, (int)h.d.size(), h.total_tiles,
-                                            h.mixed, h.src0, h.groups,
-                                            grid_blocks(ctx, h.mixed ? t.mixed_gpc : t.decolor_gpc),
-                                            st);
+    hipError_t e = hipSuccess;
+    for (const auto &r : h.runs) {
+        const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
+        if (e == hipSuccess)
+            e = dc::launch_decolor_table(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1,
+                                         h.mixed, h.src0, h.groups, r.rows,
+                                         grid_blocks(ctx, h.mixed ? t.mixed_gpc : t.decolor_gpc),
+                                         st);
+    }
     if (e != hipSuccess)
         return hip_fail(e, "decolorize launch");
     mark(ctx, marks, 1, st);
@@ -677,13 +723,13 @@ int colour_mode(float saturation)
 // Curve pass over tiles [t0, t1) of images img0 .. img0 + nimg - 1, all of
 // input type src and all with (rgb) or without colour output.
 hipError_t launch_curve(const DevBufs &b, int img0, int nimg, int64_t t0, int64_t t1, int src,
-                        int rgb, dc::TmArgs a, int64_t grid, hipStream_t st)
+                        int rgb, int rows, dc::TmArgs a, int64_t grid, hipStream_t st)
 {
     if (!rgb)
-        return dc::launch_tm_pass2(b.table, b.tile_end, img0, nimg, t0, t1, 0, src, a, b.curves,
-                                   grid, st);
+        return dc::launch_tm_pass2(b.table, b.tile_end, img0, nimg, t0, t1, 0, src, rows, a,
+                                   b.curves, grid, st);
     return dc::launch_tm_colour(b.table, b.tile_end, img0, nimg, t0, t1, src,
-                                colour_mode(a.saturation), a, b.curves, grid, st);
+                                colour_mode(a.saturation), rows, a, b.curves, grid, st);
 }
 
 // Kernel sequence of a tone map over a staged table. t.tm_pipeline = 0: the
@@ -707,7 +753,7 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
             const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
             if (e == hipSuccess)
                 e = dc::launch_tm_pass1(b.table, b.tile_end, r.img0, r.img1 - r.img0, t0, t1, 0,
-                                        r.src, a, b.parts, g1, st);
+                                        r.src, r.rows, a, b.parts, g1, st);
         }
         mark(ctx, marks, 1, st);
         if (e == hipSuccess)
@@ -719,7 +765,8 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
         for (const auto &r : h.runs) {
             const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
             if (e == hipSuccess)
-                e = launch_curve(b, r.img0, r.img1 - r.img0, t0, t1, r.src, r.rgb, a, g2, st);
+                e = launch_curve(b, r.img0, r.img1 - r.img0, t0, t1, r.src, r.rgb, r.rows, a, g2,
+                                 st);
         }
         mark(ctx, marks, 3, st);
         if (e != hipSuccess)
@@ -739,8 +786,8 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
         for (int i0 = r.img0; i0 < r.img1 && e == hipSuccess; i0 += m, ++c) {
             const int k = std::min(m, r.img1 - i0);
             const int64_t t0 = h.d[i0].tile_begin, t1 = h.tile_end[i0 + k - 1];
-            e = dc::launch_tm_pass1(b.table, b.tile_end, i0, k, t0, t1, 0, r.src, a, b.parts, g1,
-                                    st);
+            e = dc::launch_tm_pass1(b.table, b.tile_end, i0, k, t0, t1, 0, r.src, r.rows, a,
+                                    b.parts, g1, st);
             if (e == hipSuccess)
                 e = hipEventRecord(ctx->fork[c], st);
             if (e == hipSuccess)
@@ -751,7 +798,7 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
             if (e == hipSuccess)
                 e = dc::launch_tm_finalize(b.table, i0, k, a, b.parts2, b.curves, stats, ctx->side);
             if (e == hipSuccess)
-                e = launch_curve(b, i0, k, t0, t1, r.src, r.rgb, a, g2, ctx->side);
+                e = launch_curve(b, i0, k, t0, t1, r.src, r.rgb, r.rows, a, g2, ctx->side);
         }
     }
     if (e == hipSuccess)
@@ -1330,6 +1377,7 @@ int dc_decolorize_batch_betas(dc_ctx *ctx, const dc_image *imgs, int32_t n,
             mark(ctx, true, 0, st);
             const hipError_t e =
                 dc::launch_sweep(b.table, n, per, h.d[0].ntiles, h.src0, h.groups,
+                                 h.d[0].walk == dc::kWalkRows,
                                  grid_blocks(ctx, ctx->tune.decolor_gpc), st);
             if (e != hipSuccess)
                 return hip_fail(e, "sweep launch");
@@ -1481,7 +1529,7 @@ int dc_channel_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, int32_t chann
             if (e == hipSuccess)
                 e = dc::launch_channel(b.table, b.tile_end, r.img0, r.img1 - r.img0,
                                        h.d[r.img0].tile_begin, h.tile_end[r.img1 - 1], r.src, channel,
-                                       0, st);
+                                       r.rows, 0, st);
         }
         if (e != hipSuccess)
             return hip_fail(e, "channel launch");
