@@ -1210,12 +1210,15 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
 // tiny addends), hence the extra 1e-6 there. The ratio is formed first, so its
 // logarithm stays small for ordinary colours and the power is accurate:
 //   kColourGrey  (s = 0): T everywhere;
-//   kColourRatio (s = 1): C k with k = 1 / ((1 + E) L), one reciprocal for T
-//                         and 1/L together (grey T = k L);
-//   kColourPow   (other s): exp2(min(s log2(C / L) + log2 T, 0)) with
-//                         log2 T = -log2(1 + E), finite where T underflows.
-// U8: the values are wanted as 8-bit codes, so they come out times 255 (for the
-// saturating 8-bit conversion, which also does the clamp at 255).
+//   kColourRatio (s = 1): C k + g, k = T / L and g = 0, or k = 0 and g = T for
+//                         a grey pixel (one reciprocal for T and 1/L together);
+//   kColourPow   (other s): exp2(s log2(C / L + g) + log2 T) with 1/L taken as
+//                         0 and g = 1 for a grey pixel (ratio 1, so T), g = 0
+//                         otherwise; log2 T = -log2(1 + E), finite where T
+//                         underflows.
+// U8: the values are wanted as 8-bit codes, so they come out times 255 (folded
+// into k, or into the exponent as log2 255) and the saturating 8-bit
+// conversion does the clamp at 255; other outputs are clamped at 1 here.
 template <int SRC, int MODE, bool U8>
 __device__ __forceinline__ void colour_px(float R, float G, float B, float l, float E, float s,
                                           float *o)
@@ -1236,18 +1239,23 @@ __device__ __forceinline__ void colour_px(float R, float G, float B, float l, fl
     if constexpr (MODE == kColourRatio) {
         const float lc = fmaxf(l, 1e-30f);
         const float k = hw_rcp((1.0f + E) * lc);
-        const float tg = k * lc * kOut;
-        const float ko = k * kOut;
+        const float ko = grey ? 0.0f : k * kOut;
+        const float g = grey ? k * lc * kOut : 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            o[c] = grey ? tg : (U8 ? C[c] * ko : fminf(C[c] * ko, 1.0f));
+        for (int c = 0; c < 3; ++c) {
+            const float v = fmaf(C[c], ko, g);
+            o[c] = U8 ? v : fminf(v, 1.0f);
+        }
     } else {
-        const float lT = -hw_log2(1.0f + E);
-        const float il = hw_rcp(l);
-        const float tg = hw_exp2(lT) * kOut;
+        constexpr float kLogOut = U8 ? 7.99435343685885793f : 0.0f; // log2(255)
+        const float lT = kLogOut - hw_log2(1.0f + E);
+        const float il = grey ? 0.0f : hw_rcp(l);
+        const float g = grey ? 1.0f : 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            o[c] = grey ? tg : hw_exp2(fminf(fmaf(s, hw_log2(C[c] * il), lT), 0.0f)) * kOut;
+        for (int c = 0; c < 3; ++c) {
+            const float e = fmaf(s, hw_log2(fmaf(C[c], il, g)), lT);
+            o[c] = hw_exp2(U8 ? e : fminf(e, 0.0f));
+        }
     }
 }
 
@@ -1883,17 +1891,24 @@ __device__ __forceinline__ void colour_of_t(float R, float G, float B, float l, 
     const float S = (R + G) + B;
     const bool grey = !(l > fmaf(S, 1e-6f, SRC == 0 ? 1e-6f : 0.0f));
     const float C[3] = {R, G, B};
-    const float il = hw_rcp(fmaxf(l, 1e-30f));
+    const float il = grey ? 0.0f : hw_rcp(fmaxf(l, 1e-30f));
     if constexpr (MODE == kColourRatio) {
         const float ko = T * il * kOut;
+        const float g = grey ? T * kOut : 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            o[c] = grey ? T * kOut : (U8 ? C[c] * ko : fminf(C[c] * ko, 1.0f));
+        for (int c = 0; c < 3; ++c) {
+            const float v = fmaf(C[c], ko, g);
+            o[c] = U8 ? v : fminf(v, 1.0f);
+        }
     } else {
-        const float lT = hw_log2(T);
+        constexpr float kLogOut = U8 ? 7.99435343685885793f : 0.0f; // log2(255)
+        const float lT = hw_log2(T) + kLogOut;
+        const float g = grey ? 1.0f : 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            o[c] = grey ? T * kOut : hw_exp2(fminf(fmaf(s, hw_log2(C[c] * il), lT), 0.0f)) * kOut;
+        for (int c = 0; c < 3; ++c) {
+            const float e = fmaf(s, hw_log2(fmaf(C[c], il, g)), lT);
+            o[c] = hw_exp2(U8 ? e : fminf(e, 0.0f));
+        }
     }
 }
 
