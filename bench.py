@@ -27,10 +27,12 @@ METRIC = "Gpixels/s + % of HBM peak (decolorize+tonemap); p50/p99 latency served
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
-def profiled_traffic():
-    """HBM bytes per launch measured with rocprofv3 counters, from the
-    summaries under profiles/ that were taken on the current kernel source
-    (an empty dict when none matches, i.e. the kernels changed since)."""
+def profiled_counters(kind="traffic_bytes"):
+    """Per-launch counter figures measured with rocprofv3, from the summaries
+    under profiles/ that were taken on the current kernel source (an empty dict
+    when none matches, i.e. the kernels changed since): kind "traffic_bytes"
+    (calibrated HBM bytes per launch) or "valu_slots_per_px" (VALU issue slots
+    per pixel from the SQ counters)."""
     import glob
     import hashlib
     import re
@@ -43,9 +45,20 @@ def profiled_traffic():
             continue
         if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(2):
             continue
-        for key, val in re.findall(r"^traffic_bytes (\S+) (\d+)$", text, re.M):
-            found[key] = int(val)
+        for key, val in re.findall(r"^%s (\S+) ([0-9.]+)$" % kind, text, re.M):
+            found[key] = float(val) if "." in val else int(val)
     return found
+
+
+def profiled_traffic():
+    return profiled_counters("traffic_bytes")
+
+
+# VALU issue: a wave64 instruction holds one of the 1024 SIMDs (256 CUs x 4)
+# for 4 cycles at 2.4 GHz, so slots / px x px take slots x px / (16 x 1024 x
+# 2.4e9) seconds of the whole chip.
+def valu_issue_ms(slots_per_px, px):
+    return slots_per_px * px / (16.0 * 1024 * 2.4e9) * 1e3
 
 
 def add_traffic_rates(obj):
@@ -352,7 +365,9 @@ def serve_leg(args, P, dev):
     def run(max_batch, max_inflight, arrivals, name):
         srv = P.Server(budget, max_batch=max_batch, max_inflight=max_inflight, device=dev)
         srv.replay(reqs[:64], [0.0] * 64)  # warm-up (workspace growth)
+        h0, n0 = srv.host_stats()
         done = srv.replay(reqs, list(arrivals))
+        h1, n1 = srv.host_stats()
         srv.close()
         if args.serve_log:
             # one JSON object per request: times on the server clock, size, format, bytes
@@ -377,7 +392,8 @@ def serve_leg(args, P, dev):
                 "p50_ms": round(1e3 * float(np.median(lat)), 3),
                 "p99_ms": round(1e3 * float(np.quantile(lat, 0.99)), 3),
                 "mean_batch": round(float(sizes.mean()), 2), "rejected": len(done) - len(ok),
-                "wall_s": round(t_last - t_first, 4)}
+                "wall_s": round(t_last - t_first, 4),
+                "host_us_per_launch": round(1e6 * (h1 - h0) / max(1, n1 - n0), 2)}
 
     sat = run(64, 4, np.zeros(len(reqs)), "saturated")
     rate = 0.7 * sat["gpx_s"] * 1e9 / px.mean()
@@ -427,11 +443,14 @@ def serve_leg(args, P, dev):
            "saturated_gpx_s": sat["gpx_s"], "rate_req_s": round(rate, 1),
            "gpx_s": served["gpx_s"], "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"],
            "mean_batch": served["mean_batch"], "rejected": served["rejected"],
+           "host_us_per_launch": served["host_us_per_launch"],
            "fifo_per_image": fifo, "host_inputs": h2d}
     log("serving: saturated %.1f Gpx/s; at %.0f req/s: %.1f Gpx/s p50 %.3f ms p99 %.3f ms "
-        "(mean batch %.1f); FIFO per-image: %.1f Gpx/s p50 %.3f ms p99 %.3f ms" %
+        "(mean batch %.1f, %.1f us of host time per launch); FIFO per-image: %.1f Gpx/s "
+        "p50 %.3f ms p99 %.3f ms" %
         (sat["gpx_s"], rate, served["gpx_s"], served["p50_ms"], served["p99_ms"],
-         served["mean_batch"], fifo["gpx_s"], fifo["p50_ms"], fifo["p99_ms"]))
+         served["mean_batch"], served["host_us_per_launch"], fifo["gpx_s"], fifo["p50_ms"],
+         fifo["p99_ms"]))
     del pools
     torch.cuda.empty_cache()
     return out
@@ -549,6 +568,44 @@ def main():
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                          "traffic": traffic.get(dom[0]), "algorithmic_bytes": dom[2]},
         })
+        roof = result["roofline"]
+        if ceilings:
+            pat = "read6_write4" if dom[0] == "tonemap_pass2" else "read"
+            c = ceilings[pat]["gbs"]
+            roof["stream_ceiling"] = {"pattern": pat, "gbs": c, "frac_of_peak": round(c / HBM_PEAK_GBS, 4),
+                                      "achieved_frac_of_ceiling": round(ach / c, 4)}
+        # The whole step against its limits: algorithmic bytes (input read
+        # once, T written once), the counted HBM bytes of both passes, the
+        # same traffic with no arithmetic (the ceilings leg's two-pass batch
+        # order), and the VALU issue time of both passes from the SQ counters.
+        slots = profiled_counters("valu_slots_per_px")
+        step = {"ms": round(ms, 4), "algorithmic_bytes": step_bytes,
+                "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if "tonemap_pass1" in traffic and "tonemap_pass2" in traffic:
+            tb = traffic["tonemap_pass1"] + traffic["tonemap_pass2"]
+            step.update({"traffic_bytes": tb, "traffic_ratio": round(tb / step_bytes, 4),
+                         "traffic_gbs": round(tb / (ms * 1e-3) / 1e9, 1),
+                         "traffic_frac": round(tb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        if ceilings:
+            fl = ceilings["tonemap_two_pass_batch"]["ms"]
+            step.update({"traffic_floor_ms": fl, "frac_of_traffic_floor": round(fl / ms, 4),
+                         "lagged_order_floor_ms": ceilings["tonemap_two_pass_lagged"]["ms"]})
+        if "tonemap_pass1" in slots and "tonemap_pass2" in slots:
+            v1 = valu_issue_ms(slots["tonemap_pass1"], hdr_px)
+            v2 = valu_issue_ms(slots["tonemap_pass2"], hdr_px)
+            step.update({"valu_slots_per_px": {"pass1": slots["tonemap_pass1"],
+                                               "pass2": slots["tonemap_pass2"]},
+                         "valu_issue_ms": {"pass1": round(v1, 4), "pass2": round(v2, 4)},
+                         "valu_issue_frac_of_kernel": {"pass1": round(v1 / k_pass1, 4),
+                                                       "pass2": round(v2 / k_pass2, 4)},
+                         "valu_floor_ms": round(v1 + v2, 4),
+                         "frac_of_valu_floor": round((v1 + v2) / ms, 4)})
+            step["limiter"] = (
+                "pass 1 issue-bound (VALU issue %.0f %% of its time, reading 6 B/px at %.0f GB/s); "
+                "pass 2 at the 6:4 stream ceiling (%.0f GB/s)" %
+                (100 * v1 / k_pass1, hdr_px * 6 / (k_pass1 * 1e-3) / 1e9,
+                 hdr_px * 10 / (k_pass2 * 1e-3) / 1e9))
+        roof["step"] = step
 
         # CPU baseline: the FP64 oracle, single thread, on a sample of images.
         if not args.no_cpu_baseline:
@@ -895,6 +952,8 @@ def main():
                            "dtype": "f32", "data": "synthetic",
                            "config": {"workload": "serving_tonemap"}, "serving": result_serve})
 
+    if ceilings and result:
+        result["ceilings"] = ceilings
     if args.save_tuning and saved:
         with open(args.save_tuning, "w") as f:
             json.dump(P.get_tuning(dev), f)

@@ -398,6 +398,11 @@ int dc_server_poll(dc_server *server, dc_completion *out, int32_t cap);
  * queued requests of one id, the oldest is cancelled. */
 int dc_server_cancel(dc_server *server, int64_t id);
 double dc_server_clock(dc_server *server);
+/* Host cost of the server's launches since it was created: the seconds spent
+ * enqueueing lane launches (descriptor table, upload and kernels of each
+ * batch) and how many there were. Either pointer may be NULL. Errors:
+ * DC_ERR_INVALID_ARG for a NULL server. */
+int dc_server_host_stats(dc_server *server, double *launch_seconds, int64_t *launches);
 /* Trace replay: submits reqs[i] when arrival_s[i] (seconds from the call,
  * non-decreasing) has passed, stepping the server in a busy loop until all n
  * have completed; out (HOST, n entries) receives the completions in the

@@ -162,6 +162,8 @@ def lib():
     L.dc_server_cancel.argtypes = [vp, ctypes.c_int64]
     L.dc_server_clock.argtypes = [vp]
     L.dc_server_clock.restype = ctypes.c_double
+    L.dc_server_host_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
     L.dc_server_replay.argtypes = [vp, req_p, ctypes.POINTER(ctypes.c_double), i32, comp_p]
     L.dc_channel_batch.argtypes = [vp, img_p, i32, i32, vp]
     L.dc_decolorize_batch_betas.argtypes = [vp, img_p, i32, par_p, vp]
@@ -668,6 +670,13 @@ class Server:
 
     def clock(self):
         return lib().dc_server_clock(self._h)
+
+    def host_stats(self):
+        """(seconds of host time spent enqueueing launches, number of launches)
+        since the server was created."""
+        sec, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().dc_server_host_stats(self._h, ctypes.byref(sec), ctypes.byref(n)))
+        return sec.value, n.value
 
     def replay(self, reqs, arrivals):
         """Replays a trace natively; returns the completions in finishing order."""

@@ -169,6 +169,13 @@ hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int 
                              hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
                               const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s);
+// Both combine levels in one launch over groups [g0, g1) of images img0 ..
+// img0 + nimg - 1; counters: one word per table image, zero at the start and
+// left zero.
+hipError_t launch_tm_combine_finalize(const DevImage *table, const int64_t *grp_end, int img0,
+                                      int nimg, int64_t g0, int64_t g1, TmArgs tm,
+                                      const WavePart *parts, Part *parts2, unsigned *counters,
+                                      Curve *curves, StatsOut *stats, hipStream_t s);
 hipError_t launch_tm_colour(const DevImage *table, const int64_t *tile_end, int img0, int nimg,
                             int64_t t0, int64_t t1, int src_dtype, int mode, int rows, TmArgs tm,
                             const Curve *curves, int64_t grid, hipStream_t s);

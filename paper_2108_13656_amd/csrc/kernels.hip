@@ -1048,6 +1048,10 @@ __device__ __forceinline__ Part part_of(const WavePart &w, float unit)
 // partials g - grp_begin of the image (one per thread, loaded in parallel) with
 // a fixed LDS tree, and thread 0 writes one group partial. Every thread of the
 // workgroup takes part; sh is kBlock entries of LDS.
+// DEVICE = the group partial is read by another workgroup of this launch:
+// it is stored field by field at device scope (written through to the point
+// where every L2 of the chip sees it).
+template <bool DEVICE = false>
 __device__ __forceinline__ void combine_group(const DevImage &im, int64_t g,
                                               const WavePart *__restrict__ parts,
                                               Part *__restrict__ parts2, Part *sh)
@@ -1062,8 +1066,19 @@ __device__ __forceinline__ void combine_group(const DevImage &im, int64_t g,
             sh[tid] = merge(sh[tid], sh[tid + s]);
         __syncthreads();
     }
-    if (tid == 0)
-        parts2[g] = sh[0];
+    if (tid == 0) {
+        if constexpr (DEVICE) {
+            float *f = &parts2[g].n;
+            const Part r = sh[0];
+            __hip_atomic_store(f + 0, r.n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(f + 1, r.mean, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(f + 2, r.m2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(f + 3, r.lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(f + 4, r.hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            parts2[g] = sh[0];
+        }
+    }
 }
 
 // Level 1 as a kernel: block g merges group g0 + g.
@@ -1091,6 +1106,22 @@ __global__ __launch_bounds__(kBlock) void k_tm_combine(const DevImage *__restric
 // group partials in a fixed order, then thread 0 writes the curve
 // coefficients (and, when asked, the statistics for the caller). Every thread
 // takes part; sh is kBlock entries of LDS.
+// A group partial written by another workgroup of the same launch, read
+// field by field at device scope (coherent across the chip's L2s).
+__device__ __forceinline__ Part load_part_device(const Part *p)
+{
+    const float *f = &p->n;
+    Part r;
+    r.n = __hip_atomic_load(f + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.mean = __hip_atomic_load(f + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.m2 = __hip_atomic_load(f + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.lo = __hip_atomic_load(f + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.hi = __hip_atomic_load(f + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return r;
+}
+
+// DEVICE = the group partials come from other workgroups of this launch.
+template <bool DEVICE = false>
 __device__ __forceinline__ void finalize_image(const DevImage &im, int img, TmArgs tm,
                                               const Part *__restrict__ parts2,
                                               Curve *__restrict__ curves,
@@ -1099,7 +1130,8 @@ __device__ __forceinline__ void finalize_image(const DevImage &im, int img, TmAr
     const int tid = threadIdx.x;
     Part a = part_empty();
     for (int64_t c = tid; c < im.ngrp; c += kBlock)
-        a = merge(a, parts2[im.grp_begin + c]);
+        a = merge(a, DEVICE ? load_part_device(&parts2[im.grp_begin + c])
+                            : parts2[im.grp_begin + c]);
     sh[tid] = a;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
@@ -1140,6 +1172,52 @@ __global__ __launch_bounds__(kBlock) void k_tm_finalize(const DevImage *__restri
     const int img = img0 + blockIdx.x;
     const DevImage im = table[img];
     finalize_image(im, img, tm, parts2, curves, stats, sh);
+}
+
+// Both levels of the combine in one launch: block g0 + blockIdx.x merges its
+// group (level 1, as k_tm_combine) and publishes the group partial, and the
+// block that completes an image's groups merges them (level 2, as
+// k_tm_finalize) and resets the image's counter to 0 for the next use. The
+// merge trees are those of the two-kernel form, so the results are the same
+// bits; counters holds one word per table image, zero when the launch starts.
+// Publication: the partial is stored at device scope (its stores written
+// through), the workgroup waits until those stores have completed, and only
+// then counts its group with a device-scope atomic; the last counter reads the
+// partials with device-scope loads after that atomic has returned. No L2
+// write-back is needed, since nothing else of this launch is read across
+// workgroups (a release fence per workgroup, which writes the L2 back, costs
+// ~20 us over the 1024 groups of 16 x 4096^2 images).
+__global__ __launch_bounds__(kBlock) void k_tm_combine_finalize(
+    const DevImage *__restrict__ table, const int64_t *__restrict__ grp_end, int img0, int nimg,
+    int64_t g0, TmArgs tm, const WavePart *__restrict__ parts, Part *__restrict__ parts2,
+    unsigned *__restrict__ counters, Curve *__restrict__ curves, StatsOut *__restrict__ stats)
+{
+    __shared__ Part sh[kBlock];
+    __shared__ int last;
+    const int64_t g = g0 + blockIdx.x;
+    int lo = img0, hi = img0 + nimg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (grp_end[mid] > g)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    const DevImage im = table[lo];
+    combine_group<true>(im, g, parts, parts2, sh);
+    if (threadIdx.x == 0) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0); // the partial's stores have completed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        last = __hip_atomic_fetch_add(&counters[lo], 1u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) == (unsigned)(im.ngrp - 1);
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    finalize_image<true>(im, lo, tm, parts2, curves, stats, sh);
+    if (threadIdx.x == 0)
+        counters[lo] = 0u;
 }
 
 // T = 1 / (1 + exp2(a (x2 - mu2))) of one pixel.
@@ -2214,6 +2292,16 @@ hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int 
 {
     hipLaunchKernelGGL(k_tm_combine, dim3((unsigned)(g1 - g0)), dim3(kBlock), 0, s, table, grp_end,
                        img0, nimg, g0, parts, parts2);
+    return hipGetLastError();
+}
+
+hipError_t launch_tm_combine_finalize(const DevImage *table, const int64_t *grp_end, int img0,
+                                      int nimg, int64_t g0, int64_t g1, TmArgs tm,
+                                      const WavePart *parts, Part *parts2, unsigned *counters,
+                                      Curve *curves, StatsOut *stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tm_combine_finalize, dim3((unsigned)(g1 - g0)), dim3(kBlock), 0, s, table,
+                       grp_end, img0, nimg, g0, tm, parts, parts2, counters, curves, stats);
     return hipGetLastError();
 }
 

@@ -579,9 +579,12 @@ void build_table(const dc_image *imgs, int32_t n, const dc_params *params, Table
 // then the workspace: wave partials | group partials | curves, and for the
 // local tone map tile histograms | tile curve tables.
 struct Layout {
-    size_t table, ends, gends, parts, parts2, curves, hist, coef, upload, total;
+    size_t table, ends, gends, counters, parts, parts2, curves, hist, coef, upload, total;
 };
 
+// The tone map's per-image combine counters are part of the upload, written
+// as zeros with the table, so a staged call starts from zero whatever the
+// slot held before; the combine leaves them zero again (plans upload once).
 Layout layout_of(const HostTable &h)
 {
     const size_t n = h.d.size();
@@ -589,7 +592,8 @@ Layout layout_of(const HostTable &h)
     l.table = 0;
     l.ends = align_up(sizeof(dc::DevImage) * n, 256);
     l.gends = l.ends + align_up(sizeof(int64_t) * n, 256);
-    l.parts = l.gends + align_up(sizeof(int64_t) * n, 256);
+    l.counters = l.gends + align_up(sizeof(int64_t) * n, 256);
+    l.parts = l.counters + (h.tonemap ? align_up(sizeof(unsigned) * n, 256) : 0);
     l.upload = l.parts;
     l.parts2 = l.parts + (h.tonemap ? align_up(sizeof(dc::WavePart) * (size_t)h.total_tiles *
                                                    dc::kWavesPerBlock, 256) : 0);
@@ -606,6 +610,7 @@ void write_upload(const HostTable &h, const Layout &l, char *dst)
     std::memcpy(dst + l.table, h.d.data(), sizeof(dc::DevImage) * h.d.size());
     std::memcpy(dst + l.ends, h.tile_end.data(), sizeof(int64_t) * h.tile_end.size());
     std::memcpy(dst + l.gends, h.grp_end.data(), sizeof(int64_t) * h.grp_end.size());
+    std::memset(dst + l.counters, 0, l.parts - l.counters);
 }
 
 static_assert(DC_NOALLOC_SCRATCH_BYTES == dc::kScratchBytes, "scratch size in the ABI header");
@@ -624,17 +629,19 @@ struct NoAlloc {
     bool pending = false;
 };
 
-// Bytes of the largest upload (table, tile ends, group ends) of a call.
+// Bytes of the largest upload (table, tile ends, group ends, counters) of a call.
 size_t noalloc_upload_cap()
 {
     const size_t n = dc::kScratchMaxImages;
-    return align_up(sizeof(dc::DevImage) * n, 256) + 2 * align_up(sizeof(int64_t) * n, 256);
+    return align_up(sizeof(dc::DevImage) * n, 256) + 2 * align_up(sizeof(int64_t) * n, 256) +
+           align_up(sizeof(unsigned) * n, 256);
 }
 
 struct DevBufs {
     const dc::DevImage *table;
     const int64_t *tile_end;
     const int64_t *grp_end;
+    unsigned *counters;
     dc::WavePart *parts;
     dc::Part *parts2;
     dc::Curve *curves;
@@ -646,7 +653,8 @@ DevBufs bufs_of(void *dev, const Layout &l)
 {
     char *p = (char *)dev;
     return DevBufs{(const dc::DevImage *)(p + l.table), (const int64_t *)(p + l.ends),
-                   (const int64_t *)(p + l.gends), (dc::WavePart *)(p + l.parts),
+                   (const int64_t *)(p + l.gends), (unsigned *)(p + l.counters),
+                   (dc::WavePart *)(p + l.parts),
                    (dc::Part *)(p + l.parts2), (dc::Curve *)(p + l.curves),
                    (unsigned *)(p + l.hist), (dc::LtmCoef *)(p + l.coef)};
 }
@@ -741,8 +749,12 @@ hipError_t launch_curve(const DevBufs &b, int img0, int nimg, int64_t t0, int64_
 // pass of the next (the VALU-bound statistics pass beside the memory-bound
 // curve pass). Every schedule computes the same values: each kernel's
 // per-image work is fixed.
+// one_launch_combine: both combine levels in one kernel (one launch fewer,
+// for the server's small latency-bound batches; the two-kernel form is faster
+// on the device for large calls). Both give the same bits.
 int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tune &t,
-                    dc::TmArgs a, dc::StatsOut *stats, hipStream_t st, bool marks)
+                    dc::TmArgs a, dc::StatsOut *stats, hipStream_t st, bool marks,
+                    bool one_launch_combine = false)
 {
     const int n = (int)h.d.size();
     const int64_t g1 = grid_blocks(ctx, t.pass1_gpc), g2 = grid_blocks(ctx, t.pass2_gpc);
@@ -756,11 +768,18 @@ int enqueue_tonemap(dc_ctx *ctx, const HostTable &h, const DevBufs &b, const Tun
                                         r.src, r.rows, a, b.parts, g1, st);
         }
         mark(ctx, marks, 1, st);
-        if (e == hipSuccess)
-            e = dc::launch_tm_combine(b.table, b.grp_end, 0, n, 0, h.total_grps, b.parts, b.parts2,
-                                      st);
-        if (e == hipSuccess)
-            e = dc::launch_tm_finalize(b.table, 0, n, a, b.parts2, b.curves, stats, st);
+        if (one_launch_combine) {
+            if (e == hipSuccess)
+                e = dc::launch_tm_combine_finalize(b.table, b.grp_end, 0, n, 0, h.total_grps, a,
+                                                   b.parts, b.parts2, b.counters, b.curves, stats,
+                                                   st);
+        } else {
+            if (e == hipSuccess)
+                e = dc::launch_tm_combine(b.table, b.grp_end, 0, n, 0, h.total_grps, b.parts,
+                                          b.parts2, st);
+            if (e == hipSuccess)
+                e = dc::launch_tm_finalize(b.table, 0, n, a, b.parts2, b.curves, stats, st);
+        }
         mark(ctx, marks, 2, st);
         for (const auto &r : h.runs) {
             const int64_t t0 = h.d[r.img0].tile_begin, t1 = h.tile_end[r.img1 - 1];
@@ -1754,6 +1773,9 @@ struct dc_server {
         hipEvent_t done = nullptr;
         std::vector<Req> batch;
         bool busy = false;
+        // per-launch host buffers, kept for their capacity
+        std::vector<dc_image> imgs;
+        HostTable h;
     };
     dc_ctx *ctx = nullptr;
     dc_server_config cfg{};
@@ -1764,6 +1786,9 @@ struct dc_server {
     std::vector<dc_completion> done;
     std::chrono::steady_clock::time_point t0;
     int64_t in_system = 0;
+    // host time spent enqueueing lane launches, and their number
+    double launch_host_s = 0.0;
+    int64_t launches = 0;
 };
 
 namespace {
@@ -1877,8 +1902,10 @@ int server_step(dc_server *sv)
         if (ln.busy)
             continue;
         TraceRange trace("dc_server_launch");
+        const auto t_begin = std::chrono::steady_clock::now();
         const size_t k = std::min<size_t>(sv->admitted.size(), (size_t)sv->cfg.max_batch);
-        std::vector<dc_image> imgs(k);
+        std::vector<dc_image> &imgs = ln.imgs;
+        imgs.resize(k);
         const double t = server_now(sv);
         for (size_t i = 0; i < k; ++i) {
             ln.batch.push_back(sv->admitted.front());
@@ -1907,15 +1934,26 @@ int server_step(dc_server *sv)
                 imgs[i].flags &= ~DC_IMG_HOST_SRC;
             }
         }
-        HostTable h;
-        build_table(imgs.data(), (int32_t)k, &sv->cfg.params, kTabTonemap, sv->ctx->tune, h);
+        HostTable &h = ln.h;
+        {
+            TraceRange tr("dc_server_launch_table");
+            build_table(imgs.data(), (int32_t)k, &sv->cfg.params, kTabTonemap, sv->ctx->tune, h);
+        }
         dc_ctx::Slot *slot = nullptr;
         DevBufs b;
-        int rc = stage(sv->ctx, h, ln.s, &slot, &b);
+        int rc;
+        {
+            TraceRange tr("dc_server_launch_upload");
+            rc = stage(sv->ctx, h, ln.s, &slot, &b);
+        }
         if (rc != DC_OK)
             return fail_lane(sv, ln, rc);
         SlotHold hold{slot, ln.s};
-        rc = enqueue_tonemap(sv->ctx, h, b, sv->ctx->tune, tm_of(&sv->cfg.tm), nullptr, ln.s, false);
+        {
+            TraceRange tr("dc_server_launch_kernels");
+            rc = enqueue_tonemap(sv->ctx, h, b, sv->ctx->tune, tm_of(&sv->cfg.tm), nullptr, ln.s,
+                                 false, true);
+        }
         if (rc == DC_OK)
             rc = hold.finish();
         if (rc != DC_OK)
@@ -1924,6 +1962,9 @@ int server_step(dc_server *sv)
         if (e != hipSuccess)
             return fail_lane(sv, ln, hip_fail(e, "hipEventRecord"));
         ln.busy = true;
+        sv->launch_host_s +=
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count();
+        ++sv->launches;
     }
     return DC_OK;
 }
@@ -1995,6 +2036,17 @@ int dc_server_destroy(dc_server *sv)
         delete sv;
         return DC_OK;
     });
+}
+
+int dc_server_host_stats(dc_server *sv, double *launch_seconds, int64_t *launches)
+{
+    if (!sv)
+        return fail(DC_ERR_INVALID_ARG, "server is NULL");
+    if (launch_seconds)
+        *launch_seconds = sv->launch_host_s;
+    if (launches)
+        *launches = sv->launches;
+    return DC_OK;
 }
 
 double dc_server_clock(dc_server *sv) { return sv ? server_now(sv) : 0.0; }

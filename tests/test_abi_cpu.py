@@ -206,6 +206,7 @@ def test_server_calls_reject_bad_arguments(lib):
     assert lib.dc_server_submit(None, None, 0, -1.0) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_poll(None, None, 0) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_cancel(None, 7) == P.DC_ERR_INVALID_ARG
+    assert lib.dc_server_host_stats(None, None, None) == P.DC_ERR_INVALID_ARG
     assert lib.dc_server_destroy(None) == P.DC_OK
     assert lib.dc_plan_destroy(None) == P.DC_OK
     assert lib.dc_plan_run(None, None) == P.DC_ERR_INVALID_ARG

@@ -68,3 +68,19 @@ def test_committed_profiles_carry_their_source_and_traffic():
             assert m and os.path.exists(os.path.join(ROOT, m.group(1))), fn
             assert re.search(r"^rocprofv3 .* -- python3 bench\.py", text, re.M), fn
     assert with_traffic >= 6
+
+
+def test_valu_slots_from_profiles_and_issue_time(tmp_path, monkeypatch):
+    b = _bench()
+    src = tmp_path / "k.hip"
+    src.write_text("kernel source\n")
+    digest = hashlib.sha256(src.read_bytes()).hexdigest()
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "a.md").write_text(
+        "source sha256 (k.hip): %s\n\n```\nvalu_slots_per_px pass_a 43.47\n"
+        "traffic_bytes pass_a 1000\n```\n" % digest)
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.profiled_counters("valu_slots_per_px") == {"pass_a": 43.47}
+    assert b.profiled_traffic() == {"pass_a": 1000}
+    # 43.47 slots/px on 16 x 4096^2 px: 43.47 * 268435456 / (16 * 1024 * 2.4e9) s = 0.2967 ms
+    assert abs(b.valu_issue_ms(43.47, 16 * 4096 * 4096) - 0.29675) < 1e-4

@@ -139,9 +139,13 @@ def test_replay_trace_completes(dev):
     arrivals = list(np.cumsum(np.random.default_rng(4).exponential(2e-5, len(reqs))) - 2e-5)
     srv = P.Server(budget_bytes=64 << 20, max_batch=32, max_inflight=4)
     done = srv.replay(reqs, arrivals)
+    host_s, launches = srv.host_stats()
     srv.close()
     torch.cuda.synchronize()
     assert sorted(c.id for c in done) == list(range(len(reqs)))
+    # every completed request rode in some launch; host time was spent on each
+    assert 1 <= launches <= len(reqs) and host_s > 0.0
+    report("replay: %d launches, %.1f us of host time each" % (launches, 1e6 * host_s / launches))
     lat = np.array([c.t_done - c.t_submit for c in done])
     report("replay latency p50 %.1f us p99 %.1f us" % (1e6 * np.median(lat),
                                                        1e6 * np.quantile(lat, 0.99)))

@@ -301,3 +301,30 @@ def test_hdr_storage_error_against_exact_radiance(dev):
            (rel, half + 1e-5, dt, bound_t))
     assert rel <= half + 1e-5
     assert dt <= bound_t
+
+
+def test_combine_publication_across_workgroups(dev):
+    """The one-launch combine publishes each group partial for the workgroup
+    that completes its image. Two batches of different shapes alternate 24
+    times through the same context (its workspace slots hold the other
+    batch's partials and counters in between); every run's statistics and T
+    must repeat the first run's bits, and match the oracle."""
+    rng = np.random.default_rng(31)
+    a = [synth.hdr_pixels(rng, 1100, 900), synth.sdr_pixels(rng, 2000, 1500),
+         synth.hdr_pixels(rng, 64, 64)]
+    b = [synth.sdr_pixels(rng, 517, 3001), synth.hdr_pixels(rng, 2048, 2048)]
+    batches = [[to_dev(x, dev) for x in a], [to_dev(x, dev) for x in b]]
+    first = [None, None]
+    for rep in range(24):
+        k = rep % 2
+        outs, _, st = P.tonemap_global(batches[k], **TM)
+        torch.cuda.synchronize()
+        if first[k] is None:
+            first[k] = (outs, st)
+            for img, s in zip(a if k == 0 else b, P.stats_to_host(st)):
+                _, _, ref = oracle.tonemap(img, **TM)
+                _check_stats(s, ref, "batch %d" % k)
+        else:
+            assert torch.equal(st, first[k][1]), rep
+            for o, w in zip(outs, first[k][0]):
+                assert torch.equal(o, w), rep
