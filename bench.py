@@ -891,6 +891,8 @@ def main():
                     sp.run(stream)
 
             ums = time_steps(lambda: uplan.run(stream), args.steps, args.warmup, stream)
+            # the same launch without the graph, for the step's time outside the kernel
+            ums_direct = time_steps(lambda: uplan_ev.run(stream), args.steps, args.warmup, stream)
             uk = kernel_times(lambda: uplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
             ums_single = None if args.no_per_image else \
                 time_steps(ustep_single, max(3, args.steps // 2), 1, stream)
@@ -900,7 +902,8 @@ def main():
         uneven = {"workload": "uneven_batch_decolorize", "images": len(imgs), "pixels": upx,
                   "src": "128 u8 + 128 f16, sides log-uniform 64..4096", "dst": "f32",
                   "ms_per_step": round(ums, 4), "value": round(upx / (ums * 1e-3) / 1e9, 3),
-                  "unit": "Gpixels/s",
+                  "unit": "Gpixels/s", "kernel_ms": round(uk, 4),
+                  "direct_launch_ms_per_step": round(ums_direct, 4),
                   "per_image_launches_gpx": round(upx / (ums_single * 1e-3) / 1e9, 3)
                   if ums_single else None,
                   "tuning": {"mixed_groups": utune["mixed_groups"],

@@ -318,7 +318,12 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *tuning);
  * than 2 % faster, so timing noise does not flip between equal shapes) and
  * writes it to *chosen (if not NULL). The candidate runs write the images'
  * outputs. Synchronises `stream`. kind DC_PLAN_LOCAL is not tuned
- * (DC_ERR_INVALID_ARG). */
+ * (DC_ERR_INVALID_ARG). With the environment variable DC_AUTOTUNE=0 the call
+ * measures nothing and keeps (and reports) the shapes in place.
+ *
+ * Environment: DC_LOG_LEVEL=1 makes every failing call print its message
+ * (dc_last_error_message) to stderr; DC_LOG_LEVEL=2 also prints the
+ * autotuner's choices. Both variables are read once per process. */
 int dc_autotune(dc_ctx *ctx, int32_t kind, const dc_image *imgs, int32_t n,
                 const dc_params *params, const dc_tm_params *tm, void *stream,
                 dc_tuning *chosen);

@@ -169,6 +169,10 @@ hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int 
                              hipStream_t s);
 hipError_t launch_tm_finalize(const DevImage *table, int img0, int nimg, TmArgs tm,
                               const Part *parts2, Curve *curves, StatsOut *stats, hipStream_t s);
+// Copies rows x row_bytes from src (pitch src_pitch; may be pinned host memory)
+// to dst (pitch dst_pitch).
+hipError_t launch_copy_rows(void *dst, int64_t dst_pitch, const void *src, int64_t src_pitch,
+                            int64_t row_bytes, int rows, hipStream_t s);
 // Both combine levels in one launch over groups [g0, g1) of images img0 ..
 // img0 + nimg - 1; counters: one word per table image, zero at the start and
 // left zero.

@@ -2105,6 +2105,31 @@ __global__ __launch_bounds__(kBlock) void k_ltm_pass2(const DevImage *__restrict
     });
 }
 
+// ------------------------------------------------------------ row copy
+
+// Copies `rows` rows of row_bytes each from src (row pitch src_pitch; for the
+// server, a pinned host buffer the GPU reads across PCIe) to dst (row pitch
+// dst_pitch): workgroup (x, y) moves 16-byte pieces x * 256 + tid of row y,
+// the unaligned pieces and the row's last bytes included (the target serves
+// unaligned dword accesses); the grid is (ceil(row_bytes / 4096), rows).
+__global__ __launch_bounds__(kBlock) void k_copy_rows(uint8_t *__restrict__ dst, int64_t dst_pitch,
+                                                      const uint8_t *__restrict__ src,
+                                                      int64_t src_pitch, int64_t row_bytes)
+{
+    const int64_t y = blockIdx.y;
+    const int64_t off = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 16;
+    if (off >= row_bytes)
+        return;
+    const uint8_t *s = src + y * src_pitch + off;
+    uint8_t *d = dst + y * dst_pitch + off;
+    if (off + 16 <= row_bytes) {
+        *gpw<u32x4>(d) = *gp<u32x4>(s);
+    } else {
+        for (int64_t i = 0; off + i < row_bytes; ++i)
+            *gpw<uint8_t>(d + i) = *gp<uint8_t>(s + i);
+    }
+}
+
 // ------------------------------------------------------------ scratch
 
 // Workspace of dc_tonemap_global_noalloc: one per device, held until the
@@ -2293,6 +2318,27 @@ hipError_t launch_tm_combine(const DevImage *table, const int64_t *grp_end, int 
     hipLaunchKernelGGL(k_tm_combine, dim3((unsigned)(g1 - g0)), dim3(kBlock), 0, s, table, grp_end,
                        img0, nimg, g0, parts, parts2);
     return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(void *dst, int64_t dst_pitch, const void *src, int64_t src_pitch,
+                            int64_t row_bytes, int rows, hipStream_t s)
+{
+    if (rows < 1 || row_bytes < 1)
+        return hipSuccess;
+    const int64_t gx = (row_bytes + (int64_t)kBlock * 16 - 1) / ((int64_t)kBlock * 16);
+    if (gx > 0x7fffffff)
+        return hipErrorInvalidValue;
+    // the grid's y extent is at most 65535: rows go in chunks of that many
+    for (int r0 = 0; r0 < rows; r0 += 65535) {
+        const int n = rows - r0 < 65535 ? rows - r0 : 65535;
+        hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)gx, (unsigned)n), dim3(kBlock), 0, s,
+                           (uint8_t *)dst + (int64_t)r0 * dst_pitch, dst_pitch,
+                           (const uint8_t *)src + (int64_t)r0 * src_pitch, src_pitch, row_bytes);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_tm_combine_finalize(const DevImage *table, const int64_t *grp_end, int img0,

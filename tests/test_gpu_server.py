@@ -199,6 +199,41 @@ def test_host_input_requests(dev):
         assert torch.equal(alone[0], o), i
 
 
+def test_pitched_host_input_requests(dev):
+    """Pinned host inputs whose rows are further apart than their bytes (crops
+    of a wider pinned image, some starting at an odd element): the server
+    gathers the rows into its budget with a copy kernel; results equal the
+    device-input tone map bit for bit."""
+    rng = np.random.default_rng(12)
+    reqs, xs, outs = [], [], []
+    for i, (h, w, pad, off) in enumerate([(37, 101, 9, 1), (300, 517, 64, 3), (5, 4099, 1, 0),
+                                          (1, 33, 0, 2), (256, 256, 128, 5)]):
+        kind = np.uint8 if i % 2 == 0 else np.float16
+        img = synth.sdr_pixels(rng, h, w) if kind == np.uint8 else synth.hdr_pixels(rng, h, w)
+        t = torch.from_numpy(img)
+        pitch = 3 * w + 3 * pad
+        buf = torch.zeros(off + h * pitch + 8, dtype=t.dtype).pin_memory()
+        view = buf[off:off + h * pitch].view(h, pitch)[:, :3 * w].view(h, w, 3)
+        view.copy_(t)
+        xs.append(t.to(dev))
+        o = torch.empty((h, w), dtype=torch.float32, device=dev)
+        outs.append(o)
+        reqs.append(P.request_for(i, view, o))
+        assert reqs[-1].img.src_pitch == pitch * t.element_size()
+    srv = P.Server(budget_bytes=64 << 20, max_batch=4, max_inflight=2)
+    srv.submit(reqs)
+    done = []
+    while len(done) < len(reqs):
+        srv.step()
+        done += srv.poll()
+    srv.close()
+    torch.cuda.synchronize()
+    assert all(c.status == P.DC_OK for c in done)
+    for i, (x, o) in enumerate(zip(xs, outs)):
+        alone, _, _ = P.tonemap_global([x], o.dtype)
+        assert torch.equal(alone[0], o), i
+
+
 def test_host_input_budget_counts_the_copy(dev):
     """An input copy larger than the whole budget is rejected at once."""
     x = torch.zeros((512, 512, 3), dtype=torch.float16).pin_memory()
