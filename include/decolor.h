@@ -288,9 +288,10 @@ int dc_plan_destroy(dc_plan *plan);
  * groups (48 input bytes each) per thread in a decolorization tile, 1, 2 or 4,
  * per input type (index DC_U8, DC_F16, DC_F32) and for batches mixing input
  * types; *_grid_per_cu: persistent workgroups per compute unit, 0..64, where
- * 0 launches one workgroup per tile; tonemap_pipeline 1 runs the tone map
- * image by image with the curve pass of one image on a second stream beside the
- * statistics pass of the next. The tone map's statistics chunks are fixed
+ * 0 launches one workgroup per tile; tonemap_pipeline m >= 1 runs the tone map
+ * in groups of m images with the curve pass of one group on a second stream
+ * beside the statistics pass of the next (the autotuner compares m = 0 and 1).
+ * The tone map's statistics chunks are fixed
  * (1024 pixels per partial, merged in a fixed tree), so no setting changes any
  * result bit. The local tone map always runs one workgroup per 64 x 64 tile and
  * is not tuned. */

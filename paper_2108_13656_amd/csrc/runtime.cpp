@@ -411,7 +411,7 @@ struct Tune {
     int mixed_gpc = 0;
     int pass1_gpc = 16;
     int pass2_gpc = 0;
-    int tm_pipeline = 0; // 1 = per-image tone map on two streams
+    int tm_pipeline = 0; // m >= 1: the tone map in groups of m images on two streams
 };
 
 namespace {
@@ -736,8 +736,8 @@ int sweep_per(const dc_ctx *ctx, const HostTable &h)
     return (int)((n + chunks - 1) / chunks);
 }
 
-// Events for the per-image pipeline: fork[i] marks "statistics pass of image
-// i done" on the main stream; fork[n] marks "side stream done".
+// Events for the grouped pipeline: fork[i] marks "statistics pass of group i
+// done" on the main stream; fork[n] marks "side stream done".
 int ensure_fork(dc_ctx *ctx, size_t n)
 {
     if (!ctx->side) {
@@ -1301,7 +1301,7 @@ int dc_set_tuning(dc_ctx *ctx, const dc_tuning *t)
             return fail(DC_ERR_INVALID_ARG, "context or tuning is NULL");
         if (!tune_ok(*t))
             return fail(DC_ERR_INVALID_ARG, "groups must be 1, 2 or 4, grids per CU in [0, 64] and "
-                                            "tonemap_pipeline 0 or 1");
+                                            "tonemap_pipeline in [0, 1024]");
         ctx->tune = from_public(*t);
         return DC_OK;
     });
