@@ -128,6 +128,13 @@ __device__ __forceinline__ float lum(float R, float G, float B, Coef k)
 
 // ------------------------------------------------------------ memory
 
+// Buffer resources for the packed walk's loads: word 3 selects 32-bit data
+// with no swizzle (the raw form on gfx9-class chips), the record count is set
+// to its maximum so no range check ever clips a load, and the cache-policy bit
+// 2 marks a load nontemporal (streaming), as __builtin_nontemporal_load does.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kBufferNontemporal = 2;
+
 // Image pointers come from descriptors in memory, so the compiler cannot tell
 // they are global; these casts give global_load/global_store instead of flat.
 // The pointee types carry 1-byte alignment: on the row walk a unit's address
@@ -490,6 +497,28 @@ __device__ __forceinline__ void load_units(const TileRef &t, unsigned (&w)[U][3]
                                            UnitPos (&up)[U])
 {
     constexpr int PPU = unit_px(SRC);
+    if constexpr (!ROWS) {
+        // Packed walk (4-byte aligned tile base, which the runtime guarantees
+        // for this walk): unit u of lane x lies u * kBlock + x units from the
+        // tile's first byte. Buffer loads through a resource on that byte take
+        // the lane offset from one register and u's offset from a scalar one,
+        // so the loads cost no per-lane address arithmetic. The three dword
+        // loads of a unit are merged into one dwordx3.
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((void *)t.src, (short)0, -1, kBufferWord3);
+        uint32_t off = threadIdx.x * 12u;
+        asm("" : "+v"(off)); // an opaque sum, so the 4 and 8 fold into the loads' offsets
+        constexpr int aux = NT ? kBufferNontemporal : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int so = u * (kBlock * 12);
+            up[u] = UnitPos{0u, false};
+            w[u][0] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off, so, aux);
+            w[u][1] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4u, so, aux);
+            w[u][2] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off + 8u, so, aux);
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         up[u] = unit_pos<PPU, ROWS>(t, slot_lp<PPU>(true, u, 0));
@@ -896,26 +925,61 @@ __device__ __forceinline__ float xlog2(float l, float unit, float eps)
     return hw_log2(fmaf(l, unit, eps));
 }
 
+// Wave-wide reductions with DPP row permutes (no LDS round trip): two quad
+// swaps, a half-row and a row mirror leave every lane of a 16-lane row with
+// the row's result; row_bcast:15 then folds row 0 into row 1 and row 2 into
+// row 3, and row_bcast:31 rows 0-1 into rows 2-3, so lane 63 holds the result
+// over all 64 lanes, which readlane returns as a uniform value. Lanes of rows a
+// broadcast step leaves alone take the operation's identity.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_from(int identity, int v)
+{
+    return __builtin_amdgcn_update_dpp(identity, v, CTRL, ROW_MASK, 0xf, false);
+}
+constexpr int kDppQuad1032 = 0xb1, kDppQuad2301 = 0x4e, kDppRowHalfMirror = 0x141,
+              kDppRowMirror = 0x140, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_xor(v, off, 64);
-    return v;
+    // Rows that a broadcast step leaves alone add +0 (only lane 63 is read).
+    constexpr int id = 0;
+    auto add = [](float a, int b) { return a + __builtin_bit_cast(float, b); };
+    v = add(v, dpp_from<kDppQuad1032>(id, __builtin_bit_cast(int, v)));
+    v = add(v, dpp_from<kDppQuad2301>(id, __builtin_bit_cast(int, v)));
+    v = add(v, dpp_from<kDppRowHalfMirror>(id, __builtin_bit_cast(int, v)));
+    v = add(v, dpp_from<kDppRowMirror>(id, __builtin_bit_cast(int, v)));
+    v = add(v, dpp_from<kDppRowBcast15, 0xa>(id, __builtin_bit_cast(int, v)));
+    v = add(v, dpp_from<kDppRowBcast31, 0xc>(id, __builtin_bit_cast(int, v)));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
+
+// Extremes of values that are never NaN and never -0 (luminance, or the
+// infinities that stand for no pixel): for such floats the order of their bits
+// as signed integers is their numeric order, so integer min / max take the
+// place of the float ones (which would first quiet possible signalling NaNs).
 __device__ __forceinline__ float wave_min(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v = fminf(v, __shfl_xor(v, off, 64));
-    return v;
+    int x = __builtin_bit_cast(int, v);
+    constexpr int id = 0x7fffffff;
+    x = min(x, dpp_from<kDppQuad1032>(id, x));
+    x = min(x, dpp_from<kDppQuad2301>(id, x));
+    x = min(x, dpp_from<kDppRowHalfMirror>(id, x));
+    x = min(x, dpp_from<kDppRowMirror>(id, x));
+    x = min(x, dpp_from<kDppRowBcast15, 0xa>(id, x));
+    x = min(x, dpp_from<kDppRowBcast31, 0xc>(id, x));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(x, 63));
 }
 __device__ __forceinline__ float wave_max(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v = fmaxf(v, __shfl_xor(v, off, 64));
-    return v;
+    int x = __builtin_bit_cast(int, v);
+    constexpr int id = (int)0x80000000u;
+    x = max(x, dpp_from<kDppQuad1032>(id, x));
+    x = max(x, dpp_from<kDppQuad2301>(id, x));
+    x = max(x, dpp_from<kDppRowHalfMirror>(id, x));
+    x = max(x, dpp_from<kDppRowMirror>(id, x));
+    x = max(x, dpp_from<kDppRowBcast15, 0xa>(id, x));
+    x = max(x, dpp_from<kDppRowBcast31, 0xc>(id, x));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(x, 63));
 }
 
 // Statistics pass over one tile of kStatsChunkPx pixels (16 per thread). Each
@@ -986,8 +1050,8 @@ __device__ __forceinline__ void tm_pass1_tile(const DevImage &im, int64_t tile, 
     s = wave_sum(s);
     q = wave_sum(q);
     const float n = full ? (float)(64 * NV) : wave_sum(cnt); // a full tile fills every lane
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    lo = wave_min(lo + 0.0f); // + 0 turns a -0 into +0
+    hi = wave_max(hi + 0.0f);
     if ((threadIdx.x & 63) == 0)
         parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] =
             WavePart{n, K, s, q, lo, hi};
@@ -1659,8 +1723,8 @@ __device__ __forceinline__ void ltm_pass1_tile(const DevImage &im, int64_t tile,
     s = wave_sum(s);
     q = wave_sum(q);
     const float n = wave_sum(cnt);
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+    lo = wave_min(lo + 0.0f); // + 0 turns a -0 into +0
+    hi = wave_max(hi + 0.0f);
     if ((threadIdx.x & 63) == 0)
         parts[im.chunk_begin + tile * kWavesPerBlock + (threadIdx.x >> 6)] =
             WavePart{n, K, s, q, lo, hi};

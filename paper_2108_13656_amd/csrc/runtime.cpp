@@ -294,10 +294,12 @@ dc::TmArgs tm_of(const dc_tm_params *tm)
               : dc::TmArgs{1e-4f, 2.0f, 1e-3f, 1.0f, 0.5f};
 }
 
-// Walk of an image for the tile-table kernels: packed rows are one segment;
-// pitched rows take the row walk unless the width or the padding is past what
-// its 32-bit arithmetic covers (or W < 4, where a unit split by a row break
-// could reach past the next row), then one segment per row, pixel by pixel.
+// Walk of an image for the tile-table kernels: packed rows are one segment
+// (the packed walk from a 4-byte aligned start, else the row walk with zero
+// gaps); pitched rows take the row walk unless the width or the padding is past
+// what its 32-bit arithmetic covers (or W < 4, where a unit split by a row
+// break could reach past the next row), then one segment per row, pixel by
+// pixel.
 int walk_of(const dc_image &m)
 {
     const int64_t W = m.width, H = m.height;
@@ -306,8 +308,16 @@ int walk_of(const dc_image &m)
     const int64_t e2 = m.dst2 ? dc::elem_size(m.dst2_dtype) : 0;
     const int64_t gs = m.src_pitch - 3 * es * W, gd = m.dst_pitch - e1 * W;
     const int64_t g2 = m.dst2 ? m.dst2_pitch - e2 * W : 0;
+    // The packed walk's unit loads are buffer loads from each tile's first
+    // byte, which must be 4-byte aligned: tiles start at multiples of 12 bytes
+    // from the image's first byte, so that byte must be. Packed rows at an
+    // unaligned start take the row walk with zero gaps, whose tiles, units and
+    // addresses are the packed walk's (every row offset q * gap is 0, and a
+    // unit across a row break is contiguous), so the results are the same
+    // bits, for any width.
+    const bool aligned = ((uintptr_t)m.src & 3u) == 0;
     if (H == 1 || (gs == 0 && gd == 0 && g2 == 0))
-        return dc::kWalkPacked;
+        return aligned ? dc::kWalkPacked : dc::kWalkRows;
     if (W >= 4 && W <= dc::kRowWalkMaxWidth && gs < dc::kRowWalkMaxGap &&
         gd < dc::kRowWalkMaxGap && g2 < dc::kRowWalkMaxGap)
         return dc::kWalkRows;
@@ -356,9 +366,12 @@ dc::DevImage describe(const dc_image &m, int index, int64_t tile_px, const dc_pa
         if (!packed) {
             d.magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)W +
                                  (((uint64_t)1 << 32) % (uint64_t)W != 0));
-            d.gap_src = (uint32_t)gs;
-            d.gap_dst = (uint32_t)gd;
-            d.gap_dst2 = (uint32_t)g2;
+            // One row, or rows without padding: every row offset is 0 (the
+            // pitch of a single row is never used).
+            const bool nogap = H == 1 || (gs == 0 && gd == 0 && g2 == 0);
+            d.gap_src = nogap ? 0u : (uint32_t)gs;
+            d.gap_dst = nogap ? 0u : (uint32_t)gd;
+            d.gap_dst2 = nogap ? 0u : (uint32_t)g2;
         }
     } else {
         d.walk = dc::kWalkScalar;

@@ -197,3 +197,27 @@ def test_wide_rows_take_the_per_pixel_walk(dev):
     outs, _, _ = P.tonemap_global([xv], **TM)
     check_f32(outs[0].cpu().numpy(), t_ref, "wide pitched tone map vs oracle")
     report("46005-px rows: per-pixel walk matches")
+
+
+@pytest.mark.parametrize("kind", ["u8", "f16", "f32"])
+def test_packed_rows_at_any_element_offset(dev, kind):
+    """Packed rows (pitch = row bytes) whose first byte is not 4-byte aligned
+    take the row walk with zero gaps, whose tiles, units and addresses are the
+    packed walk's: decolorization, T and the statistics are the aligned copy's
+    bits, for every width (below 4 and single rows included)."""
+    shapes = [(1, 9), (2, 3), (5, 4), (7, 1001), (3, 4097), (40, 257)]
+    for i, (h, w) in enumerate(shapes):
+        img = _pixels(kind, h, w, 500 + i)
+        xp = to_dev(img, dev)
+        for off in (1, 2, 3):
+            xv = _pitched_input(img, 0, off, dev)
+            what = "%s %dx%d at element offset %d" % (kind, w, h, off)
+            _same(P.decolorize(xv), P.decolorize(xp), what)
+            _same(P.decolorize(xv, out_dtype=torch.uint8), P.decolorize(xp, out_dtype=torch.uint8),
+                  what + " u8")
+            tv, _, sv = P.tonemap_global([xv], **TM)
+            tp, _, sp = P.tonemap_global([xp], **TM)
+            torch.cuda.synchronize()
+            _same(tv[0], tp[0], what + " T")
+            _same(sv, sp, what + " statistics")
+    report("packed rows at element offsets 1-3 match the aligned copies")
