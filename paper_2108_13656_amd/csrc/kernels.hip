@@ -517,6 +517,10 @@ __device__ __forceinline__ void load_units(const TileRef &t, unsigned (&w)[U][3]
             w[u][1] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4u, so, aux);
             w[u][2] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off + 8u, so, aux);
         }
+        // Keeps every load above the callers' stores: the compiler may not
+        // prove that a store misses the input, and a load sunk below one
+        // would wait for it, and for the loads before it, one unit at a time.
+        asm volatile("" ::: "memory");
         return;
     }
 #pragma unroll
