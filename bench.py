@@ -562,20 +562,22 @@ def main():
             def step():
                 plan.run(stream)
 
-            ms = time_steps(step, args.steps, args.warmup, stream)
-            # The same step kept running (five more blocks of K steps, not part
-            # of the timed result): the MI355X's power management slows the
-            # first few dozen steps after the GPU has idled, so the timed block
-            # above can sit a few per cent above the steady state.
-            steady = [time_steps(step, args.steps, 0, stream) for _ in range(5)]
-            # Per-kernel durations from the batch schedule (three kernels on one
-            # stream, events between them), the same kernels the step runs.
+            # The untimed measurements of this leg come first: per-kernel
+            # durations from the batch schedule (three kernels on one stream,
+            # events between them; the same kernels the step runs) and the
+            # per-call API path. The MI355X's power management slows the first
+            # few dozen steps after the GPU has idled, so they also keep the
+            # GPU busy until the W warm-up steps and the K timed steps.
             P.set_tuning(dict(tuning, tonemap_pipeline=0), dev)
             plan_ev = P.Plan(P.PLAN_TONEMAP, xs, outs, stats=stats, graph=False)
             ktimes = kernel_times(lambda: plan_ev.run(stream), max(5, args.steps // 2), P, dev)
             P.set_tuning(tuning, dev)
             dyn_ms = time_steps(lambda: P.tonemap_global(xs, outs=outs, stats=stats, stream=stream),
                                 max(3, args.steps // 2), 1, stream)
+            ms = time_steps(step, args.steps, args.warmup, stream)
+            # The same step kept running (five more blocks of K steps, not part
+            # of the timed result): the steady state beside the timed block.
+            steady = [time_steps(step, args.steps, 0, stream) for _ in range(5)]
         log("tonemap step %.3f ms (steady %.3f); kernels (pass1, combine, pass2) %s ms" %
             (ms, float(np.median(steady)), ", ".join("%.3f" % t for t in ktimes)))
         gpx = hdr_px / (ms * 1e-3) / 1e9
@@ -721,11 +723,11 @@ def main():
         for sat in (1.0, 0.6):
             with torch.cuda.stream(stream):
                 cplan = P.Plan(P.PLAN_TONEMAP, xs, couts, graph=True, saturation=sat)
-                cms = time_steps(lambda: cplan.run(stream), args.steps, args.warmup, stream)
                 P.set_tuning(dict(tuning, tonemap_pipeline=0), dev)
                 cev = P.Plan(P.PLAN_TONEMAP, xs, couts, graph=False, saturation=sat)
                 ck = kernel_times(lambda: cev.run(stream), max(5, args.steps // 2), P, dev)
                 P.set_tuning(tuning, dev)
+                cms = time_steps(lambda: cplan.run(stream), args.steps, args.warmup, stream)
                 cplan.close()
                 cev.close()
             key = "tonemap_colour_s1" if sat == 1.0 else "tonemap_colour_pow"
@@ -765,9 +767,9 @@ def main():
         louts = [torch.empty((size, size), dtype=torch.float32, device=dev) for _ in xs]
         with torch.cuda.stream(stream):
             lplan = P.Plan(P.PLAN_LOCAL, xs, louts, graph=True)
-            lms = time_steps(lambda: lplan.run(stream), args.steps, args.warmup, stream)
             lev = P.Plan(P.PLAN_LOCAL, xs, louts, graph=False)
             lk = kernel_times(lambda: lev.run(stream), max(5, args.steps // 2), P, dev)
+            lms = time_steps(lambda: lplan.run(stream), args.steps, args.warmup, stream)
             lplan.close()
             lev.close()
         b1, b2 = hdr_px * (6 + 4), hdr_px * (4 + 4)
@@ -823,8 +825,8 @@ def main():
                 for sp in singles:
                     sp.run(stream)
 
-            vms = time_steps(lambda: vplan.run(stream), args.steps, args.warmup, stream)
             vk = kernel_times(lambda: vplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
+            vms = time_steps(lambda: vplan.run(stream), args.steps, args.warmup, stream)
             vms_single = None if args.no_per_image else \
                 time_steps(vstep_single, max(3, args.steps // 2), 1, stream)
             vplan.close()
@@ -932,17 +934,15 @@ def main():
                 for sp in singles:
                     sp.run(stream)
 
+            uk = kernel_times(lambda: uplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
             ums = time_steps(lambda: uplan.run(stream), args.steps, args.warmup, stream)
             # Graph replay against the same launch made directly, in alternating
-            # blocks after the first (which carries the power-management
-            # slowdown that follows an idle GPU): the step's time outside the
-            # kernel.
+            # blocks: the step's time outside the kernel.
             ug, ud = [], []
             for _ in range(3):
                 ud.append(time_steps(lambda: uplan_ev.run(stream), args.steps, 0, stream))
                 ug.append(time_steps(lambda: uplan.run(stream), args.steps, 0, stream))
             ums_direct = float(np.median(ud))
-            uk = kernel_times(lambda: uplan_ev.run(stream), max(5, args.steps // 2), P, dev)[0]
             ums_single = None if args.no_per_image else \
                 time_steps(ustep_single, max(3, args.steps // 2), 1, stream)
             for pl in [uplan, uplan_ev] + singles:
