@@ -84,8 +84,8 @@ def test_sweep_pair_chunks(dev, npairs, kind):
 
 
 def test_sweep_row_walk(dev):
-    """A sweep into padded output rows, 16-byte aligned (the row walk: input rows
-    of 624 bytes, output rows of 848) and not (the per-pixel walk)."""
+    """A sweep into padded output rows (input rows of 624 bytes), 16-byte
+    aligned (output rows of 848 bytes) and not (844 bytes)."""
     img = synth.sdr_pixels(np.random.default_rng(47), 70, 208)
     x = to_dev(img, dev)
     for pad in (4, 3):

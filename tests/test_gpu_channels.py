@@ -49,7 +49,7 @@ def test_mixed_batch_and_views(dev, kind):
             synth.random_image(63, 5, 4099, np.float32), synth.sdr_pixels(rng, 1, 1)]
     xs = [to_dev(a, dev) for a in imgs]
     big = synth.sdr_pixels(rng, 40, 96)
-    xs.append(to_dev(big, dev)[:, 1:71])  # unaligned view: per-pixel walk
+    xs.append(to_dev(big, dev)[:, 1:71])  # a view starting at an odd pixel
     imgs.append(big[:, 1:71])
     outs = P.channel_batch(xs, kind)
     for a, o in zip(imgs, outs):

@@ -93,17 +93,16 @@ def test_unit_saturation_output_luminance_is_t(dev):
 
 @pytest.mark.parametrize("kind", ["u8", "f16"])
 def test_pitched_views(dev, kind):
-    """Input and colour-output row pitches: 16-byte multiples (row walk) and odd
-    ones (per-pixel walk) match the oracle and leave the row padding alone. (The
-    walks split an image into different statistics chunks, so their results
-    agree within the tolerance, not bit for bit.)"""
+    """Input and colour-output row pitches, 16-byte multiples and odd ones, and
+    an input starting at an odd pixel: all match the oracle and leave the row
+    padding alone."""
     img = _image(kind, 40, 150, 8)
     x = to_dev(img, dev)
     ref = oracle.tonemap_colour(img, saturation=0.7, **TM)[0]
     big = torch.zeros((40, 176, 3), dtype=x.dtype, device=dev)  # rows of 528 or 1056 bytes
     # (first input column, output row padding): column 16 starts 16-byte aligned
-    # and output rows of (150 + 2) * 12 bytes are a 16-byte multiple, so the first
-    # case takes the row walk and the others the per-pixel walk.
+    # and output rows of (150 + 2) * 12 bytes are a 16-byte multiple; the other
+    # cases pad the output rows oddly or start the input at an odd pixel.
     for c0, pad in ((16, 2), (16, 5), (3, 2)):
         big.zero_()
         big[:, c0:c0 + 150] = x

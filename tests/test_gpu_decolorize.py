@@ -132,10 +132,11 @@ def _check_any(out, img, dtype, what):
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("src", [np.uint8, np.float16, np.float32])
-@pytest.mark.parametrize("walk", ["packed", "rows", "scalar"])
+@pytest.mark.parametrize("walk", ["packed", "rows", "odd"])
 def test_shapes_and_walks(dev, shape, src, walk):
     """Ragged sizes through each of the three walks: packed (one segment),
-    16-byte aligned pitched rows, and the per-pixel walk for unaligned views."""
+    pitched rows starting 16-byte aligned, and pitched rows starting at an odd
+    element (both on the row walk; widths below 4 on the per-pixel walk)."""
     h, w = shape
     seed = hash((h, w, np.dtype(src).name, walk)) & 0xFFFF
     if walk == "packed":

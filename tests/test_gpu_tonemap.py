@@ -113,7 +113,7 @@ def test_result_independent_of_batch(dev):
 
 def test_pitched_and_unaligned_views(dev):
     big = synth.random_image(11, 50, 96, np.uint8)
-    for x0, name in ((16, "rows"), (1, "scalar")):
+    for x0, name in ((16, "aligned rows"), (1, "odd-offset rows")):
         view = big[:, x0:x0 + 70]
         t_ref, _, st_ref = oracle.tonemap(view, **TM)
         outs, _, stats = P.tonemap_global([to_dev(big, dev)[:, x0:x0 + 70]], **TM)
