@@ -1365,22 +1365,38 @@ __global__ __launch_bounds__(kBlock) void k_tm_pass2(const DevImage *__restrict_
 // U8: the values are wanted as 8-bit codes, so they come out times 255 (folded
 // into k, or into the exponent as log2 255) and the saturating 8-bit
 // conversion does the clamp at 255; other outputs are clamped at 1 here.
-template <int SRC, int MODE, bool U8>
-__device__ __forceinline__ void colour_px(float R, float G, float B, float l, float E, float s,
-                                          float *o)
+// Whether a pixel has no colour to carry (the grey case of colour_px), from
+// the raw channels and its L.
+template <int SRC>
+__device__ __forceinline__ bool colour_grey(float R, float G, float B, float l)
 {
-    constexpr float kOut = U8 ? 255.0f : 1.0f;
     if constexpr (SRC != 0) {
         R = chan_clamp(R, 0.0f, chan_max<SRC>());
         G = chan_clamp(G, 0.0f, chan_max<SRC>());
         B = chan_clamp(B, 0.0f, chan_max<SRC>());
     }
+    const float S = (R + G) + B;
+    return !(l > fmaf(S, 1e-6f, SRC == 0 ? 1e-6f : 0.0f));
+}
+
+// ANYGREY = false: the caller has found that no pixel of this unit, in any
+// lane of the wave, is grey, so the selects between the grey and the coloured
+// form are left out; the coloured form's values are the same bits either way.
+template <int SRC, int MODE, bool U8, bool ANYGREY = true>
+__device__ __forceinline__ void colour_px(float R, float G, float B, float l, float E, float s,
+                                          float *o)
+{
+    constexpr float kOut = U8 ? 255.0f : 1.0f;
     if constexpr (MODE == kColourGrey) {
         o[0] = o[1] = o[2] = hw_rcp(1.0f + E) * kOut;
         return;
     }
-    const float S = (R + G) + B;
-    const bool grey = !(l > fmaf(S, 1e-6f, SRC == 0 ? 1e-6f : 0.0f));
+    const bool grey = ANYGREY && colour_grey<SRC>(R, G, B, l);
+    if constexpr (SRC != 0) {
+        R = chan_clamp(R, 0.0f, chan_max<SRC>());
+        G = chan_clamp(G, 0.0f, chan_max<SRC>());
+        B = chan_clamp(B, 0.0f, chan_max<SRC>());
+    }
     const float C[3] = {R, G, B};
     if constexpr (MODE == kColourRatio) {
         const float lc = fmaxf(l, 1e-30f);
@@ -1506,14 +1522,32 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             patch_unit<SRC, ROWS>(t, slot_lp<PPU>(true, u, 0), up[u], w[u]);
-            float o[3 * PPU];
+            float o[3 * PPU], l[PPU], E[PPU];
+            bool grey = false;
 #pragma unroll
             for (int j = 0; j < PPU; ++j) {
                 const float R = chan<SRC>(w[u], 3 * j), G = chan<SRC>(w[u], 3 * j + 1),
                             B = chan<SRC>(w[u], 3 * j + 2);
-                const float l = lum<SRC>(R, G, B, im.k);
-                const float E = hw_exp2(cv.a * (xlog2(l, im.unit, tm.eps) - cv.mu2));
-                colour_px<SRC, MODE, U8>(R, G, B, l, E, tm.saturation, &o[3 * j]);
+                l[j] = lum<SRC>(R, G, B, im.k);
+                E[j] = hw_exp2(cv.a * (xlog2(l[j], im.unit, tm.eps) - cv.mu2));
+                grey = grey || colour_grey<SRC>(R, G, B, l[j]);
+            }
+            // A grey pixel (black, mostly) anywhere in the wave's unit takes the
+            // form with the grey selects; other units skip them.
+            if (MODE == kColourGrey || __builtin_amdgcn_ballot_w64(grey) == 0) {
+#pragma unroll
+                for (int j = 0; j < PPU; ++j)
+                    colour_px<SRC, MODE, U8, false>(chan<SRC>(w[u], 3 * j),
+                                                    chan<SRC>(w[u], 3 * j + 1),
+                                                    chan<SRC>(w[u], 3 * j + 2), l[j], E[j],
+                                                    tm.saturation, &o[3 * j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < PPU; ++j)
+                    colour_px<SRC, MODE, U8, true>(chan<SRC>(w[u], 3 * j),
+                                                   chan<SRC>(w[u], 3 * j + 1),
+                                                   chan<SRC>(w[u], 3 * j + 2), l[j], E[j],
+                                                   tm.saturation, &o[3 * j]);
             }
             const uint32_t lp = slot_lp<PPU>(true, u, 0);
             if (!up[u].split) {
