@@ -1501,6 +1501,72 @@ __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_
     }
 }
 
+// Colour curve pass with 8-bit RGB output over a full packed tile of binary16
+// input, each lane taking two adjacent units (4 pixels): their 12 bytes of
+// RGB codes go out in one dwordx3, so every store instruction of a wave
+// writes 768 contiguous bytes and no line leaves L2 partly written (a lane's
+// single unit has 6 bytes of output, which took a dword and a short store
+// whose lines the two instructions each covered only in part). Loads: the
+// pair's 24 bytes as buffer loads from the tile's first byte (the packed
+// walk's 4-byte aligned base). Per pixel, the same expressions as the unit
+// form, so the same bits.
+template <int SRC, int MODE>
+__device__ __forceinline__ void tm_colour_pairs(const DevImage &im, const TileRef &t, TmArgs tm,
+                                                Curve cv)
+{
+    constexpr int NP = kStatsPxPerThread / 4; // pairs of units per lane
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)t.src, (short)0, -1, kBufferWord3);
+    uint32_t off = threadIdx.x * 24u;
+    asm("" : "+v"(off)); // an opaque sum, so the constant offsets fold into the loads
+    unsigned w[NP][2][3];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) {
+        const int so = v * (kBlock * 24);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                w[v][h][c] = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(
+                    r, off + 12u * h + 4u * c, so, kBufferNontemporal);
+    }
+    asm volatile("" ::: "memory"); // loads stay above the stores that follow
+#pragma unroll
+    for (int v = 0; v < NP; ++v) {
+        float o[12], l[4], E[4];
+        bool grey = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned(&u)[3] = w[v][j >> 1];
+            const int b = 3 * (j & 1);
+            const float R = chan<SRC>(u, b), G = chan<SRC>(u, b + 1), B = chan<SRC>(u, b + 2);
+            l[j] = lum<SRC>(R, G, B, im.k);
+            E[j] = hw_exp2(cv.a * (xlog2(l[j], im.unit, tm.eps) - cv.mu2));
+            grey = grey || colour_grey<SRC>(R, G, B, l[j]);
+        }
+        if (MODE == kColourGrey || __builtin_amdgcn_ballot_w64(grey) == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const unsigned(&u)[3] = w[v][j >> 1];
+                const int b = 3 * (j & 1);
+                colour_px<SRC, MODE, true, false>(chan<SRC>(u, b), chan<SRC>(u, b + 1),
+                                                  chan<SRC>(u, b + 2), l[j], E[j],
+                                                  tm.saturation, &o[3 * j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const unsigned(&u)[3] = w[v][j >> 1];
+                const int b = 3 * (j & 1);
+                colour_px<SRC, MODE, true, true>(chan<SRC>(u, b), chan<SRC>(u, b + 1),
+                                                 chan<SRC>(u, b + 2), l[j], E[j], tm.saturation,
+                                                 &o[3 * j]);
+            }
+        }
+        store_rgb_unit<4>(t.dst, 0, (uint32_t)(v * kBlock + threadIdx.x) * 4u, o);
+    }
+}
+
 // Curve pass with colour output over one statistics tile: the same units,
 // tiles and curve as tm_pass2_tile, and 3 output channels per pixel. U8 =
 // the image's dst is 8-bit (a uniform choice per image).
@@ -1515,6 +1581,12 @@ __device__ __forceinline__ void tm_colour_tile(const DevImage &im, int64_t tile,
     const Enc e{1.0f, 1.0f};
     const int dt = U8 ? 0 : im.dst_dtype;
     const bool vec = im.walk != kWalkScalar;
+    if constexpr (U8 && PPU == 2 && !ROWS) {
+        if (vec && t.rem >= kStatsChunkPx) {
+            tm_colour_pairs<SRC, MODE>(im, t, tm, cv);
+            return;
+        }
+    }
     if (vec && t.rem >= kStatsChunkPx) {
         unsigned w[U][3];
         UnitPos up[U];
