@@ -42,8 +42,12 @@
  * their own row pitch. Host arrays passed to a call (dc_image lists, params)
  * are read before the call returns and may be freed at once. The context owns
  * its workspace (descriptor tables, statistics partials) and frees it in
- * dc_destroy. 16-byte aligned bases and pitches take the vectorised path;
- * anything else is still correct but slower.
+ * dc_destroy. Every pixel is read and written with 12-byte vector units
+ * (4 8-bit, 2 binary16 or 1 binary32 pixels) whatever the alignment of its
+ * element: rows whose pitch exceeds their bytes (crops, padding) are tiled
+ * like their packed copy, for widths of 4 to 46000 pixels and row padding
+ * below 256 KiB; images past those limits are walked pixel by pixel, still
+ * correct but slower.
  *
  * Streams. `stream` is a hipStream_t passed as void* (NULL = the null stream).
  * All compute calls are asynchronous with respect to the host.
@@ -176,8 +180,8 @@ int dc_decolorize_batch(dc_ctx *ctx, const dc_image *imgs, int32_t n, const dc_p
  * weight-sweep explorer of Fig. 4, which plots how beta_R and beta_k bias L
  * along colour ramps: a sweep of one image over many (beta_R, beta_k) pairs is
  * n descriptors sharing one src with n outputs, all in one launch. When every
- * descriptor has the same src, size, src_pitch, dst_dtype and dst_pitch, no
- * dst2, and outputs with the same 16-byte alignment, the launch reads each
+ * descriptor has the same src, size, src_pitch, dst_dtype and dst_pitch and
+ * no dst2, the launch reads each
  * input tile once for all the pairs (the weight-independent terms of Eqs.
  * (1)-(6) are evaluated once per pixel); otherwise it is the tile table of
  * dc_decolorize_batch. Every weight must be finite and in [0, 1]. Results are

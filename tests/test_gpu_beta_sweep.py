@@ -27,12 +27,11 @@ def test_colour_ramps_sweep(dev):
             check_f32(got[i], oracle.decolorize(img, br, bk), "%s beta (%g, %g)" % (name, br, bk))
 
 
-# (input, height, width, output type). Planes of an (n, H, W) output start
-# 16-byte aligned when H * W * (output bytes) is a multiple of 16; then every
-# image of the call has the same walk and the call runs as one pass over the
-# input (the shared-input sweep kernel); 123 x 517 with FP32 output leaves the
-# planes unaligned and takes the per-image table instead. Both must equal
-# single calls bit for bit.
+# (input, height, width, output type). The planes of an (n, H, W) output start
+# wherever H * W * (output bytes) puts them (123 x 517 FP32 planes, for one,
+# are not 16-byte aligned); every image of the call has the same walk either
+# way, so the call runs as one pass over the input (the shared-input sweep
+# kernel), and must equal single calls bit for bit.
 SWEEP_CASES = [("u8", 123, 517, torch.float32), ("u8", 128, 517, torch.float32),
                ("u8", 64, 250, torch.uint8), ("u8", 96, 130, torch.float16),
                ("f16", 64, 1000, torch.float32), ("f16", 64, 1000, torch.float16),
