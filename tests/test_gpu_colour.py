@@ -163,3 +163,38 @@ def test_flag_rejected_outside_tone_map(dev):
     with pytest.raises(P.DecolorError) as e:
         P.decolorize(x, out=torch.empty((8, 8, 3), device=dev))
     assert e.value.status == P.DC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("s", [1.0, 0.6, 0.0])
+@pytest.mark.parametrize("kind", ["u8", "f16", "f32"])
+def test_grey_pixels_in_some_waves(dev, kind, s):
+    """Black and achromatic pixels in a few waves of an image of full tiles:
+    their units take the form with the grey selects, the rest skip it, and the
+    8-bit output (binary16 input: two units per lane, one 12-byte store) and
+    the FP32 output match the oracle; the packed image and a pitched copy of
+    it (one unit per lane, the row walk) give the same bytes."""
+    h, w = 64, 512  # 8 tiles of 4096 pixels
+    img = _image(kind, h, w, 77).copy()
+    img[3, 40:60] = 0                              # black run (one wave)
+    img[20, 100:103] = img[20, 100:103, :1]        # achromatic pixels
+    img[41, 7] = 0                                 # a single black pixel
+    img[63, 500:] = img[63, 500:, 1:2]             # grey at the image's end
+    x = to_dev(img, dev)
+    rgb_ref, _, _, _ = oracle.tonemap_colour(img, saturation=s, **TM)
+    name = "grey waves %s s=%g" % (kind, s)
+    o8 = P.tonemap_global([x], torch.uint8, colour=True, saturation=s, **TM)[0][0]
+    check_u8(o8.cpu().numpy(), rgb_ref, name + " u8", max_fraction=U8_COLOUR_FRACTION)
+    of = P.tonemap_global([x], torch.float32, colour=True, saturation=s, **TM)[0][0]
+    check_f32(of.cpu().numpy(), rgb_ref, name + " f32")
+    grey = np.all(img[..., :1] == img, axis=-1)
+    t_ref = oracle.tonemap(img, **TM)[0]
+    assert np.allclose(of.cpu().numpy()[grey], t_ref[grey][:, None], atol=1e-5), name
+    # a pitched copy: the row walk, one unit per lane
+    big = torch.zeros((h, w + 8, 3), dtype=x.dtype, device=dev)
+    big[:, :w] = x
+    ob = torch.full((h, w + 4, 3), 7, dtype=torch.uint8, device=dev)
+    P.tonemap_global([big[:, :w]], outs=[ob[:, :w]], colour=True, saturation=s, **TM)
+    torch.cuda.synchronize()
+    assert torch.equal(ob[:, :w], o8), name + ": row walk differs from the packed walk"
+    assert bool((ob[:, w:] == 7).all()), name + ": padding written"
+    report("%s: %d grey pixels" % (name, int(grey.sum())))
