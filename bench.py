@@ -745,6 +745,15 @@ def main():
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(cach / HBM_PEAK_GBS, 4), "traffic": traffic.get(key),
                              "algorithmic_bytes": hdr_px * 9}}
+            # The curve pass with colour output issues VALU work for most of its
+            # time (SQ counters in profiles/): its HBM rate is set by that.
+            cslots = profiled_counters("valu_slots_per_px").get(key)
+            if cslots:
+                vi = valu_issue_ms(cslots, hdr_px)
+                legs["s=%g" % sat]["roofline"].update({
+                    "valu_slots_per_px": cslots, "valu_issue_ms": round(vi, 4),
+                    "valu_issue_frac_of_kernel": round(vi / ck[2], 4),
+                    "limiter": "VALU issue (%.0f %% of the curve pass's time)" % (100 * vi / ck[2])})
             log("colour tone map s=%g: step %.3f ms (%.1f Gpx/s); kernels %s ms; curve pass %.0f GB/s"
                 % (sat, cms, legs["s=%g" % sat]["value"], ", ".join("%.3f" % t for t in ck), cach))
         colour = {"workload": "hdr_tonemap_colour", "images": n_img, "height": size, "width": size,
