@@ -2125,23 +2125,23 @@ __device__ __forceinline__ void ltm_pass2_staged_tile(const DevImage &im, int64_
 // Colour output of one pixel from a tone-mapped T (the local map's blend):
 // every channel T (C / L)^s clamped to at most 1, grey T where there is no
 // colour to carry, in the same three modes and 8-bit scaling as colour_px
-// (which takes the global curve's exponential instead of T).
-template <int SRC, int MODE, bool U8>
+// (which takes the global curve's exponential instead of T); ANYGREY as
+// there.
+template <int SRC, int MODE, bool U8, bool ANYGREY = true>
 __device__ __forceinline__ void colour_of_t(float R, float G, float B, float l, float T, float s,
                                             float *o)
 {
     constexpr float kOut = U8 ? 255.0f : 1.0f;
+    if constexpr (MODE == kColourGrey) {
+        o[0] = o[1] = o[2] = T * kOut;
+        return;
+    }
+    const bool grey = ANYGREY && colour_grey<SRC>(R, G, B, l);
     if constexpr (SRC != 0) {
         R = chan_clamp(R, 0.0f, chan_max<SRC>());
         G = chan_clamp(G, 0.0f, chan_max<SRC>());
         B = chan_clamp(B, 0.0f, chan_max<SRC>());
     }
-    if constexpr (MODE == kColourGrey) {
-        o[0] = o[1] = o[2] = T * kOut;
-        return;
-    }
-    const float S = (R + G) + B;
-    const bool grey = !(l > fmaf(S, 1e-6f, SRC == 0 ? 1e-6f : 0.0f));
     const float C[3] = {R, G, B};
     const float il = grey ? 0.0f : hw_rcp(fmaxf(l, 1e-30f));
     if constexpr (MODE == kColourRatio) {
@@ -2204,15 +2204,30 @@ __device__ __forceinline__ void ltm_colour_tile(const DevImage &im, int64_t tile
                 int cy0;
                 float wy;
                 ltm_axis(row, r.ty, r.ny, cy0, wy);
-                float o[3 * PPU];
+                float o[3 * PPU], l[PPU], T[PPU];
+                bool grey = false;
 #pragma unroll
                 for (int j = 0; j < PPU; ++j) {
                     const float R = chan<SRC>(w[i], 3 * j), G = chan<SRC>(w[i], 3 * j + 1),
                                 B = chan<SRC>(w[i], 3 * j + 2);
-                    const float l = lum<SRC>(R, G, B, im.k);
-                    const float T = ltm_value(xlog2(l, im.unit, tm.eps), u0, tm, cv, lds, cx0[j],
-                                              wx[j], cy0, wy);
-                    colour_of_t<SRC, MODE, U8>(R, G, B, l, T, tm.saturation, &o[3 * j]);
+                    l[j] = lum<SRC>(R, G, B, im.k);
+                    T[j] = ltm_value(xlog2(l[j], im.unit, tm.eps), u0, tm, cv, lds, cx0[j], wx[j],
+                                     cy0, wy);
+                    grey = grey || colour_grey<SRC>(R, G, B, l[j]);
+                }
+                // as in the global map: units of grey-free waves skip the selects
+                if (MODE == kColourGrey || __builtin_amdgcn_ballot_w64(grey) == 0) {
+#pragma unroll
+                    for (int j = 0; j < PPU; ++j)
+                        colour_of_t<SRC, MODE, U8, false>(
+                            chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
+                            chan<SRC>(w[i], 3 * j + 2), l[j], T[j], tm.saturation, &o[3 * j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < PPU; ++j)
+                        colour_of_t<SRC, MODE, U8, true>(
+                            chan<SRC>(w[i], 3 * j), chan<SRC>(w[i], 3 * j + 1),
+                            chan<SRC>(w[i], 3 * j + 2), l[j], T[j], tm.saturation, &o[3 * j]);
                 }
                 store_rgb_unit<PPU>(dst + row * r.dp, dt, col, o);
             }
