@@ -33,9 +33,11 @@ __host__ __device__ constexpr int elem_size(int dtype)
 
 // How an image is walked.
 enum Walk : int32_t {
-    kWalkPacked = 0, // one segment of W*H pixels, vector units
-    kWalkRows = 1,   // pitched rows: tiled as one segment of W*H pixels in row-major
-                     // order, vector units placed across the row breaks (magic, gaps)
+    kWalkPacked = 0, // one segment of W*H pixels from a 4-byte aligned start, vector
+                     // units loaded with buffer loads
+    kWalkRows = 1,   // pitched rows, or packed rows from an unaligned start (all gaps
+                     // 0): tiled as one segment of W*H pixels in row-major order,
+                     // vector units placed across the row breaks (magic, gaps)
     kWalkScalar = 2, // H segments of W pixels, one pixel at a time
 };
 

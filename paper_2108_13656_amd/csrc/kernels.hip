@@ -209,7 +209,8 @@ __device__ __forceinline__ float chan(const unsigned (&w)[3], int e)
     }
 }
 
-// One unit: three dwords from a 4-byte aligned address (a single dwordx3).
+// One unit: three dwords from any element-aligned address (a single dwordx3;
+// the target serves unaligned dword accesses).
 // The loads are nontemporal (NT): a pass reads each input byte once, and an
 // input that a later pass reads again (the tone map's curve pass) is, at the
 // batch sizes that matter, far larger than the caches. Streaming loads leave
@@ -1422,10 +1423,9 @@ __device__ __forceinline__ void colour_px(float R, float G, float B, float l, fl
 }
 
 // Stores the 3 * PPU channel values of one unit (PPU pixels) at pixel lp of
-// an interleaved RGB row whose pixel 0 is at base (16-byte aligned on the
-// vector walks, so every unit is aligned to its own size's largest power of
-// two up to 16). 8-bit values arrive times 255 and are converted by the
-// saturating v_cvt_pk_u8_f32.
+// an interleaved RGB row whose pixel 0 is at base (any element alignment; the
+// target serves unaligned dword accesses). 8-bit values arrive times 255 and
+// are converted by the saturating v_cvt_pk_u8_f32.
 template <int PPU>
 __device__ __forceinline__ void store_rgb_unit(uint8_t *base, int dtype, uint32_t lp,
                                                const float (&o)[3 * PPU])
